@@ -1,0 +1,201 @@
+/*
+ * mg.h -- C ABI of the MI355X (gfx950) masked multigrid Poisson solver.
+ *
+ * Method: Guillet & Teyssier, "A Simple Multigrid Scheme for Solving the
+ * Poisson Equation with Arbitrary Domain Boundaries" (arXiv:1104.1703).
+ * The solver computes Phi with  Delta Phi = rho  on the cells where the
+ * caller's mask is +1 (Eq. "poisson"), with Dirichlet values on the faces
+ * between active and inactive cells (Sec. 2, Fig. "grid").
+ *
+ * Conventions for every entry point:
+ *   - Fields are C-contiguous (nz, ny, nx) boxes, x fastest; linear index
+ *     (k*ny + j)*nx + i.  Coarse level l has dims (n >> l) per axis and
+ *     spacing h * 2^l.
+ *   - Pointers named *_dev are DEVICE pointers on the current HIP device;
+ *     the caller owns them and keeps them alive for the call.  Pointers
+ *     named *_host or *out are host pointers.
+ *   - `stream` is a hipStream_t passed as void*.  All device work of a
+ *     hierarchy is enqueued on the stream given at creation; 0 makes the
+ *     library create its own blocking stream (the legacy null stream cannot
+ *     be captured into a graph).  Calls that return host values synchronise
+ *     that stream.
+ *   - Errors are reported as mg_status; nothing throws or aborts.  The text
+ *     of the last error of the calling thread is mg_last_error().
+ *   - A hierarchy is not re-entrant: one call at a time per hierarchy.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_NOT_CONVERGED = 1,   /* max_cycles reached; phi holds the last iterate */
+    MG_ERR_ARG = -1,        /* invalid argument (see each entry point) */
+    MG_ERR_NO_ACTIVE = -2,  /* the mask has no active cell */
+    MG_ERR_HIP = -3,        /* a HIP runtime call failed; see mg_last_error() */
+    MG_ERR_DIVERGED = -4,   /* residual norm became non-finite */
+    MG_ERR_ALLOC = -5       /* device allocation failed */
+} mg_status;
+
+typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
+
+/* Coarse-level boundary reconstruction (Sec. 3 second order, Sec. 4 first
+ * order); AUTO starts in second order and switches at run time (Sec. 4). */
+typedef enum { MG_BC_AUTO = 0, MG_BC_FIRST = 1, MG_BC_SECOND = 2 } mg_bc_order;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  When
+ * alloc is NULL the library uses hipMalloc/hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} mg_allocator;
+
+typedef struct {
+    int32_t n_pre;            /* smoothing passes before restriction (Sec. 2: 2) */
+    int32_t n_post;           /* smoothing passes after prolongation (Sec. 2: 2) */
+    int32_t n_cycles;         /* coarse iterations per level: 1 = V, 2 = W (Sec. 5.3) */
+    int32_t n_coarse_sweeps;  /* passes on the deepest level (default 32) */
+    int32_t min_coarse_dim;   /* stop coarsening below this edge (default 4) */
+    int32_t max_cycles;       /* solve-loop cap (default 200) */
+    int32_t precision;        /* mg_precision (default MG_FP64) */
+    int32_t bc_order;         /* mg_bc_order (default MG_BC_AUTO) */
+    double eta;               /* switch threshold on ||r_n+1||/||r_n|| (Sec. 4: 0.5) */
+    int32_t first_order_hold; /* solves kept in first order after a switch (Sec. 4: 10) */
+    int32_t use_graph;        /* 1 = replay each cycle as a captured hipGraph (default 1) */
+    mg_allocator allocator;
+} mg_options;
+
+typedef struct {
+    int32_t cycles;            /* iterations performed */
+    int32_t order_used;        /* 1 or 2: boundary order at the end of the solve */
+    int32_t switched_at_cycle; /* cycle after which AUTO switched, -1 if none */
+    int32_t status;            /* same value as returned */
+    double r_ref;              /* ||r(phi = 0)||_2 = ||f||_2 over active cells */
+    double r0;                 /* residual norm of the initial guess */
+    double r_final;            /* residual norm at return */
+    double ms;                 /* wall time of the call on the stream (HIP events) */
+    double history[257];       /* history[n] = ||r|| after cycle n, n <= 256 */
+} mg_solve_info;
+
+typedef struct mg_hierarchy mg_hierarchy; /* opaque */
+
+/* Fill *o with the defaults listed above. */
+void mg_default_options(mg_options *o);
+
+/*
+ * Build the multigrid hierarchy for a mask (Sec. 2 Fig. "hierarchy"; Sec. 3
+ * mask colouring and recursive R1 averaging; Sec. 4 first-order sets).
+ *   mask_dev : int8 device array (nz, ny, nx), +1 active, -1 inactive.  Only
+ *              read during the call; the caller may free it afterwards.
+ *   h        : cell width (> 0).  opt: NULL = defaults.  out: receives the
+ *              handle, to be released with mg_destroy_hierarchy.
+ * Errors: MG_ERR_ARG for NULL pointers, non-positive dims or h, mask values
+ * other than +-1, or a non-inactive outermost cell layer; MG_ERR_NO_ACTIVE
+ * when no cell is +1; MG_ERR_ALLOC / MG_ERR_HIP.
+ */
+mg_status mg_create_hierarchy(const int8_t *mask_dev, int32_t nx, int32_t ny, int32_t nz, double h,
+                              const mg_options *opt, void *stream, mg_hierarchy **out);
+
+/* Release all device memory of the hierarchy (NULL is a no-op). */
+void mg_destroy_hierarchy(mg_hierarchy *H);
+
+/*
+ * Solve Delta phi = rho with Dirichlet values (Sec. 2 iteration repeated
+ * until ||r||_2 <= tol * ||r(phi = 0)||_2; Sec. 4 runtime order switch).
+ *   rho_dev       : float64 (nz, ny, nx), read on active cells.
+ *   phi_dev       : float64 (nz, ny, nx): initial guess in, solution out on
+ *                   active cells; inactive cells are not written.
+ *   dirichlet_dev : float64 cell-centred field B or NULL (= 0).  The value on
+ *                   the face between active i and inactive j is (B_i+B_j)/2.
+ *   tol           : > 0.   info: NULL or receives the solve record.
+ * Returns MG_OK, MG_NOT_CONVERGED, MG_ERR_DIVERGED, MG_ERR_ARG, MG_ERR_HIP.
+ */
+mg_status mg_solve(mg_hierarchy *H, const double *rho_dev, double *phi_dev, const double *dirichlet_dev, double tol,
+                   mg_solve_info *info);
+
+/* ||Delta phi - rho||_2 over active cells (Sec. 2 step 2) into *norm_out (host). */
+mg_status mg_residual_norm(mg_hierarchy *H, const double *rho_dev, const double *phi_dev,
+                           const double *dirichlet_dev, double *norm_out);
+
+/* Static text of a status code. */
+const char *mg_status_string(mg_status s);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *mg_last_error(void);
+
+/* ---------------- introspection ---------------- */
+
+/* Levels used by boundary order `order` (1 or 2; 0 = levels that exist
+ * geometrically).  The deepest used level is the deepest non-empty one. */
+int32_t mg_num_levels(const mg_hierarchy *H, int32_t order);
+
+/* dims_out[0..2] = (nx, ny, nz) of level l. */
+mg_status mg_level_dims(const mg_hierarchy *H, int32_t level, int32_t *dims_out);
+
+/* Number of active cells of level l under boundary order `order`. */
+int64_t mg_level_active(const mg_hierarchy *H, int32_t level, int32_t order);
+
+/* Copy the integer mask counts of level l (active finest descendants per
+ * cell, int32, dims of level l) into a device array (Sec. 3 R1 of the mask). */
+mg_status mg_level_counts(const mg_hierarchy *H, int32_t level, int32_t *counts_dev);
+
+/* Copy the operator diagonal d (the cell's coefficient in h^2 * Laplacian,
+ * negated; 0 on inactive cells) of level l and order into a float64 device
+ * array.  Level 0: 6 active-neighbour faces + 2 per boundary face (Sec. 3,
+ * boundary on the face); coarse levels: active neighbours + 1/theta. */
+mg_status mg_level_diag(const mg_hierarchy *H, int32_t level, int32_t order, double *d_dev);
+
+/* ---------------- single steps (Sec. 2 iteration), FP64 ---------------- */
+/* All fields below are float64 device boxes of the named level.  Inputs are
+ * read on active cells only; outputs are written on every cell (0 off the
+ * active set unless stated). */
+
+/* Right-hand side with the Dirichlet values folded in: f = rho - (1/h^2)
+ * sum over boundary faces of (B_i + B_j); the finest system is then
+ * (1/h^2)(sum_active x_j - d_i x_i) = f_i. */
+mg_status mg_fold(mg_hierarchy *H, const double *rho_dev, const double *dirichlet_dev, double *f_dev);
+
+/* `passes` red-black Gauss-Seidel passes (red = (i+j+k) even first) on
+ * level l for the system L x = f (Sec. 2); x in/out. */
+mg_status mg_smooth(mg_hierarchy *H, int32_t level, int32_t order, double *x_dev, const double *f_dev,
+                    int32_t passes);
+
+/* r = L x - f on level l (Sec. 2 step 2). */
+mg_status mg_residual(mg_hierarchy *H, int32_t level, int32_t order, const double *x_dev, const double *f_dev,
+                      double *r_dev);
+
+/* Coarse right-hand side f_c = -R1(L x - f) on level l+1 (Sec. 2 steps 2-5):
+ * the sum over active children divided by 8, on active coarse cells. */
+mg_status mg_restrict_residual(mg_hierarchy *H, int32_t level, int32_t order, const double *x_dev,
+                               const double *f_dev, double *fc_dev);
+
+/* x += P2(xc) on active cells of level l, xc on level l+1 (Sec. 2 steps
+ * 6-7; coarse values off the coarse domain count as 0).  x in/out. */
+mg_status mg_prolong(mg_hierarchy *H, int32_t level, int32_t order, const double *xc_dev, double *x_dev);
+
+/* One multigrid iteration MG(0) (Sec. 2) on the folded finest system,
+ * x in/out (finest level), f from mg_fold. */
+mg_status mg_vcycle(mg_hierarchy *H, int32_t order, double *x_dev, const double *f_dev);
+
+/*
+ * Run the finest-level smoother kernel `launches` times on the hierarchy's
+ * own buffers (contents left by the last solve), back to back on the
+ * hierarchy stream, for bandwidth measurement.  Host returns at once.
+ */
+mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches);
+
+/* The stream the hierarchy enqueues on (as void*). */
+void *mg_stream(const mg_hierarchy *H);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

@@ -1,0 +1,813 @@
+// C ABI of the masked multigrid library: hierarchy construction, the
+// multigrid iteration as a fixed kernel sequence (replayed as a hipGraph), the
+// solve loop with the runtime order switch, and single-step entry points.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "mg_core.h"
+
+namespace mg {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &s) { g_err = s; }
+
+bool hip_ok(hipError_t e, const char *what) {
+    if (e == hipSuccess) return true;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return false;
+}
+
+void *dev_alloc(mg_hierarchy *H, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (H->opt.allocator.alloc) {
+        p = H->opt.allocator.alloc(bytes, H->opt.allocator.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) H->allocs.push_back(p);
+    return p;
+}
+
+namespace {
+
+struct Fail {
+    mg_status st;
+};
+
+#define HIPCHK(call)                                  \
+    do {                                              \
+        if (!hip_ok((call), #call)) throw Fail{MG_ERR_HIP}; \
+    } while (0)
+
+template <typename T>
+T *alloc_n(mg_hierarchy *H, size_t n) {
+    void *p = dev_alloc(H, n * sizeof(T));
+    if (!p) {
+        set_error("device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+        throw Fail{MG_ERR_ALLOC};
+    }
+    return (T *)p;
+}
+
+const OrderData &odata(const mg_hierarchy *H, int l, int order) { return H->lev[l].od[l == 0 ? 2 : order]; }
+
+// ---------------------------------------------------------------- build --
+
+void build_lists(mg_hierarchy *H, int l, int order) {
+    Level &L = H->lev[l];
+    const int nt = L.ntx * L.nty * L.ntz;
+    uint8_t *flags = alloc_n<uint8_t>(H, (size_t)nt);
+    launch_tile_flags(L, l, order, flags, H->stream);
+    std::vector<uint8_t> hf(nt);
+    HIPCHK(hipMemcpyAsync(hf.data(), flags, nt, hipMemcpyDeviceToHost, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+    std::vector<int> tiles;
+    for (int t = 0; t < nt; t++)
+        if (hf[t]) tiles.push_back(t);
+    // smoother items: runs of active tiles along z, cut every SEG_TILES tiles
+    std::vector<Seg> segs;
+    for (int ty = 0; ty < L.nty; ty++)
+        for (int tx = 0; tx < L.ntx; tx++) {
+            int tz = 0;
+            while (tz < L.ntz) {
+                if (!hf[(tz * L.nty + ty) * L.ntx + tx]) {
+                    tz++;
+                    continue;
+                }
+                int t1 = tz;
+                const int seg_tiles = (l == 0) ? SEG_TILES_FINE : SEG_TILES_COARSE;
+                while (t1 < L.ntz && hf[(t1 * L.nty + ty) * L.ntx + tx] && t1 - tz < seg_tiles) t1++;
+                segs.push_back(Seg{tx * TX, ty * TY, tz * TZ, std::min(L.nz, t1 * TZ)});
+                tz = t1;
+            }
+        }
+    std::sort(segs.begin(), segs.end(), [](const Seg &a, const Seg &b) {
+        if (a.z0 != b.z0) return a.z0 < b.z0;
+        if (a.y0 != b.y0) return a.y0 < b.y0;
+        return a.x0 < b.x0;
+    });
+    OrderData &od = L.od[order];
+    od.ntiles = (int)tiles.size();
+    od.nsegs = (int)segs.size();
+    od.tiles = alloc_n<int>(H, std::max<size_t>(1, tiles.size()));
+    od.segs = alloc_n<Seg>(H, std::max<size_t>(1, segs.size()));
+    if (!tiles.empty())
+        HIPCHK(hipMemcpyAsync(od.tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, H->stream));
+    if (!segs.empty())
+        HIPCHK(hipMemcpyAsync(od.segs, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice, H->stream));
+    HIPCHK(hipStreamSynchronize(H->stream));
+}
+
+mg_status validate_options(const mg_options &o) {
+    if (o.n_pre < 0 || o.n_post < 0 || o.n_cycles < 1 || o.n_coarse_sweeps < 0 || o.min_coarse_dim < 1 ||
+        o.max_cycles < 0 || (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.bc_order < 0 ||
+        o.bc_order > 2 || !(o.eta > 0) || o.first_order_hold < 0) {
+        set_error("invalid mg_options");
+        return MG_ERR_ARG;
+    }
+    if (o.n_cycles > 4) {
+        set_error("n_cycles above 4 is not supported");
+        return MG_ERR_ARG;
+    }
+    return MG_OK;
+}
+
+void create(mg_hierarchy *H, const int8_t *mask, int nx, int ny, int nz, double h) {
+    hipStream_t s = H->stream;
+    HIPCHK(hipGetDevice(&H->device));
+    // geometry of the levels: halve while every edge is even and stays >= min_coarse_dim
+    Level *lev = H->lev;
+    lev[0].nx = nx; lev[0].ny = ny; lev[0].nz = nz; lev[0].h = h;
+    int L = 1;
+    while (L < MAXL) {
+        const Level &p = lev[L - 1];
+        if (p.nx % 2 || p.ny % 2 || p.nz % 2) break;
+        const int m = H->opt.min_coarse_dim;
+        if (p.nx / 2 < m || p.ny / 2 < m || p.nz / 2 < m) break;
+        lev[L].nx = p.nx / 2; lev[L].ny = p.ny / 2; lev[L].nz = p.nz / 2; lev[L].h = 2 * p.h;
+        L++;
+    }
+    H->nlev_geom = L;
+    for (int l = 0; l < L; l++) {
+        Level &v = lev[l];
+        v.n = (size_t)v.nx * v.ny * v.nz;
+        v.ntx = (v.nx + TX - 1) / TX;
+        v.nty = (v.ny + TY - 1) / TY;
+        v.ntz = (v.nz + TZ - 1) / TZ;
+    }
+    // validation on the device: bad values, non-inactive frame, active count
+    unsigned long long *ctr = alloc_n<unsigned long long>(H, 3 + 2 * MAXL + 1);
+    HIPCHK(hipMemsetAsync(ctr, 0, (3 + 2 * MAXL + 1) * sizeof(unsigned long long), s));
+    launch_validate(mask, nx, ny, nz, ctr, s);
+    unsigned long long hv[3 + 2 * MAXL + 1];
+    HIPCHK(hipMemcpyAsync(hv, ctr, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hv[0]) {
+        set_error("mask holds " + std::to_string(hv[0]) + " values other than +1/-1");
+        throw Fail{MG_ERR_ARG};
+    }
+    if (hv[1]) {
+        set_error("mask has " + std::to_string(hv[1]) + " active cells in the outermost layer");
+        throw Fail{MG_ERR_ARG};
+    }
+    if (hv[2] == 0) {
+        set_error("mask has no active cell");
+        throw Fail{MG_ERR_NO_ACTIVE};
+    }
+    // integer mask counts per level (R1 of the mask)
+    for (int l = 0; l < L; l++) lev[l].cnt = alloc_n<int32_t>(H, lev[l].n);
+    launch_count0(mask, lev[0].cnt, lev[0].n, s);
+    for (int l = 1; l < L; l++) launch_count_up(lev[l - 1], lev[l], s);
+    // finest code, coarse diagonals per order
+    lev[0].code = alloc_n<uint8_t>(H, lev[0].n);
+    unsigned long long *nact = ctr + 3;
+    launch_code0(lev[0], nact, s);
+    for (int o = 1; o <= 2; o++)
+        for (int l = 1; l < L; l++) {
+            lev[l].od[o].d = alloc_n<double>(H, lev[l].n);
+            launch_diag(lev[l], l, o, lev[l].od[o].d, nact + 2 * l + (o - 1), s);
+        }
+    HIPCHK(hipMemcpyAsync(hv, nact, (2 * MAXL + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    lev[0].od[1].nact = lev[0].od[2].nact = (int64_t)hv[0];
+    for (int o = 1; o <= 2; o++) {
+        H->nlev[o] = 1;
+        for (int l = 1; l < L; l++) {
+            lev[l].od[o].nact = (int64_t)hv[2 * l + (o - 1)];
+            if (lev[l].od[o].nact > 0 && H->nlev[o] == l) H->nlev[o] = l + 1;
+        }
+    }
+    // active tile lists
+    build_lists(H, 0, 2);
+    lev[0].od[1] = lev[0].od[2];
+    for (int o = 1; o <= 2; o++)
+        for (int l = 1; l < H->nlev[o]; l++) build_lists(H, l, o);
+    // level buffers
+    const int nl = std::max(H->nlev[1], H->nlev[2]);
+    const bool mixed = H->opt.precision == MG_MIXED;
+    for (int l = 0; l < nl; l++) {
+        Level &v = lev[l];
+        for (int b = 0; b < 2; b++) {
+            v.x[b] = alloc_n<double>(H, v.n);
+            HIPCHK(hipMemsetAsync(v.x[b], 0, v.n * sizeof(double), s));
+        }
+        v.f = alloc_n<double>(H, v.n);
+        HIPCHK(hipMemsetAsync(v.f, 0, v.n * sizeof(double), s));
+        if (mixed) {
+            for (int b = 0; b < 2; b++) {
+                v.x32[b] = alloc_n<float>(H, v.n);
+                HIPCHK(hipMemsetAsync(v.x32[b], 0, v.n * sizeof(float), s));
+            }
+            v.f32 = alloc_n<float>(H, v.n);
+            HIPCHK(hipMemsetAsync(v.f32, 0, v.n * sizeof(float), s));
+            if (l > 0)
+                for (int o = 1; o <= 2; o++)
+                    if (l < H->nlev[o]) {
+                        v.od[o].d32 = alloc_n<float>(H, v.n);
+                        launch_to_float(v.od[o].d, v.od[o].d32, v.n, s);
+                    }
+        }
+    }
+    // first level of the one-workgroup kernel, per order
+    const int small_lim = small_init();
+    for (int o = 1; o <= 2; o++) {
+        H->ls[o] = -1;
+        for (int l = 1; l < H->nlev[o]; l++)
+            if (lev[l].n <= SMALL_MAX_CELLS && H->nlev[o] - l <= MAXS &&
+                small_lds_bytes(H, o, l, false) <= (size_t)small_lim) {
+                H->ls[o] = l;
+                break;
+            }
+    }
+    H->part_cap = std::max(1, lev[0].od[2].ntiles * TZ);
+    H->part = alloc_n<double>(H, (size_t)H->part_cap);
+    H->norm_dev = alloc_n<double>(H, 8);
+    HIPCHK(hipMemsetAsync(H->norm_dev, 0, 8 * sizeof(double), s));
+    HIPCHK(hipHostMalloc((void **)&H->norm_host, 8 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipEventCreate(&H->ev0));
+    HIPCHK(hipEventCreate(&H->ev1));
+    HIPCHK(hipStreamSynchronize(s));
+    H->coarse_order_state = 0;
+}
+
+// ---------------------------------------------------------- iteration --
+
+struct Cur {
+    int c[MAXL];
+};
+
+// `passes` red-black passes on level l; zero_start: the iterate starts at 0.
+void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur &cur, bool f32) {
+    Level &L = H->lev[l];
+    const OrderData &od = odata(H, l, order);
+    if (passes == 0) {
+        if (zero_start) {
+            if (f32) launch_zero_tiles32(L, od, L.x32[cur.c[l]], H->stream);
+            else launch_zero_tiles(L, od, L.x[cur.c[l]], H->stream);
+        }
+        return;
+    }
+    for (int p = 0; p < passes; p++) {
+        const int a = cur.c[l], b = a ^ 1;
+        const bool zin = (p == 0 && zero_start);
+        if (f32) launch_rbgs32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream);
+        else launch_rbgs(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream);
+        cur.c[l] = b;
+    }
+}
+
+// One multigrid iteration at level l (Sec. 2 enumerated recipe): N_pre
+// passes, residual and R1 restriction, N_cycles iterations of the coarse
+// correction problem from zero, P2 prolongation and correction, N_post passes.
+// The deepest level is relaxed n_coarse_sweeps times.
+void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool f32) {
+    const mg_options &o = H->opt;
+    const int last = H->nlev[order] - 1;
+    Level &L = H->lev[l];
+    if (l == H->ls[order]) {
+        // the whole call MG(l) on the small levels in one workgroup
+        if (f32) launch_small32(H, order, l, zero_start, L.f32, L.x32[cur.c[l]], H->stream);
+        else launch_small(H, order, l, zero_start, L.f, L.x[cur.c[l]], H->stream);
+        return;
+    }
+    if (l == last) {
+        smooth(H, l, order, o.n_coarse_sweeps, zero_start, cur, f32);
+        return;
+    }
+    Level &C = H->lev[l + 1];
+    smooth(H, l, order, o.n_pre, zero_start, cur, f32);
+    if (f32) launch_restrict32(L, C, l, order, L.x32[cur.c[l]], L.f32, C.f32, H->stream);
+    else launch_restrict(L, C, l, order, L.x[cur.c[l]], L.f, C.f, H->stream);
+    for (int c = 0; c < o.n_cycles; c++) mg_level(H, l + 1, order, c == 0, cur, f32);
+    if (f32) launch_prolong32(L, C, l, order, C.x32[cur.c[l + 1]], L.x32[cur.c[l]], H->stream);
+    else launch_prolong(L, C, l, order, C.x[cur.c[l + 1]], L.x[cur.c[l]], H->stream);
+    smooth(H, l, order, o.n_post, false, cur, f32);
+}
+
+// Coarse iterates must be 0 outside the active tiles of the order in use.
+void ensure_coarse_clean(mg_hierarchy *H, int order) {
+    if (H->coarse_order_state == 0 || H->coarse_order_state == order) {
+        H->coarse_order_state = order;
+        return;
+    }
+    for (int l = 1; l < std::max(H->nlev[1], H->nlev[2]); l++) {
+        Level &L = H->lev[l];
+        for (int b = 0; b < 2; b++) {
+            HIPCHK(hipMemsetAsync(L.x[b], 0, L.n * sizeof(double), H->stream));
+            if (L.x32[b]) HIPCHK(hipMemsetAsync(L.x32[b], 0, L.n * sizeof(float), H->stream));
+        }
+    }
+    H->coarse_order_state = order;
+}
+
+void zero_level_x(mg_hierarchy *H, int l) {
+    Level &L = H->lev[l];
+    for (int b = 0; b < 2; b++) HIPCHK(hipMemsetAsync(L.x[b], 0, L.n * sizeof(double), H->stream));
+}
+
+// One solve-loop cycle as a kernel sequence: FP64 MG(0) then the residual
+// norm of the new iterate, or (mixed) the FP32 inner MG(0) on L e = f - L x
+// from e = 0, x += e, and the FP64 residual norm that also writes the next
+// inner right-hand side.  Ends with an 8-byte copy of the norm to the host.
+void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out) {
+    Cur cur;
+    for (int l = 0; l < MAXL; l++) cur.c[l] = 0;
+    Level &L0 = H->lev[0];
+    const OrderData &od0 = odata(H, 0, order);
+    if (!mixed) {
+        cur.c[0] = parity;
+        mg_level(H, 0, order, false, cur, false);
+        launch_resnorm(L0, 0, od0, L0.x[cur.c[0]], L0.f, H->part, H->norm_dev, 0, H->stream);
+    } else {
+        mg_level(H, 0, order, true, cur, true);
+        launch_axpy32(L0, od0, L0.x32[cur.c[0]], L0.x[parity], H->stream);
+        launch_resnorm32(L0, od0, L0.x[parity], L0.f, L0.f32, H->part, H->norm_dev, 0, H->stream);
+    }
+    HIPCHK(hipMemcpyAsync(H->norm_host, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
+    *parity_out = mixed ? parity : cur.c[0];
+}
+
+int cycle_parity_after(const mg_hierarchy *H, int order, int parity) {
+    const mg_options &o = H->opt;
+    const int passes = (H->nlev[order] == 1) ? o.n_coarse_sweeps : (o.n_pre + o.n_post);
+    return parity ^ (passes & 1);
+}
+
+void run_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out) {
+    if (!H->opt.use_graph) {
+        enqueue_cycle(H, order, parity, mixed, parity_out);
+        return;
+    }
+    for (auto &g : H->graphs)
+        if (g.order == order && g.parity == parity && g.mixed == mixed) {
+            HIPCHK(hipGraphLaunch(g.exec, H->stream));
+            *parity_out = mixed ? parity : cycle_parity_after(H, order, parity);
+            return;
+        }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(H->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_cycle(H, order, parity, mixed, parity_out);
+    } catch (...) {
+        hipGraph_t tmp;
+        (void)hipStreamEndCapture(H->stream, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(H->stream, &graph));
+    Graph g;
+    g.order = order;
+    g.parity = parity;
+    g.mixed = mixed;
+    HIPCHK(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    H->graphs.push_back(g);
+    HIPCHK(hipGraphLaunch(g.exec, H->stream));
+}
+
+double read_norm(mg_hierarchy *H) {
+    HIPCHK(hipStreamSynchronize(H->stream));
+    return sqrt(H->norm_host[0]);
+}
+
+mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol, mg_solve_info *info) {
+    const mg_options &o = H->opt;
+    mg_solve_info tmp;
+    if (!info) info = &tmp;
+    memset(info, 0, sizeof(*info));
+    info->switched_at_cycle = -1;
+    int order;
+    if (o.bc_order == MG_BC_FIRST || o.bc_order == MG_BC_SECOND) {
+        order = o.bc_order;
+    } else if (H->hold_left > 0) {
+        order = 1;
+        H->hold_left--;
+    } else {
+        order = 2;
+    }
+    const bool mixed = o.precision == MG_MIXED;
+    Level &L0 = H->lev[0];
+    const OrderData &od0 = odata(H, 0, order);
+    hipStream_t s = H->stream;
+    ensure_coarse_clean(H, order);
+    HIPCHK(hipEventRecord(H->ev0, s));
+    launch_fold(L0, od0, rho, B, phi, L0.f, L0.x[0], s);
+    launch_resnorm(L0, 0, od0, nullptr, L0.f, H->part, H->norm_dev, 1, s);
+    if (mixed) launch_resnorm32(L0, od0, L0.x[0], L0.f, L0.f32, H->part, H->norm_dev, 0, s);
+    else launch_resnorm(L0, 0, od0, L0.x[0], L0.f, H->part, H->norm_dev, 0, s);
+    HIPCHK(hipMemcpyAsync(H->norm_host, H->norm_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double rprev = sqrt(H->norm_host[0]);
+    double rref = sqrt(H->norm_host[1]);
+    info->r0 = rprev;
+    if (rref == 0.0) rref = rprev;
+    info->r_ref = rref;
+    info->history[0] = rprev;
+    info->order_used = order;
+    info->r_final = rprev;
+    mg_status st = MG_NOT_CONVERGED;
+    int parity = 0;
+    if (!(rprev > tol * rref)) {
+        st = std::isfinite(rprev) ? MG_OK : MG_ERR_DIVERGED;
+    } else {
+        for (int n = 1; n <= o.max_cycles; n++) {
+            int np = parity;
+            run_cycle(H, order, parity, mixed, &np);
+            parity = np;
+            const double rn = read_norm(H);
+            info->cycles = n;
+            info->r_final = rn;
+            if (n < 257) info->history[n] = rn;
+            if (!std::isfinite(rn)) {
+                st = MG_ERR_DIVERGED;
+                break;
+            }
+            if (rn <= tol * rref) {
+                st = MG_OK;
+                break;
+            }
+            if (o.bc_order == MG_BC_AUTO && order == 2 && rn / rprev > o.eta) {
+                order = 1;
+                H->hold_left = o.first_order_hold;
+                info->switched_at_cycle = n;
+                info->order_used = 1;
+                ensure_coarse_clean(H, order);
+            }
+            rprev = rn;
+        }
+    }
+    launch_store(L0, od0, L0.x[parity], phi, s);
+    HIPCHK(hipEventRecord(H->ev1, s));
+    HIPCHK(hipEventSynchronize(H->ev1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, H->ev0, H->ev1));
+    info->ms = ms;
+    info->status = st;
+    return st;
+}
+
+mg_status check_level(const mg_hierarchy *H, int level, int order, bool need_coarser) {
+    if (!H) {
+        set_error("null hierarchy");
+        return MG_ERR_ARG;
+    }
+    if (order != 1 && order != 2) {
+        set_error("order must be 1 or 2");
+        return MG_ERR_ARG;
+    }
+    const int top = H->nlev[order] - (need_coarser ? 1 : 0);
+    if (level < 0 || level >= top) {
+        set_error("level out of range for this order");
+        return MG_ERR_ARG;
+    }
+    return MG_OK;
+}
+
+template <class F>
+mg_status guarded(F &&fn) {
+    try {
+        return fn();
+    } catch (const Fail &f) {
+        return f.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return MG_ERR_ALLOC;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return MG_ERR_HIP;
+    }
+}
+
+}  // namespace
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+void mg_default_options(mg_options *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->n_pre = 2;
+    o->n_post = 2;
+    o->n_cycles = 1;
+    o->n_coarse_sweeps = 32;
+    o->min_coarse_dim = 4;
+    o->max_cycles = 200;
+    o->precision = MG_FP64;
+    o->bc_order = MG_BC_AUTO;
+    o->eta = 0.5;
+    o->first_order_hold = 10;
+    o->use_graph = 1;
+}
+
+const char *mg_status_string(mg_status s) {
+    switch (s) {
+        case MG_OK: return "ok";
+        case MG_NOT_CONVERGED: return "not converged (max_cycles reached)";
+        case MG_ERR_ARG: return "invalid argument";
+        case MG_ERR_NO_ACTIVE: return "mask has no active cell";
+        case MG_ERR_HIP: return "HIP runtime error";
+        case MG_ERR_DIVERGED: return "diverged (non-finite residual)";
+        case MG_ERR_ALLOC: return "allocation failed";
+    }
+    return "unknown status";
+}
+
+const char *mg_last_error(void) { return g_err.c_str(); }
+
+void mg_destroy_hierarchy(mg_hierarchy *H) {
+    if (!H) return;
+    for (auto &g : H->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (H->stream) (void)hipStreamSynchronize(H->stream);
+    for (void *p : H->allocs) {
+        if (H->opt.allocator.free) H->opt.allocator.free(p, H->opt.allocator.ctx);
+        else if (!H->opt.allocator.alloc) (void)hipFree(p);
+    }
+    if (H->norm_host) (void)hipHostFree(H->norm_host);
+    if (H->own_stream && H->stream) (void)hipStreamDestroy(H->stream);
+    if (H->ev0) (void)hipEventDestroy(H->ev0);
+    if (H->ev1) (void)hipEventDestroy(H->ev1);
+    delete H;
+}
+
+mg_status mg_create_hierarchy(const int8_t *mask_dev, int32_t nx, int32_t ny, int32_t nz, double h,
+                              const mg_options *opt, void *stream, mg_hierarchy **out) {
+    set_error("");
+    if (!out) {
+        set_error("out is NULL");
+        return MG_ERR_ARG;
+    }
+    *out = nullptr;
+    if (!mask_dev || nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !std::isfinite(h)) {
+        set_error("invalid mask pointer, dims or h");
+        return MG_ERR_ARG;
+    }
+    if ((size_t)nx * ny * nz >= ((size_t)1 << 34)) {
+        set_error("box too large");
+        return MG_ERR_ARG;
+    }
+    mg_hierarchy *H = new (std::nothrow) mg_hierarchy();
+    if (!H) return MG_ERR_ALLOC;
+    if (opt) H->opt = *opt;
+    else mg_default_options(&H->opt);
+    mg_status st = validate_options(H->opt);
+    if (st != MG_OK) {
+        delete H;
+        return st;
+    }
+    H->stream = (hipStream_t)stream;
+    st = guarded([&]() {
+        if (!H->stream) {
+            // the legacy null stream cannot be captured into a graph: use a
+            // blocking stream of our own (it still orders with the null stream)
+            HIPCHK(hipStreamCreate(&H->stream));
+            H->own_stream = true;
+        }
+        create(H, mask_dev, nx, ny, nz, h);
+        return MG_OK;
+    });
+    if (st != MG_OK) {
+        mg_destroy_hierarchy(H);
+        return st;
+    }
+    *out = H;
+    return MG_OK;
+}
+
+mg_status mg_solve(mg_hierarchy *H, const double *rho_dev, double *phi_dev, const double *dirichlet_dev, double tol,
+                   mg_solve_info *info) {
+    if (!H || !rho_dev || !phi_dev || !(tol > 0)) {
+        set_error("null argument or tol <= 0");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() { return solve(H, rho_dev, phi_dev, dirichlet_dev, tol, info); });
+}
+
+mg_status mg_residual_norm(mg_hierarchy *H, const double *rho_dev, const double *phi_dev,
+                           const double *dirichlet_dev, double *norm_out) {
+    if (!H || !rho_dev || !phi_dev || !norm_out) {
+        set_error("null argument");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        Level &L0 = H->lev[0];
+        const OrderData &od0 = odata(H, 0, 2);
+        // fold into the hierarchy's own buffers, then ||L x - f||
+        launch_fold(L0, od0, rho_dev, dirichlet_dev, phi_dev, L0.f, L0.x[0], H->stream);
+        launch_resnorm(L0, 0, od0, L0.x[0], L0.f, H->part, H->norm_dev, 0, H->stream);
+        HIPCHK(hipMemcpyAsync(H->norm_host, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
+        *norm_out = read_norm(H);
+        return MG_OK;
+    });
+}
+
+int32_t mg_num_levels(const mg_hierarchy *H, int32_t order) {
+    if (!H) return 0;
+    if (order == 1 || order == 2) return H->nlev[order];
+    return H->nlev_geom;
+}
+
+mg_status mg_level_dims(const mg_hierarchy *H, int32_t level, int32_t *dims_out) {
+    if (!H || !dims_out || level < 0 || level >= H->nlev_geom) {
+        set_error("invalid level");
+        return MG_ERR_ARG;
+    }
+    dims_out[0] = H->lev[level].nx;
+    dims_out[1] = H->lev[level].ny;
+    dims_out[2] = H->lev[level].nz;
+    return MG_OK;
+}
+
+int64_t mg_level_active(const mg_hierarchy *H, int32_t level, int32_t order) {
+    if (!H || level < 0 || level >= H->nlev_geom || (order != 1 && order != 2)) return -1;
+    return H->lev[level].od[level == 0 ? 2 : order].nact;
+}
+
+mg_status mg_level_counts(const mg_hierarchy *H, int32_t level, int32_t *counts_dev) {
+    if (!H || !counts_dev || level < 0 || level >= H->nlev_geom) {
+        set_error("invalid level or pointer");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        const Level &L = H->lev[level];
+        HIPCHK(hipMemcpyAsync(counts_dev, L.cnt, L.n * sizeof(int32_t), hipMemcpyDeviceToDevice, H->stream));
+        HIPCHK(hipStreamSynchronize(H->stream));
+        return MG_OK;
+    });
+}
+
+mg_status mg_level_diag(const mg_hierarchy *H, int32_t level, int32_t order, double *d_dev) {
+    if (!H || !d_dev || level < 0 || level >= H->nlev_geom || (order != 1 && order != 2)) {
+        set_error("invalid level, order or pointer");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        const Level &L = H->lev[level];
+        if (level == 0) {
+            // diagonal of the finest level from the neighbour code: 12 - code
+            std::vector<uint8_t> code(L.n);
+            std::vector<double> d(L.n);
+            HIPCHK(hipMemcpyAsync(code.data(), L.code, L.n, hipMemcpyDeviceToHost, H->stream));
+            HIPCHK(hipStreamSynchronize(H->stream));
+            for (size_t p = 0; p < L.n; p++) d[p] = code[p] == CODE_OFF ? 0.0 : 12.0 - code[p];
+            HIPCHK(hipMemcpyAsync(d_dev, d.data(), L.n * sizeof(double), hipMemcpyHostToDevice, H->stream));
+        } else {
+            HIPCHK(hipMemcpyAsync(d_dev, L.od[order].d, L.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
+        }
+        HIPCHK(hipStreamSynchronize(H->stream));
+        return MG_OK;
+    });
+}
+
+mg_status mg_fold(mg_hierarchy *H, const double *rho_dev, const double *dirichlet_dev, double *f_dev) {
+    if (!H || !rho_dev || !f_dev) {
+        set_error("null argument");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        Level &L0 = H->lev[0];
+        HIPCHK(hipMemsetAsync(f_dev, 0, L0.n * sizeof(double), H->stream));
+        launch_fold(L0, odata(H, 0, 2), rho_dev, dirichlet_dev, nullptr, f_dev, nullptr, H->stream);
+        HIPCHK(hipStreamSynchronize(H->stream));
+        return MG_OK;
+    });
+}
+
+mg_status mg_smooth(mg_hierarchy *H, int32_t level, int32_t order, double *x_dev, const double *f_dev,
+                    int32_t passes) {
+    mg_status st = check_level(H, level, order, false);
+    if (st != MG_OK) return st;
+    if (!x_dev || !f_dev || passes < 0) {
+        set_error("null argument or negative passes");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        Level &L = H->lev[level];
+        const OrderData &od = odata(H, level, order);
+        zero_level_x(H, level);
+        launch_copy_masked(L, level, od, x_dev, L.x[0], H->stream);
+        int c = 0;
+        for (int p = 0; p < passes; p++) {
+            launch_rbgs(L, level, od, L.x[c], L.x[c ^ 1], f_dev, H->stream);
+            c ^= 1;
+        }
+        HIPCHK(hipMemcpyAsync(x_dev, L.x[c], L.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
+        zero_level_x(H, level);
+        HIPCHK(hipStreamSynchronize(H->stream));
+        if (level > 0) H->coarse_order_state = 0;
+        return MG_OK;
+    });
+}
+
+mg_status mg_residual(mg_hierarchy *H, int32_t level, int32_t order, const double *x_dev, const double *f_dev,
+                      double *r_dev) {
+    mg_status st = check_level(H, level, order, false);
+    if (st != MG_OK) return st;
+    if (!x_dev || !f_dev || !r_dev) {
+        set_error("null argument");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        Level &L = H->lev[level];
+        const OrderData &od = odata(H, level, order);
+        zero_level_x(H, level);
+        launch_copy_masked(L, level, od, x_dev, L.x[0], H->stream);
+        HIPCHK(hipMemsetAsync(r_dev, 0, L.n * sizeof(double), H->stream));
+        launch_residual(L, level, od, L.x[0], f_dev, r_dev, H->stream);
+        zero_level_x(H, level);
+        HIPCHK(hipStreamSynchronize(H->stream));
+        if (level > 0) H->coarse_order_state = 0;
+        return MG_OK;
+    });
+}
+
+mg_status mg_restrict_residual(mg_hierarchy *H, int32_t level, int32_t order, const double *x_dev,
+                               const double *f_dev, double *fc_dev) {
+    mg_status st = check_level(H, level, order, true);
+    if (st != MG_OK) return st;
+    if (!x_dev || !f_dev || !fc_dev) {
+        set_error("null argument");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        Level &L = H->lev[level];
+        Level &C = H->lev[level + 1];
+        const OrderData &od = odata(H, level, order);
+        zero_level_x(H, level);
+        launch_copy_masked(L, level, od, x_dev, L.x[0], H->stream);
+        HIPCHK(hipMemsetAsync(fc_dev, 0, C.n * sizeof(double), H->stream));
+        launch_restrict(L, C, level, order, L.x[0], f_dev, fc_dev, H->stream);
+        zero_level_x(H, level);
+        HIPCHK(hipStreamSynchronize(H->stream));
+        if (level > 0) H->coarse_order_state = 0;
+        return MG_OK;
+    });
+}
+
+mg_status mg_prolong(mg_hierarchy *H, int32_t level, int32_t order, const double *xc_dev, double *x_dev) {
+    mg_status st = check_level(H, level, order, true);
+    if (st != MG_OK) return st;
+    if (!x_dev || !xc_dev) {
+        set_error("null argument");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        Level &L = H->lev[level];
+        Level &C = H->lev[level + 1];
+        zero_level_x(H, level + 1);
+        launch_copy_masked(C, level + 1, odata(H, level + 1, order), xc_dev, C.x[0], H->stream);
+        launch_prolong(L, C, level, order, C.x[0], x_dev, H->stream);
+        zero_level_x(H, level + 1);
+        HIPCHK(hipStreamSynchronize(H->stream));
+        H->coarse_order_state = 0;
+        return MG_OK;
+    });
+}
+
+mg_status mg_vcycle(mg_hierarchy *H, int32_t order, double *x_dev, const double *f_dev) {
+    mg_status st = check_level(H, 0, order, false);
+    if (st != MG_OK) return st;
+    if (!x_dev || !f_dev) {
+        set_error("null argument");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        Level &L0 = H->lev[0];
+        const OrderData &od0 = odata(H, 0, order);
+        ensure_coarse_clean(H, order);
+        launch_copy_masked(L0, 0, od0, x_dev, L0.x[0], H->stream);
+        HIPCHK(hipMemcpyAsync(L0.f, f_dev, L0.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
+        Cur cur;
+        for (int l = 0; l < MAXL; l++) cur.c[l] = 0;
+        mg_level(H, 0, order, false, cur, false);
+        launch_store(L0, od0, L0.x[cur.c[0]], x_dev, H->stream);
+        HIPCHK(hipStreamSynchronize(H->stream));
+        return MG_OK;
+    });
+}
+
+mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches) {
+    if (!H || (order != 1 && order != 2) || launches < 0) {
+        set_error("invalid argument");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        Level &L0 = H->lev[0];
+        const OrderData &od0 = odata(H, 0, order);
+        for (int p = 0; p < launches; p++) launch_rbgs(L0, 0, od0, L0.x[p & 1], L0.x[(p & 1) ^ 1], L0.f, H->stream);
+        if (launches & 1)
+            HIPCHK(hipMemcpyAsync(L0.x[0], L0.x[1], L0.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
+        return MG_OK;
+    });
+}
+
+void *mg_stream(const mg_hierarchy *H) { return H ? (void *)H->stream : nullptr; }
+
+}  // extern "C"

@@ -1,0 +1,262 @@
+// Small coarse levels in one workgroup.
+//
+// Below a few thousand cells a level is far too small to fill the GPU, and
+// one launch per half-sweep would cost more than the work.  This kernel runs
+// one whole multigrid call MG(ls) (Sec. 2 enumerated recipe, with N_cycles
+// recursive calls per level and n_coarse passes on the deepest level) for the
+// levels ls..last inside one 1024-thread workgroup, with every level's x, f
+// and diagonal resident in LDS.  Red-black Gauss-Seidel is done in place with
+// a barrier between the colours (a colour only reads the other colour).
+#include <algorithm>
+
+#include "mg_core.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int NT = 1024;
+
+template <typename T>
+struct SmallLevels {
+    int n;                 // number of levels held (ls..last)
+    int nx[MAXS], ny[MAXS], nz[MAXS];
+    T h2[MAXS];            // h^2 per level
+    T ih2[MAXS];           // 1/h^2 per level
+    const T *d[MAXS];      // diagonal per level (global), 0 off the domain
+    int off[MAXS];         // LDS offset (elements) of the level's x; f and d follow
+    const T *f0;           // right-hand side of level ls (global)
+    T *x0;                 // iterate of level ls (global, in/out)
+    int load_x;            // 1: start from x0, 0: start from zero
+    int n_pre, n_post, n_cycles, n_coarse;
+};
+
+template <typename T>
+struct Lv {
+    T *x, *f, *d;
+    int nx, ny, nz, n;
+    T h2, ih2;
+};
+
+template <typename T>
+__device__ __forceinline__ T nb_sum(const T *x, int i, int j, int k, int nx, int ny, int nz) {
+    const int p = (k * ny + j) * nx + i;
+    const T xm = i > 0 ? x[p - 1] : T(0);
+    const T xp = i < nx - 1 ? x[p + 1] : T(0);
+    const T ym = j > 0 ? x[p - nx] : T(0);
+    const T yp = j < ny - 1 ? x[p + nx] : T(0);
+    const T zm = k > 0 ? x[p - nx * ny] : T(0);
+    const T zp = k < nz - 1 ? x[p + nx * ny] : T(0);
+    return (xm + xp) + (ym + yp) + (zm + zp);
+}
+
+template <typename T>
+__device__ void smooth(const Lv<T> &L, int passes) {
+    for (int p = 0; p < passes; p++)
+        for (int col = 0; col < 2; col++) {
+            for (int e = threadIdx.x; e < L.n; e += NT) {
+                const int i = e % L.nx, j = (e / L.nx) % L.ny, k = e / (L.nx * L.ny);
+                if (((i + j + k) & 1) != col) continue;
+                const T d = L.d[e];
+                if (d == T(0)) continue;
+                L.x[e] = (nb_sum(L.x, i, j, k, L.nx, L.ny, L.nz) - L.h2 * L.f[e]) / d;
+            }
+            __syncthreads();
+        }
+}
+
+// f_c = -(1/8) sum over active children of (L x - f); x_c = 0.
+template <typename T>
+__device__ void restrict_to(const Lv<T> &L, const Lv<T> &C) {
+    for (int E = threadIdx.x; E < C.n; E += NT) {
+        const int I = E % C.nx, J = (E / C.nx) % C.ny, K = E / (C.nx * C.ny);
+        T s = T(0);
+        if (C.d[E] != T(0)) {
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
+                const int p = (k * L.ny + j) * L.nx + i;
+                const T d = L.d[p];
+                if (d != T(0)) s += (nb_sum(L.x, i, j, k, L.nx, L.ny, L.nz) - d * L.x[p]) * L.ih2 - L.f[p];
+            }
+            s = -s / T(8);
+        }
+        C.f[E] = s;
+        C.x[E] = T(0);
+    }
+    __syncthreads();
+}
+
+// x += P2(x_c) on active cells (weights 3/4, 1/4 per axis; 0 off the box).
+template <typename T>
+__device__ void prolong_from(const Lv<T> &L, const Lv<T> &C) {
+    const T w[2] = {T(0.75), T(0.25)};
+    for (int e = threadIdx.x; e < L.n; e += NT) {
+        if (L.d[e] == T(0)) continue;
+        const int i = e % L.nx, j = (e / L.nx) % L.ny, k = e / (L.nx * L.ny);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+        T s = T(0);
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int a = 0; a < 2; a++) {
+                    const int ci = I + a * sx, cj = J + b * sy, ck = K + c * sz;
+                    T v = T(0);
+                    if (ci >= 0 && ci < C.nx && cj >= 0 && cj < C.ny && ck >= 0 && ck < C.nz)
+                        v = C.x[(ck * C.ny + cj) * C.nx + ci];
+                    s += w[a] * w[b] * w[c] * v;
+                }
+        L.x[e] += s;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_coarse(SmallLevels<T> S) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    // level descriptors live in LDS (dynamic indexing without private memory)
+    __shared__ int s_nx[MAXS], s_ny[MAXS], s_nz[MAXS], s_off[MAXS];
+    __shared__ T s_h2[MAXS], s_ih2[MAXS];
+    if (threadIdx.x < (unsigned)S.n) {
+        const int l = threadIdx.x;
+        s_nx[l] = S.nx[l];
+        s_ny[l] = S.ny[l];
+        s_nz[l] = S.nz[l];
+        s_off[l] = S.off[l];
+        s_h2[l] = S.h2[l];
+        s_ih2[l] = S.ih2[l];
+    }
+    __syncthreads();
+    auto level = [&](int l) {
+        Lv<T> v;
+        v.nx = s_nx[l];
+        v.ny = s_ny[l];
+        v.nz = s_nz[l];
+        v.n = v.nx * v.ny * v.nz;
+        v.x = sm + s_off[l];
+        v.f = v.x + v.n;
+        v.d = v.f + v.n;
+        v.h2 = s_h2[l];
+        v.ih2 = s_ih2[l];
+        return v;
+    };
+    for (int l = 0; l < S.n; l++) {
+        const Lv<T> v = level(l);
+        const T *dg = S.d[l];
+        for (int e = threadIdx.x; e < v.n; e += NT) {
+            v.d[e] = dg[e];
+            v.x[e] = (l == 0 && S.load_x) ? S.x0[e] : T(0);
+            if (l == 0) v.f[e] = S.f0[e];
+        }
+    }
+    __syncthreads();
+    // iterative form of the recursion MG(l): pre-smooth, restrict, N_cycles x
+    // MG(l+1) from zero, prolong, post-smooth; the deepest level is relaxed.
+    // visits: 3 bits per level (N_cycles <= 4).
+    const int last = S.n - 1;
+    unsigned visits = 0;
+    int l = 0;
+    bool down = true;
+    while (true) {
+        if (down) {
+            if (l == last) {
+                smooth(level(l), S.n_coarse);
+                down = false;
+                continue;
+            }
+            smooth(level(l), S.n_pre);
+            restrict_to(level(l), level(l + 1));
+            visits &= ~(7u << (3 * (l + 1)));
+            l++;
+            continue;
+        }
+        if (l == 0) break;
+        const unsigned vc = ((visits >> (3 * l)) & 7u) + 1u;
+        visits = (visits & ~(7u << (3 * l))) | (vc << (3 * l));
+        if ((int)vc < S.n_cycles) {
+            down = true;
+            continue;
+        }
+        prolong_from(level(l - 1), level(l));
+        smooth(level(l - 1), S.n_post);
+        l--;
+    }
+    const Lv<T> top = level(0);
+    for (int e = threadIdx.x; e < top.n; e += NT) S.x0[e] = top.x[e];
+}
+
+template <typename T>
+void launch_impl(const mg_hierarchy *H, int order, int ls, bool zero_start, const T *f0, T *x0, hipStream_t s,
+                 bool f32) {
+    SmallLevels<T> S{};
+    const int last = H->nlev[order] - 1;
+    S.n = last - ls + 1;
+    int off = 0;
+    for (int q = 0; q < S.n; q++) {
+        const Level &L = H->lev[ls + q];
+        S.nx[q] = L.nx;
+        S.ny[q] = L.ny;
+        S.nz[q] = L.nz;
+        S.h2[q] = (T)(L.h * L.h);
+        S.ih2[q] = (T)(1.0 / (L.h * L.h));
+        S.d[q] = f32 ? (const T *)L.od[order].d32 : (const T *)L.od[order].d;
+        S.off[q] = off;
+        off += 3 * (int)L.n;
+    }
+    S.f0 = f0;
+    S.x0 = x0;
+    S.load_x = zero_start ? 0 : 1;
+    S.n_pre = H->opt.n_pre;
+    S.n_post = H->opt.n_post;
+    S.n_cycles = H->opt.n_cycles;
+    S.n_coarse = H->opt.n_coarse_sweeps;
+    const size_t bytes = (size_t)off * sizeof(T);
+    k_coarse<T><<<1, NT, bytes, s>>>(S);
+}
+
+}  // namespace
+
+size_t small_lds_bytes(const mg_hierarchy *H, int order, int ls, bool f32) {
+    size_t n = 0;
+    for (int l = ls; l < H->nlev[order]; l++) n += 3 * H->lev[l].n;
+    return n * (f32 ? sizeof(float) : sizeof(double));
+}
+
+// Largest dynamic LDS the one-workgroup kernel may use on the current device
+// (0 if it cannot run).  Any refused request is cleared so that no error is
+// left pending for the caller's next HIP call.
+int small_init() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int lim = std::min(v, SMALL_LDS_MAX) - 1024;  // room for the kernel's static LDS
+    if (lim > 64 * 1024 - 1024) {
+        if (hipFuncSetAttribute((const void *)k_coarse<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) !=
+                hipSuccess ||
+            hipFuncSetAttribute((const void *)k_coarse<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            lim = 64 * 1024 - 1024;
+        }
+    }
+    return lim > 0 ? lim : 0;
+}
+
+void launch_small(const mg_hierarchy *H, int order, int ls, bool zero_start, const double *f0, double *x0,
+                  hipStream_t s) {
+    launch_impl<double>(H, order, ls, zero_start, f0, x0, s, false);
+}
+
+void launch_small32(const mg_hierarchy *H, int order, int ls, bool zero_start, const float *f0, float *x0,
+                    hipStream_t s) {
+    launch_impl<float>(H, order, ls, zero_start, f0, x0, s, true);
+}
+
+}  // namespace mg

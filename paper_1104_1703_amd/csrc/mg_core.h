@@ -1,0 +1,148 @@
+// Internal declarations of the gfx950 masked multigrid library.
+// Layout of every level: dense (nz, ny, nx) box, x fastest.  Work is issued
+// only over "active tiles" (TX x TY x TZ blocks holding at least one active
+// cell), so cost follows the active cell count, as the paper's hierarchy
+// restricted to active cells does (Sec. 2, Fig. "hierarchy").
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "mg.h"
+
+namespace mg {
+
+constexpr int TX = 32;          // tile width along x (one 256-byte row of doubles)
+constexpr int TY = 8;
+constexpr int TZ = 8;
+constexpr int SEG_TILES_FINE = 2;    // z-tiles per smoother work item on the finest level
+constexpr int SEG_TILES_COARSE = 1;  // ... and on coarse levels (shorter chains, more items)
+constexpr int MAXL = 16;
+constexpr int MAXS = 8;                    // levels handled by the one-workgroup kernel
+constexpr size_t SMALL_MAX_CELLS = 4096;   // first level handled there has at most this many cells
+constexpr int SMALL_LDS_MAX = 160 * 1024;  // LDS of one gfx950 workgroup
+constexpr uint8_t CODE_OFF = 255;
+
+// Smoother work item: origin of an xy tile and a z range [z0, z1).
+struct Seg {
+    int x0, y0, z0, z1;
+};
+
+// Per boundary order data of one level (index 1 = first order, 2 = second).
+struct OrderData {
+    double *d = nullptr;   // operator diagonal (coarse levels), 0 off the active set
+    float *d32 = nullptr;  // float copy for the mixed-precision inner cycle
+    int *tiles = nullptr;  // active tile ids (device)
+    Seg *segs = nullptr;   // smoother work items (device)
+    int ntiles = 0, nsegs = 0;
+    int64_t nact = 0;
+};
+
+struct Level {
+    int nx = 0, ny = 0, nz = 0;
+    double h = 0;
+    size_t n = 0;
+    int ntx = 0, nty = 0, ntz = 0;
+    int32_t *cnt = nullptr;   // active finest descendants per cell
+    uint8_t *code = nullptr;  // level 0: number of active neighbours, CODE_OFF if inactive
+    OrderData od[3];
+    double *x[2] = {nullptr, nullptr};  // ping-pong iterate
+    double *f = nullptr;                // right-hand side
+    float *x32[2] = {nullptr, nullptr};
+    float *f32 = nullptr;
+};
+
+struct Graph {
+    hipGraphExec_t exec = nullptr;
+    int order = 0, parity = 0;
+    bool mixed = false;
+};
+
+}  // namespace mg
+
+struct mg_hierarchy {
+    mg_options opt;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;        // created here because the caller passed the null stream
+    int device = 0;
+    int nlev_geom = 0;
+    int nlev[3] = {0, 0, 0};
+    int ls[3] = {-1, -1, -1};       // first level run by the one-workgroup kernel, per order (-1: none)
+    mg::Level lev[mg::MAXL];
+    int hold_left = 0;
+    int coarse_order_state = 0;     // order whose tiles the coarse x buffers are clean for
+    double *part = nullptr;         // per-block partial sums (device)
+    int part_cap = 0;
+    double *norm_dev = nullptr;     // finalised sums (device, 4 doubles)
+    double *norm_host = nullptr;    // pinned mirror
+    double *scratch = nullptr;      // finest-level float64 scratch (fold/residual of the fine level)
+    double *scratch2 = nullptr;
+    std::vector<void *> allocs;
+    std::vector<mg::Graph> graphs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace mg {
+
+// -------- allocation / errors (api.hip) --------
+void *dev_alloc(mg_hierarchy *H, size_t bytes);
+void set_error(const std::string &s);
+bool hip_ok(hipError_t e, const char *what);
+
+// -------- setup kernels (setup.hip) --------
+void launch_validate(const int8_t *mask, int nx, int ny, int nz, unsigned long long *bad, hipStream_t s);
+void launch_count0(const int8_t *mask, int32_t *cnt, size_t n, hipStream_t s);
+void launch_count_up(const Level &fine, const Level &coarse, hipStream_t s);
+void launch_code0(const Level &L, unsigned long long *nact, hipStream_t s);
+void launch_diag(const Level &L, int level, int order, double *d, unsigned long long *nact, hipStream_t s);
+void launch_tile_flags(const Level &L, int level, int order, uint8_t *flags, hipStream_t s);
+void launch_to_float(const double *a, float *b, size_t n, hipStream_t s);
+
+// -------- smoother (smooth.hip) --------
+// One red-black pass over the segments of `od`; xin == nullptr reads zero.
+void launch_rbgs(const Level &L, int level, const OrderData &od, const double *xin, double *xout,
+                 const double *f, hipStream_t s);
+void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
+                   hipStream_t s);
+
+// -------- small levels in one workgroup (coarse.hip) --------
+size_t small_lds_bytes(const mg_hierarchy *H, int order, int ls, bool f32);
+int small_init();  // usable dynamic LDS bytes of the one-workgroup kernel (0: none)
+// One call MG(ls) for the levels ls..deepest; x0 is level ls's iterate (in/out).
+void launch_small(const mg_hierarchy *H, int order, int ls, bool zero_start, const double *f0, double *x0,
+                  hipStream_t s);
+void launch_small32(const mg_hierarchy *H, int order, int ls, bool zero_start, const float *f0, float *x0,
+                    hipStream_t s);
+
+// -------- transfers and reductions (transfer.hip) --------
+void launch_fold(const Level &L, const OrderData &od, const double *rho, const double *B, const double *phi,
+                 double *f, double *x, hipStream_t s);
+void launch_store(const Level &L, const OrderData &od, const double *x, double *phi, hipStream_t s);
+void launch_copy_masked(const Level &L, int level, const OrderData &od, const double *src, double *dst,
+                        hipStream_t s);
+// Sum of squares of (L x - f) (or of f alone when x == nullptr) into part[],
+// then a fixed-order total into out[slot].
+void launch_resnorm(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *part,
+                    double *out, int slot, hipStream_t s);
+void launch_residual(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *r,
+                     hipStream_t s);
+void launch_restrict(const Level &L, const Level &C, int level, int order, const double *x, const double *f,
+                     double *fc, hipStream_t s);
+void launch_restrict32(const Level &L, const Level &C, int level, int order, const float *x, const float *f,
+                       float *fc, hipStream_t s);
+void launch_prolong(const Level &L, const Level &C, int level, int order, const double *xc, double *x,
+                    hipStream_t s);
+void launch_prolong32(const Level &L, const Level &C, int level, int order, const float *xc, float *x,
+                      hipStream_t s);
+void launch_zero_tiles(const Level &L, const OrderData &od, double *x, hipStream_t s);
+void launch_zero_tiles32(const Level &L, const OrderData &od, float *x, hipStream_t s);
+// Mixed precision: outer FP64 residual norm of the finest level that also
+// writes r32 = f - L x in float (the inner right-hand side), and x += e.
+void launch_resnorm32(const Level &L, const OrderData &od, const double *x, const double *f, float *r32, double *part,
+                      double *out, int slot, hipStream_t s);
+void launch_axpy32(const Level &L, const OrderData &od, const float *e, double *x, hipStream_t s);
+
+}  // namespace mg

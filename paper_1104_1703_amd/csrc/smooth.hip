@@ -1,0 +1,224 @@
+// Masked red-black Gauss-Seidel smoother (Sec. 2: red-black ordering of the
+// 7-point Laplacian; Sec. 3: ghost-modified operator near the boundary).
+//
+// One launch performs one full pass (red half-sweep, then black) over the
+// active segments of a level.  Relaxing an active cell i solves its own
+// equation (1/h^2)(sum_{j active} x_j - d_i x_i) = f_i for x_i; inactive
+// cells hold x = 0, so the neighbour sum runs over all six neighbours.
+//
+// Work item: a TX x TY column of cells marching up a z range.  The block keeps
+// a ring of four planes in LDS: x with a 2-cell xy halo, f and the diagonal
+// (or the finest-level neighbour code) with a 1-cell halo.  At step k it
+// relaxes red cells of plane k+1 on the tile plus a 1-cell ring (redundantly
+// with the neighbouring work items, from identical inputs), then black cells
+// of plane k on the tile, and writes plane k.  Red cells only read black ones
+// and vice versa, so each plane is updated in place; reads come from `xin`
+// and writes go to `xout` (ping-pong), so concurrent work items never see
+// each other's results.  Global loads of the planes needed two and three
+// steps ahead are in flight in registers while a step computes, so the
+// compute phases touch LDS only.  Net HBM traffic per pass: one read of x, f,
+// code/diagonal and one write of x.
+#include <type_traits>
+
+#include "mg_core.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int BX = TX, BY = TY;
+constexpr int PX = BX + 4, PY = BY + 4, PN = PX * PY;  // x plane with 2-cell halo
+constexpr int QX = BX + 2, QY = BY + 2, QN = QX * QY;  // f / diag plane with 1-cell halo
+constexpr int NT = 256;
+constexpr int XR = (PN + NT - 1) / NT;  // x elements per thread per plane
+constexpr int QR = (QN + NT - 1) / NT;  // f elements per thread per plane
+
+// Work items are dealt to the 8 XCDs round-robin by block id; give each XCD a
+// contiguous range of work items so that halo re-reads hit its own L2.
+__device__ __forceinline__ int xcd_item(int b, int nb) {
+    const int per = nb >> 3;  // nb is a multiple of 8
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename T, bool FINE>
+struct PlaneRegs {
+    T x[XR];
+    T f[QR];
+    typename std::conditional<FINE, uint8_t, T>::type d[QR];  // raw code byte or diagonal
+    unsigned ok;  // validity bits: x elements in bits 0..XR-1, f/d elements above
+};
+
+template <typename T, bool FINE>
+__global__ __launch_bounds__(NT) void k_rbgs(const T *__restrict__ xin, T *__restrict__ xout,
+                                              const T *__restrict__ f, const uint8_t *__restrict__ code,
+                                              const T *__restrict__ dco, int nx, int ny, int nz, T h2,
+                                              const Seg *__restrict__ segs, int nsegs) {
+    __shared__ T sx[4][PN];
+    __shared__ T sf[4][QN];
+    __shared__ T sd[4][QN];
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= nsegs) return;
+    const Seg sg = segs[item];
+    const int gx0 = sg.x0 - 2, gy0 = sg.y0 - 2;  // origin of the x plane (2-cell halo)
+    const size_t plane = (size_t)nx * ny;
+    const int tid = threadIdx.x;
+    const int z0 = sg.z0, z1 = sg.z1;
+
+    // Per-thread element positions are the same for every plane: precompute
+    // the clamped in-plane offsets and the in-box flags once.
+    int xoff[XR], qoff[QR];
+    unsigned okxy = 0;
+#pragma unroll
+    for (int q = 0; q < XR; q++) {
+        const int e = min(tid + q * NT, PN - 1);
+        const int gx = gx0 + e % PX, gy = gy0 + e / PX;
+        const bool in = (tid + q * NT < PN) && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        okxy |= (unsigned)in << q;
+        xoff[q] = min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1);
+    }
+#pragma unroll
+    for (int q = 0; q < QR; q++) {
+        const int e = min(tid + q * NT, QN - 1);
+        const int gx = gx0 + 1 + e % QX, gy = gy0 + 1 + e / QX;
+        const bool in = (tid + q * NT < QN) && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        okxy |= (unsigned)in << (XR + q);
+        qoff[q] = min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1);
+    }
+
+    const T *xsrc = xin ? xin : f;  // any valid array of the same shape when x starts at zero
+    // global -> registers for plane k.  Loads are unconditional (clamped
+    // addresses); validity is applied at commit, so issuing never waits.
+    auto fetch = [&](PlaneRegs<T, FINE> &r, int k) {
+        const bool kin = k >= 0 && k < nz && k <= z1 + 1;
+        const size_t base = (size_t)min(max(k, 0), nz - 1) * plane;
+        r.ok = kin ? okxy : 0u;
+        if (!xin) r.ok &= ~((1u << XR) - 1u);  // zero iterate: loaded values are discarded
+#pragma unroll
+        for (int q = 0; q < XR; q++) r.x[q] = xsrc[base + xoff[q]];
+#pragma unroll
+        for (int q = 0; q < QR; q++) {
+            if constexpr (FINE) r.d[q] = code[base + qoff[q]];
+            else r.d[q] = dco[base + qoff[q]];
+            r.f[q] = f[base + qoff[q]];
+        }
+    };
+    // registers -> LDS ring slot of plane k (zeros where invalid)
+    auto commit = [&](const PlaneRegs<T, FINE> &r, int k) {
+        T *dx = sx[k & 3];
+        T *df = sf[k & 3];
+        T *dd = sd[k & 3];
+#pragma unroll
+        for (int q = 0; q < XR; q++) {
+            const int e = tid + q * NT;
+            if (e < PN) dx[e] = ((r.ok >> q) & 1u) ? r.x[q] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < QR; q++) {
+            const int e = tid + q * NT;
+            if (e < QN) {
+                const bool ok = (r.ok >> (XR + q)) & 1u;
+                T dv;
+                if constexpr (FINE) dv = r.d[q] == CODE_OFF ? T(0) : T(12 - (int)r.d[q]);
+                else dv = r.d[q];
+                df[e] = ok ? r.f[q] : T(0);
+                dd[e] = ok ? dv : T(0);
+            }
+        }
+    };
+
+    // Relax colour `col` of plane k on [lo, PX-lo) x [lo, PY-lo) (x-plane coords).
+    auto relax = [&](int k, int col, int lo) {
+        if (k < 0 || k >= nz) return;
+        T *c = sx[k & 3];
+        const T *dn = sx[(k - 1) & 3];
+        const T *up = sx[(k + 1) & 3];
+        const T *fq = sf[k & 3];
+        const T *dq = sd[k & 3];
+        const int half = (PX - 2 * lo) >> 1;
+        const int rows = PY - 2 * lo;
+        for (int e = tid; e < half * rows; e += NT) {
+            const int v = lo + e / half;
+            const int u = lo + ((col + gy0 + v + k + gx0 + lo) & 1) + 2 * (e % half);
+            const int qq = (v - 1) * QX + (u - 1);
+            const T d = dq[qq];
+            if (d == T(0)) continue;  // inactive or outside the box
+            const int q = v * PX + u;
+            const T s = (c[q - 1] + c[q + 1]) + (c[q - PX] + c[q + PX]) + (dn[q] + up[q]);
+            c[q] = (s - h2 * fq[qq]) / d;
+        }
+    };
+
+    auto store = [&](int k) {
+        const T *c = sx[k & 3];
+        for (int e = tid; e < BX * BY; e += NT) {
+            const int u = 2 + e % BX, v = 2 + e / BX;
+            const int gx = gx0 + u, gy = gy0 + v;
+            if (gx < nx && gy < ny) xout[(size_t)k * plane + (size_t)gy * nx + gx] = c[v * PX + u];
+        }
+    };
+
+    PlaneRegs<T, FINE> ra, rb;
+    fetch(ra, z0 - 2);
+    fetch(rb, z0 - 1);
+    commit(ra, z0 - 2);
+    commit(rb, z0 - 1);
+    fetch(ra, z0);
+    fetch(rb, z0 + 1);
+    commit(ra, z0);
+    commit(rb, z0 + 1);
+    fetch(ra, z0 + 2);
+    fetch(rb, z0 + 3);
+    __syncthreads();
+    relax(z0 - 1, 0, 1);
+    relax(z0, 0, 1);
+    __syncthreads();
+    for (int k = z0; k < z1; k += 2) {
+        commit(ra, k + 2);
+        fetch(ra, k + 4);
+        __syncthreads();
+        relax(k + 1, 0, 1);
+        __syncthreads();
+        relax(k, 1, 2);
+        __syncthreads();
+        store(k);
+        if (k + 1 >= z1) break;
+        commit(rb, k + 3);
+        fetch(rb, k + 5);
+        __syncthreads();
+        relax(k + 2, 0, 1);
+        __syncthreads();
+        relax(k + 1, 1, 2);
+        __syncthreads();
+        store(k + 1);
+    }
+}
+
+inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
+
+}  // namespace
+
+void launch_rbgs(const Level &L, int level, const OrderData &od, const double *xin, double *xout, const double *f,
+                 hipStream_t s) {
+    if (od.nsegs == 0) return;
+    const double h2 = L.h * L.h;
+    if (level == 0)
+        k_rbgs<double, true><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
+                                                             od.segs, od.nsegs);
+    else
+        k_rbgs<double, false><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz, h2,
+                                                              od.segs, od.nsegs);
+}
+
+void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
+                   hipStream_t s) {
+    if (od.nsegs == 0) return;
+    const float h2 = (float)(L.h * L.h);
+    if (level == 0)
+        k_rbgs<float, true><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
+                                                            od.segs, od.nsegs);
+    else
+        k_rbgs<float, false><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d32, L.nx, L.ny, L.nz, h2,
+                                                             od.segs, od.nsegs);
+}
+
+}  // namespace mg

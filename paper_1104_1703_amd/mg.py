@@ -1,0 +1,300 @@
+"""Python binding of ``libmg.so`` (the gfx950 masked multigrid library).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  Device memory comes from torch tensors; the library's own level
+buffers can come from torch's caching allocator through the allocator
+callback of ``mg_options``.  The library must be built (``build.py``); if it is
+missing or cannot be loaded, importing the solver raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmg.so")
+
+MG_OK, MG_NOT_CONVERGED, MG_ERR_ARG, MG_ERR_NO_ACTIVE, MG_ERR_HIP, MG_ERR_DIVERGED, MG_ERR_ALLOC = 0, 1, -1, -2, -3, -4, -5
+MG_FP64, MG_MIXED = 0, 1
+MG_BC_AUTO, MG_BC_FIRST, MG_BC_SECOND = 0, 1, 2
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("n_pre", C.c_int32), ("n_post", C.c_int32), ("n_cycles", C.c_int32), ("n_coarse_sweeps", C.c_int32),
+                ("min_coarse_dim", C.c_int32), ("max_cycles", C.c_int32), ("precision", C.c_int32),
+                ("bc_order", C.c_int32), ("eta", C.c_double), ("first_order_hold", C.c_int32),
+                ("use_graph", C.c_int32), ("allocator", Allocator)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("order_used", C.c_int32), ("switched_at_cycle", C.c_int32),
+                ("status", C.c_int32), ("r_ref", C.c_double), ("r0", C.c_double), ("r_final", C.c_double),
+                ("ms", C.c_double), ("history", C.c_double * 257)]
+
+    def as_dict(self):
+        n = min(self.cycles, 256)
+        return {"status": self.status, "cycles": self.cycles, "order_used": self.order_used,
+                "switched_at": self.switched_at_cycle, "r_ref": self.r_ref, "r0": self.r0,
+                "r_final": self.r_final, "ms": self.ms, "history": [self.history[i] for i in range(n + 1)]}
+
+
+# every symbol the C header declares: (name, restype, argtypes)
+_P = C.c_void_p
+_I = C.c_int32
+_D = C.c_double
+SYMBOLS = [
+    ("mg_default_options", None, [C.POINTER(Options)]),
+    ("mg_create_hierarchy", C.c_int, [_P, _I, _I, _I, _D, C.POINTER(Options), _P, C.POINTER(_P)]),
+    ("mg_destroy_hierarchy", None, [_P]),
+    ("mg_solve", C.c_int, [_P, _P, _P, _P, _D, C.POINTER(SolveInfo)]),
+    ("mg_residual_norm", C.c_int, [_P, _P, _P, _P, C.POINTER(_D)]),
+    ("mg_status_string", C.c_char_p, [C.c_int]),
+    ("mg_last_error", C.c_char_p, []),
+    ("mg_num_levels", _I, [_P, _I]),
+    ("mg_level_dims", C.c_int, [_P, _I, C.POINTER(_I)]),
+    ("mg_level_active", C.c_int64, [_P, _I, _I]),
+    ("mg_level_counts", C.c_int, [_P, _I, _P]),
+    ("mg_level_diag", C.c_int, [_P, _I, _I, _P]),
+    ("mg_fold", C.c_int, [_P, _P, _P, _P]),
+    ("mg_smooth", C.c_int, [_P, _I, _I, _P, _P, _I]),
+    ("mg_residual", C.c_int, [_P, _I, _I, _P, _P, _P]),
+    ("mg_restrict_residual", C.c_int, [_P, _I, _I, _P, _P, _P]),
+    ("mg_prolong", C.c_int, [_P, _I, _I, _P, _P]),
+    ("mg_vcycle", C.c_int, [_P, _I, _P, _P]),
+    ("mg_time_smoother", C.c_int, [_P, _I, _I]),
+    ("mg_stream", _P, [_P]),
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmg.so and declare every exported symbol.  Raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"libmg.so not built ({path}); run `python -m paper_1104_1703_amd.build`")
+        lib = C.CDLL(path)
+        for name, res, args in SYMBOLS:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class MGError(RuntimeError):
+    def __init__(self, status, where):
+        lib = load_library()
+        msg = lib.mg_status_string(status).decode()
+        detail = lib.mg_last_error().decode()
+        super().__init__(f"{where}: {msg} ({status}){': ' + detail if detail else ''}")
+        self.status = status
+
+
+def _check(status, where, ok=(MG_OK,)):
+    if status not in ok:
+        raise MGError(status, where)
+    return status
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load_library().mg_default_options(C.byref(o))
+    for k, v in kw.items():
+        if k == "bc_order" and isinstance(v, str):
+            v = {"auto": MG_BC_AUTO, "first": MG_BC_FIRST, "second": MG_BC_SECOND}[v]
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": MG_FP64, "mixed": MG_MIXED}[v]
+        if k == "allocator":
+            continue
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class _TorchAllocator:
+    """Routes the library's level buffers through torch's caching allocator."""
+
+    def __init__(self, device, stream):
+        self.device = device
+        self.stream = stream
+
+        def _alloc(nbytes, ctx):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream))
+            except Exception:  # out of memory: the library reports MG_ERR_ALLOC
+                return None
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc_fn = _ALLOC_FN(_alloc)
+        self.free_fn = _FREE_FN(_free)
+
+    def fill(self, opts: Options):
+        opts.allocator.alloc = self.alloc_fn
+        opts.allocator.free = self.free_fn
+        opts.allocator.ctx = None
+
+
+class Hierarchy:
+    """Multigrid hierarchy of a mask on the current CUDA (HIP) device.
+
+    ``mask``: int8 tensor (nz, ny, nx) with +1 active / -1 inactive cells
+    and an inactive outermost layer.  Options are ``mg_options`` fields
+    (n_pre, n_post, n_cycles, n_coarse_sweeps, min_coarse_dim, max_cycles,
+    precision 'fp64'|'mixed', bc_order 'auto'|'first'|'second', eta,
+    first_order_hold, use_graph); ``torch_allocator`` routes buffers through
+    torch's caching allocator.
+    """
+
+    def __init__(self, mask: torch.Tensor, h: float, stream=None, torch_allocator: bool = True, **options):
+        lib = load_library()
+        if mask.dtype != torch.int8:
+            raise ValueError("mask must be int8")
+        self.device = mask.device
+        # a dedicated stream per hierarchy (graphs cannot be captured on the
+        # legacy default stream); calls order it against the caller's stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.shape = tuple(mask.shape)
+        self.h = float(h)
+        self.opts = default_options(**options)
+        self._alloc = None
+        if torch_allocator:
+            self._alloc = _TorchAllocator(self.device, self.stream)
+            self._alloc.fill(self.opts)
+        nz, ny, nx = self.shape
+        out = C.c_void_p()
+        mask = mask.contiguous()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.device(self.device):
+            st = lib.mg_create_hierarchy(_ptr(mask), nx, ny, nz, self.h, C.byref(self.opts),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(out))
+        _check(st, "mg_create_hierarchy")
+        self._h = out
+
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def _call(self, fn, *args):
+        self._enter()
+        with torch.cuda.device(self.device):
+            st = fn(*args)
+        self._leave()
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            with torch.cuda.device(self.device):
+                load_library().mg_destroy_hierarchy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- introspection ----
+    def nlevels(self, order: int = 0) -> int:
+        return int(load_library().mg_num_levels(self._h, order))
+
+    def dims(self, level: int):
+        d = (C.c_int32 * 3)()
+        _check(load_library().mg_level_dims(self._h, level, d), "mg_level_dims")
+        return int(d[2]), int(d[1]), int(d[0])
+
+    def n_active(self, level: int = 0, order: int = 2) -> int:
+        return int(load_library().mg_level_active(self._h, level, order))
+
+    def counts(self, level: int) -> torch.Tensor:
+        out = torch.empty(self.dims(level), dtype=torch.int32, device=self.device)
+        _check(self._call(load_library().mg_level_counts, self._h, level, _ptr(out)), "mg_level_counts")
+        return out
+
+    def diag(self, level: int, order: int = 2) -> torch.Tensor:
+        out = torch.empty(self.dims(level), dtype=torch.float64, device=self.device)
+        _check(self._call(load_library().mg_level_diag, self._h, level, order, _ptr(out)), "mg_level_diag")
+        return out
+
+    # ---- solve ----
+    def solve(self, rho, phi=None, dirichlet=None, tol: float = 1e-10, check: bool = True):
+        """Solve in place into ``phi`` (zeros if None); returns (phi, info dict)."""
+        if phi is None:
+            phi = torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+        info = SolveInfo()
+        st = self._call(load_library().mg_solve, self._h, _ptr(rho), _ptr(phi), _ptr(dirichlet), float(tol),
+                        C.byref(info))
+        if check:
+            _check(st, "mg_solve", ok=(MG_OK, MG_NOT_CONVERGED))
+        return phi, info.as_dict()
+
+    def residual_norm(self, rho, phi, dirichlet=None) -> float:
+        out = C.c_double()
+        st = self._call(load_library().mg_residual_norm, self._h, _ptr(rho), _ptr(phi), _ptr(dirichlet),
+                        C.byref(out))
+        _check(st, "mg_residual_norm")
+        return float(out.value)
+
+    # ---- single steps ----
+    def fold(self, rho, dirichlet=None):
+        f = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(self._call(load_library().mg_fold, self._h, _ptr(rho), _ptr(dirichlet), _ptr(f)), "mg_fold")
+        return f
+
+    def smooth(self, level, x, f, passes=1, order=2):
+        x = x.clone().contiguous()
+        _check(self._call(load_library().mg_smooth, self._h, level, order, _ptr(x), _ptr(f), passes), "mg_smooth")
+        return x
+
+    def residual(self, level, x, f, order=2):
+        r = torch.empty_like(x)
+        _check(self._call(load_library().mg_residual, self._h, level, order, _ptr(x), _ptr(f), _ptr(r)), "mg_residual")
+        return r
+
+    def restrict_residual(self, level, x, f, order=2):
+        fc = torch.empty(self.dims(level + 1), dtype=torch.float64, device=self.device)
+        _check(self._call(load_library().mg_restrict_residual, self._h, level, order, _ptr(x), _ptr(f), _ptr(fc)),
+               "mg_restrict_residual")
+        return fc
+
+    def prolong(self, level, xc, x, order=2):
+        x = x.clone().contiguous()
+        _check(self._call(load_library().mg_prolong, self._h, level, order, _ptr(xc), _ptr(x)), "mg_prolong")
+        return x
+
+    def vcycle(self, x, f, order=2):
+        x = x.clone().contiguous()
+        _check(self._call(load_library().mg_vcycle, self._h, order, _ptr(x), _ptr(f)), "mg_vcycle")
+        return x
+
+    def time_smoother(self, launches: int, order: int = 2):
+        _check(self._call(load_library().mg_time_smoother, self._h, order, launches), "mg_time_smoother")

@@ -1,0 +1,292 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Bar (FP64): max |gpu - oracle| / max |oracle| <= 1e-11 per field after the
+same number of operations; integer hierarchy data bit-exact; same cycle
+count, status and switch cycle for solves; residual histories within 1e-6
+relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1104_1703_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def mg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1104_1703_amd import mg as M
+    M.load_library()
+    return M
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b, where=None):
+    if where is not None:
+        a, b = a[where], b[where]
+    scale = max(np.abs(b).max(), 1e-300)
+    return float(np.abs(a - b).max() / scale)
+
+
+PROBLEMS = {
+    "sphere32": lambda: gen.sphere_problem(32),
+    "holes64": lambda: gen.holes_problem(n=64, seed=2),
+    "rand_ragged": lambda: gen.random_small_problem((24, 40, 56), 3, active_frac=0.7, blur=1.5),
+    "rand_dirichlet": lambda: gen.random_small_problem((32, 32, 32), 5, active_frac=0.8, blur=1.0),
+    "porous64": lambda: gen.porous_problem(n=64, seed=4),
+    "patch_odd": lambda: gen.patch_problems(count=3, seed=3)[2],
+}
+
+
+def _print_case(name, p):
+    print(f"[case] {name} shape={p.shape} active={p.n_active}", flush=True)
+
+
+def _pair(name, mg, **opts):
+    p = PROBLEMS[name]()
+    _print_case(name, p)
+    H = mg.Hierarchy(dev(p.mask), p.h, **opts)
+    orc = O.Oracle(p.mask, p.h, min_coarse_dim=opts.get("min_coarse_dim", 4))
+    return p, H, orc
+
+
+# ---------------------------------------------------------------- hierarchy
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_hierarchy_counts_and_active_sets(mg, name):
+    p, H, orc = _pair(name, mg)
+    assert H.nlevels(0) == orc.nlevels(0)
+    for order in (1, 2):
+        assert H.nlevels(order) == orc.nlevels(order)
+    for l in range(orc.nlevels(0)):
+        assert np.array_equal(host(H.counts(l)), orc.counts(l).astype(np.int32))
+        for order in (1, 2):
+            assert H.n_active(l, order) == int(orc.active(l, order).sum())
+    for order in (1, 2):
+        for l in range(orc.nlevels(order)):
+            assert relerr(host(H.diag(l, order)), orc.diag(l, order)) <= 1e-15
+    H.close()
+
+
+# ---------------------------------------------------------------- operators
+@pytest.mark.parametrize("name", ["sphere32", "rand_ragged", "rand_dirichlet", "patch_odd"])
+def test_fold_equals_minus_residual_of_zero(mg, name):
+    p, H, orc = _pair(name, mg)
+    f = host(H.fold(dev(p.rho), None if p.dirichlet is None else dev(p.dirichlet)))
+    ref = -orc.residual(0, np.zeros(p.shape), p.rho, p.dirichlet)
+    assert relerr(f, ref) <= 1e-13
+    H.close()
+
+
+def _rand_on(act, seed):
+    rng = np.random.default_rng(seed)
+    return np.where(act, rng.standard_normal(act.shape), 0.0)
+
+
+@pytest.mark.parametrize("name", ["sphere32", "holes64", "rand_ragged", "rand_dirichlet", "patch_odd"])
+@pytest.mark.parametrize("order", [1, 2])
+def test_smoother_residual_restrict_prolong_each_level(mg, name, order):
+    p, H, orc = _pair(name, mg)
+    for l in range(orc.nlevels(order)):
+        act = orc.active(l, order).astype(bool)
+        x = _rand_on(act, 10 + l)
+        if l == 0:
+            f_or = p.rho
+            B = p.dirichlet
+            f_gpu = H.fold(dev(p.rho), None if B is None else dev(B))
+        else:
+            f_or = _rand_on(act, 20 + l)
+            B = None
+            f_gpu = dev(f_or)
+        for passes in (1, 2):
+            got = host(H.smooth(l, dev(x), f_gpu, passes=passes, order=order))
+            ref = orc.smooth(l, x, f_or, B, passes=passes, order=order)
+            assert relerr(got, ref) <= TOL, (l, passes)
+        got = host(H.residual(l, dev(x), f_gpu, order=order))
+        ref = orc.residual(l, x, f_or, B, order=order)
+        assert relerr(got, ref) <= TOL, l
+        if l + 1 < orc.nlevels(order):
+            got = host(H.restrict_residual(l, dev(x), f_gpu, order=order))
+            refc = orc.restrict(l, ref, order=order)
+            assert relerr(got, refc) <= TOL, l
+            cact = orc.active(l + 1, order).astype(bool)
+            xc = _rand_on(cact, 30 + l)
+            got = host(H.prolong(l, dev(xc), dev(x), order=order))
+            refp = orc.prolong(l, xc, x, order=order)
+            assert relerr(got, refp, act) <= TOL, l
+    H.close()
+
+
+@pytest.mark.parametrize("name", ["sphere32", "holes64", "rand_dirichlet"])
+@pytest.mark.parametrize("order", [1, 2])
+def test_vcycle_matches_oracle_per_cycle(mg, name, order):
+    p, H, orc = _pair(name, mg)
+    B = p.dirichlet
+    f = H.fold(dev(p.rho), None if B is None else dev(B))
+    x_g = torch.zeros(p.shape, dtype=torch.float64, device="cuda")
+    x_o = np.zeros(p.shape)
+    act = p.mask == 1
+    for c in range(3):
+        x_g = H.vcycle(x_g, f, order=order)
+        x_o = orc.vcycle(x_o, p.rho, B, order=order)
+        assert relerr(host(x_g), x_o, act) <= TOL, c
+    H.close()
+
+
+# ---------------------------------------------------------------- solves
+def _solve_pair(mg, name, tol=1e-10, **opts):
+    p, H, orc = _pair(name, mg, **{k: v for k, v in opts.items() if k in ("min_coarse_dim",)})
+    H.close()
+    H = mg.Hierarchy(dev(p.mask), p.h, **opts)
+    B = None if p.dirichlet is None else dev(p.dirichlet)
+    phi, info = H.solve(dev(p.rho), None, B, tol=tol)
+    oo = {k: v for k, v in opts.items() if k in ("n_pre", "n_post", "n_cycles", "max_cycles", "bc_order", "eta")}
+    if "n_coarse_sweeps" in opts:
+        oo["n_coarse"] = opts["n_coarse_sweeps"]
+    ref, rinfo = orc.solve(p.rho, None, p.dirichlet, tol=tol, **oo)
+    return p, H, host(phi), info, ref, rinfo
+
+
+@pytest.mark.parametrize("name", ["sphere32", "holes64", "rand_ragged", "rand_dirichlet", "patch_odd"])
+def test_solve_matches_oracle(mg, name):
+    p, H, got, info, ref, rinfo = _solve_pair(mg, name)
+    act = p.mask == 1
+    assert info["status"] == rinfo["status"] == 0
+    assert info["cycles"] == rinfo["cycles"]
+    assert info["switched_at"] == rinfo["switched_at"]
+    assert relerr(got, ref, act) <= TOL
+    # residual norms agree to 1e-6 relative down to the cancellation floor:
+    # evaluating h^-2 (sum x_j - d x_i) - f loses about eps * ||f|| absolutely
+    h1, h2 = np.array(info["history"]), np.array(rinfo["history"])
+    assert np.all(np.abs(h1 - h2) <= 1e-6 * h2 + 1e-13 * info["r_ref"])
+    assert info["r_final"] <= 1e-10 * info["r_ref"]
+    H.close()
+
+
+def test_solve_auto_switch_islands(mg):
+    p, H, got, info, ref, rinfo = _solve_pair(mg, "porous64", tol=1e-10)
+    assert rinfo["switched_at"] >= 1
+    assert info["switched_at"] == rinfo["switched_at"] and info["order_used"] == 1
+    assert info["cycles"] == rinfo["cycles"]
+    assert relerr(got, ref, p.mask == 1) <= TOL
+    # the next solve starts in first order (hold of 10 solves)
+    B = None
+    phi2, info2 = H.solve(dev(p.rho), None, B, tol=1e-10)
+    assert info2["order_used"] == 1 and info2["switched_at"] == -1
+    H.close()
+
+
+@pytest.mark.parametrize("opts", [dict(bc_order="first"), dict(n_cycles=2), dict(n_pre=1, n_post=2),
+                                  dict(use_graph=0), dict(n_pre=3, n_post=1, n_coarse_sweeps=7)])
+def test_solve_options_match_oracle(mg, opts):
+    p, H, got, info, ref, rinfo = _solve_pair(mg, "holes64", **opts)
+    assert info["status"] == rinfo["status"]
+    assert info["cycles"] == rinfo["cycles"]
+    assert relerr(got, ref, p.mask == 1) <= TOL
+    H.close()
+
+
+def test_solve_from_guess_and_residual_norm(mg):
+    p = gen.random_small_problem((32, 32, 32), 8, active_frac=0.8, blur=1.0)
+    H = mg.Hierarchy(dev(p.mask), p.h)
+    orc = O.Oracle(p.mask, p.h)
+    rng = np.random.default_rng(0)
+    guess = rng.standard_normal(p.shape)           # inactive cells carry junk: never read
+    phi = dev(guess.copy())
+    B = dev(p.dirichlet)
+    rn = H.residual_norm(dev(p.rho), phi, B)
+    assert abs(rn - orc.residual_norm(p.rho, np.where(p.mask == 1, guess, 0.0), p.dirichlet)) <= 1e-12 * rn
+    phi, info = H.solve(dev(p.rho), phi, B, tol=1e-9)
+    ref, rinfo = orc.solve(p.rho, np.where(p.mask == 1, guess, 0.0), p.dirichlet, tol=1e-9)
+    got = host(phi)
+    act = p.mask == 1
+    assert info["cycles"] == rinfo["cycles"]
+    assert relerr(got, ref, act) <= TOL
+    assert np.array_equal(got[~act], guess[~act])   # inactive cells untouched
+    H.close()
+
+
+# ---------------------------------------------------------------- edge cases
+def test_invalid_masks_are_rejected(mg):
+    m = np.ones((16, 16, 16), np.int8)
+    with pytest.raises(mg.MGError) as e:
+        mg.Hierarchy(dev(m), 1 / 16)                 # active frame
+    assert e.value.status == mg.MG_ERR_ARG
+    m2 = gen.sphere_problem(16).mask.copy()
+    m2[8, 8, 8] = 0
+    with pytest.raises(mg.MGError) as e:
+        mg.Hierarchy(dev(m2), 1 / 16)                # value other than +-1
+    assert e.value.status == mg.MG_ERR_ARG
+    with pytest.raises(mg.MGError) as e:
+        mg.Hierarchy(dev(-np.ones((8, 8, 8), np.int8)), 1 / 8)
+    assert e.value.status == mg.MG_ERR_NO_ACTIVE
+
+
+def test_single_active_cell_and_odd_dims(mg):
+    m = -np.ones((5, 7, 9), np.int8)                 # odd dims: one level only
+    m[2, 3, 4] = 1
+    rho = np.zeros(m.shape)
+    rho[2, 3, 4] = 2.0
+    H = mg.Hierarchy(dev(m), 0.5)
+    assert H.nlevels(2) == 1
+    phi, info = H.solve(dev(rho), tol=1e-12)
+    orc = O.Oracle(m, 0.5)
+    ref, rinfo = orc.solve(rho, tol=1e-12)
+    assert info["cycles"] == rinfo["cycles"] == 1
+    assert abs(host(phi)[2, 3, 4] - ref[2, 3, 4]) <= 1e-15 * abs(ref[2, 3, 4])
+    assert ref[2, 3, 4] == pytest.approx(2.0 * 0.25 / -12.0)   # 12 phi/h^2 = -rho: exact
+    H.close()
+
+
+def test_zero_rhs_returns_at_once(mg):
+    p = gen.sphere_problem(16)
+    H = mg.Hierarchy(dev(p.mask), p.h)
+    phi, info = H.solve(torch.zeros(p.shape, dtype=torch.float64, device="cuda"), tol=1e-10)
+    assert info["status"] == 0 and info["cycles"] == 0
+    assert not host(phi).any()
+    H.close()
+
+
+def test_max_cycles_status(mg):
+    p = gen.holes_problem(n=64, seed=2)
+    H = mg.Hierarchy(dev(p.mask), p.h, max_cycles=2)
+    phi, info = H.solve(dev(p.rho), tol=1e-12)
+    assert info["status"] == mg.MG_NOT_CONVERGED and info["cycles"] == 2
+    H.close()
+
+
+# ---------------------------------------------------------------- full size
+def test_full_size_holes256_two_cycles_and_converged_residual(mg):
+    """The 256^3 masked workload in the configuration the benchmark times:
+    two cycles element by element against the oracle, then the converged
+    GPU solution checked with the oracle's own residual."""
+    p = gen.holes_problem(n=256, seed=2)
+    _print_case("holes256", p)
+    H = mg.Hierarchy(dev(p.mask), p.h, bc_order="second", max_cycles=2)
+    orc = O.Oracle(p.mask, p.h)
+    phi, info = H.solve(dev(p.rho), tol=1e-12, check=False)
+    ref, rinfo = orc.solve(p.rho, tol=1e-12, bc_order="second", max_cycles=2)
+    act = p.mask == 1
+    assert info["cycles"] == rinfo["cycles"] == 2
+    assert relerr(host(phi), ref, act) <= TOL
+    H.close()
+    H = mg.Hierarchy(dev(p.mask), p.h)
+    phi, info = H.solve(dev(p.rho), tol=1e-10)
+    assert info["status"] == 0
+    got = host(phi)
+    rr = orc.residual_norm(p.rho, np.where(act, got, 0.0))
+    assert rr <= 1e-10 * info["r_ref"] * (1 + 1e-6)
+    H.close()
