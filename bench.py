@@ -10,7 +10,7 @@ its average launch duration with HIP events on the solver's stream, and the
 oracle (plain FP64 C, host cores) on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       [--precision fp64|mixed] [--no-cpu-baseline]
+       [--variants mixed] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -29,6 +29,26 @@ SMOOTH_BYTES_FP64 = 25.0    # per active cell per pass: x read + x write + f rea
 SMOOTH_BYTES_FP32 = 13.0
 
 
+def measured_traffic():
+    """HBM bytes per launch of the finest smoother from the committed counter
+    runs (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or
+    None when the kernel's sources changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "smoother_traffic_holes256.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as src:
+                h.update(src.read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -37,11 +57,43 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--variants", default="mixed", help="comma list of extra variants timed beside fp64: mixed")
     ap.add_argument("--smoother-launches", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2)
+    ap.add_argument("--profile-smoother", type=int, default=0, metavar="N",
+                    help="counter runs: build the 256^3 hierarchy, launch only the finest smoother N times, exit")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="counter runs: 4 plain device copies of MIB MiB (known bytes), exit")
     return ap.parse_args()
+
+
+def profile_smoother(args):
+    """Finest-level smoother launches alone, for hardware-counter runs."""
+    import torch
+
+    from paper_1104_1703_amd import gen, mg
+    p = gen.holes_problem(n=args.n, seed=args.seed)
+    H = mg.Hierarchy(torch.from_numpy(p.mask).cuda(), p.h)
+    n = args.profile_smoother + (args.profile_smoother % 2)
+    H.time_smoother(n)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "profile-smoother", "launches": n, "active_cells": H.n_active(0),
+                      "algorithmic_bytes_per_launch": SMOOTH_BYTES_FP64 * H.n_active(0)}), flush=True)
+    H.close()
+
+
+def copy_calibration(args):
+    """Plain copies of a known number of bytes (reference for FETCH_SIZE/WRITE_SIZE)."""
+    import torch
+    n = args.copy_calibration * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy-calibration", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
+                      "copies": 4}), flush=True)
 
 
 def cpu_baseline(p, gpu_cycles, cycles):
@@ -69,6 +121,10 @@ def cpu_baseline(p, gpu_cycles, cycles):
 
 def main():
     args = parse()
+    if args.profile_smoother:
+        return profile_smoother(args)
+    if args.copy_calibration:
+        return copy_calibration(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
               "(domain decomposition is described, not implemented).", file=sys.stderr)
@@ -83,25 +139,26 @@ def main():
     mask = torch.from_numpy(p.mask).to(dev)
     rho = torch.from_numpy(p.rho).to(dev)
     phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
-    H = mg.Hierarchy(mask, p.h, precision=args.precision)
+
+    def time_solves(H):
+        def step():
+            phi.zero_()
+            return H.solve(rho, phi, None, tol=args.tol)[1]
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            infos.append(step())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        last = infos[-1] if infos else step()
+        return wall / max(1, args.steps) * 1e3, float(np.median([i["ms"] for i in infos])) if infos else None, last
+
+    H = mg.Hierarchy(mask, p.h, precision="fp64")
     n_act = H.n_active(0)
-
-    def step():
-        phi.zero_()
-        return H.solve(rho, phi, None, tol=args.tol)[1]
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos.append(step())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_wall = wall / max(1, args.steps) * 1e3
-    ms_events = float(np.median([i["ms"] for i in infos])) if infos else float("nan")
-    last = infos[-1] if infos else step()
+    ms_wall, ms_events, last = time_solves(H)
 
     # dominant kernel: finest-level smoother, HIP events on the solver's stream
     launches = args.smoother_launches - (args.smoother_launches % 2)
@@ -115,7 +172,20 @@ def main():
     smooth_ms = e0.elapsed_time(e1) / launches
     bytes_per = SMOOTH_BYTES_FP64 * n_act
     achieved = bytes_per / (smooth_ms * 1e-3) / 1e9
+    phi64 = phi.clone()
+    H.close()
 
+    variants = {}
+    for v in [x for x in args.variants.split(",") if x]:
+        Hv = mg.Hierarchy(mask, p.h, precision=v)
+        v_wall, v_events, v_last = time_solves(Hv)
+        diff = float((phi - phi64).abs().max() / phi64.abs().max())
+        variants[v] = {"ms": round(v_wall, 4), "speedup_vs_fp64": round(ms_wall / v_wall, 3),
+                       "cycles": v_last["cycles"], "final_rel_residual": v_last["r_final"] / v_last["r_ref"],
+                       "max_rel_diff_vs_fp64_solution": diff}
+        Hv.close()
+
+    traffic = measured_traffic() if args.n == 256 and args.seed == 2 else None
     out = {
         "metric": "time-to-1e-10 residual & smoother HBM GB/s at 256^3 masked; learned/mixed vs FP64",
         "value": round(ms_wall, 4),
@@ -127,19 +197,20 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32-in-f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": f"holes{args.n}: {args.n}^3 unit cube, outer sphere R=0.45 minus 64 seeded spheres "
                         f"(seed {args.seed}), rho = 32 Gaussians, Dirichlet 0, zero guess, V(2,2), tol {args.tol:g}",
             "active_cells": n_act,
-            "precision": args.precision,
+            "precision": "fp64",
             "cycles": last["cycles"],
             "order_used": last["order_used"],
             "switched_at": last["switched_at"],
             "final_rel_residual": last["r_final"] / last["r_ref"],
             "ms_events_median": round(ms_events, 4),
         },
+        "variants": variants,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_rbgs<double,true> (finest-level red-black pass)",
@@ -147,12 +218,13 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_gbs": round(traffic / (smooth_ms * 1e-3) / 1e9, 1) if traffic else None,
             "avg_launch_us": round(smooth_ms * 1e3, 3),
             "algorithmic_bytes_per_launch": bytes_per,
         },
     }
-    H.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, last["cycles"], args.cpu_cycles)
     print(json.dumps(out), flush=True)

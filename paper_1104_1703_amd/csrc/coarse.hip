@@ -15,12 +15,13 @@ namespace mg {
 
 namespace {
 
-constexpr int NT = 1024;
+constexpr int NT = 256;  // the levels are tiny: fewer waves, cheaper barriers
 
 template <typename T>
 struct SmallLevels {
     int n;                 // number of levels held (ls..last)
     int nx[MAXS], ny[MAXS], nz[MAXS];
+    unsigned long long mx[MAXS], mxy[MAXS];  // division magics, see qdiv
     T h2[MAXS];            // h^2 per level
     T ih2[MAXS];           // 1/h^2 per level
     const T *d[MAXS];      // diagonal per level (global), 0 off the domain
@@ -35,8 +36,23 @@ template <typename T>
 struct Lv {
     T *x, *f, *d;
     int nx, ny, nz, n;
+    unsigned long long mx, mxy;  // ceil(2^32 / nx), ceil(2^32 / (nx*ny))
     T h2, ih2;
 };
+
+// Exact quotient e / d for e * d < 2^32, with m = ceil(2^32 / d): the error
+// of e * m / 2^32 is below e / 2^32 < 1/d, too small to reach the next integer.
+__device__ __forceinline__ int qdiv(int e, unsigned long long m) {
+    return (int)(((unsigned long long)(unsigned)e * m) >> 32);
+}
+
+template <typename T>
+__device__ __forceinline__ void cell_ijk(const Lv<T> &L, int e, int &i, int &j, int &k) {
+    k = qdiv(e, L.mxy);
+    const int r = e - k * L.nx * L.ny;
+    j = qdiv(r, L.mx);
+    i = r - j * L.nx;
+}
 
 template <typename T>
 __device__ __forceinline__ T nb_sum(const T *x, int i, int j, int k, int nx, int ny, int nz) {
@@ -55,7 +71,8 @@ __device__ void smooth(const Lv<T> &L, int passes) {
     for (int p = 0; p < passes; p++)
         for (int col = 0; col < 2; col++) {
             for (int e = threadIdx.x; e < L.n; e += NT) {
-                const int i = e % L.nx, j = (e / L.nx) % L.ny, k = e / (L.nx * L.ny);
+                int i, j, k;
+                cell_ijk(L, e, i, j, k);
                 if (((i + j + k) & 1) != col) continue;
                 const T d = L.d[e];
                 if (d == T(0)) continue;
@@ -69,7 +86,8 @@ __device__ void smooth(const Lv<T> &L, int passes) {
 template <typename T>
 __device__ void restrict_to(const Lv<T> &L, const Lv<T> &C) {
     for (int E = threadIdx.x; E < C.n; E += NT) {
-        const int I = E % C.nx, J = (E / C.nx) % C.ny, K = E / (C.nx * C.ny);
+        int I, J, K;
+        cell_ijk(C, E, I, J, K);
         T s = T(0);
         if (C.d[E] != T(0)) {
 #pragma unroll
@@ -93,7 +111,8 @@ __device__ void prolong_from(const Lv<T> &L, const Lv<T> &C) {
     const T w[2] = {T(0.75), T(0.25)};
     for (int e = threadIdx.x; e < L.n; e += NT) {
         if (L.d[e] == T(0)) continue;
-        const int i = e % L.nx, j = (e / L.nx) % L.ny, k = e / (L.nx * L.ny);
+        int i, j, k;
+        cell_ijk(L, e, i, j, k);
         const int I = i >> 1, J = j >> 1, K = k >> 1;
         const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
         T s = T(0);
@@ -120,6 +139,7 @@ __global__ __launch_bounds__(NT) void k_coarse(SmallLevels<T> S) {
     T *sm = reinterpret_cast<T *>(smem_raw);
     // level descriptors live in LDS (dynamic indexing without private memory)
     __shared__ int s_nx[MAXS], s_ny[MAXS], s_nz[MAXS], s_off[MAXS];
+    __shared__ unsigned long long s_mx[MAXS], s_mxy[MAXS];
     __shared__ T s_h2[MAXS], s_ih2[MAXS];
     if (threadIdx.x < (unsigned)S.n) {
         const int l = threadIdx.x;
@@ -127,6 +147,8 @@ __global__ __launch_bounds__(NT) void k_coarse(SmallLevels<T> S) {
         s_ny[l] = S.ny[l];
         s_nz[l] = S.nz[l];
         s_off[l] = S.off[l];
+        s_mx[l] = S.mx[l];
+        s_mxy[l] = S.mxy[l];
         s_h2[l] = S.h2[l];
         s_ih2[l] = S.ih2[l];
     }
@@ -137,6 +159,8 @@ __global__ __launch_bounds__(NT) void k_coarse(SmallLevels<T> S) {
         v.ny = s_ny[l];
         v.nz = s_nz[l];
         v.n = v.nx * v.ny * v.nz;
+        v.mx = s_mx[l];
+        v.mxy = s_mxy[l];
         v.x = sm + s_off[l];
         v.f = v.x + v.n;
         v.d = v.f + v.n;
@@ -201,6 +225,8 @@ void launch_impl(const mg_hierarchy *H, int order, int ls, bool zero_start, cons
         S.nx[q] = L.nx;
         S.ny[q] = L.ny;
         S.nz[q] = L.nz;
+        S.mx[q] = (0x100000000ull + (unsigned)L.nx - 1) / (unsigned)L.nx;
+        S.mxy[q] = (0x100000000ull + (unsigned)(L.nx * L.ny) - 1) / (unsigned)(L.nx * L.ny);
         S.h2[q] = (T)(L.h * L.h);
         S.ih2[q] = (T)(1.0 / (L.h * L.h));
         S.d[q] = f32 ? (const T *)L.od[order].d32 : (const T *)L.od[order].d;

@@ -32,6 +32,7 @@ constexpr int QX = BX + 2, QY = BY + 2, QN = QX * QY;  // f / diag plane with 1-
 constexpr int NT = 256;
 constexpr int XR = (PN + NT - 1) / NT;  // x elements per thread per plane
 constexpr int QR = (QN + NT - 1) / NT;  // f elements per thread per plane
+constexpr int PF = 4;                   // planes of global loads in flight
 
 // Work items are dealt to the 8 XCDs round-robin by block id; give each XCD a
 // contiguous range of work items so that halo re-reads hit its own L2.
@@ -48,14 +49,17 @@ struct PlaneRegs {
     unsigned ok;  // validity bits: x elements in bits 0..XR-1, f/d elements above
 };
 
-template <typename T, bool FINE>
+template <typename T, bool FINE, int SEGZ>
 __global__ __launch_bounds__(NT) void k_rbgs(const T *__restrict__ xin, T *__restrict__ xout,
                                               const T *__restrict__ f, const uint8_t *__restrict__ code,
                                               const T *__restrict__ dco, int nx, int ny, int nz, T h2,
                                               const Seg *__restrict__ segs, int nsegs) {
+    // f and the diagonal are needed for planes k .. k+2 at step k: 3-slot ring.
+    // The finest level keeps its 1-byte neighbour code instead of a diagonal.
+    using DT = typename std::conditional<FINE, uint8_t, T>::type;
     __shared__ T sx[4][PN];
-    __shared__ T sf[4][QN];
-    __shared__ T sd[4][QN];
+    __shared__ T sf[3][QN];
+    __shared__ DT sd[3][QN];
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= nsegs) return;
     const Seg sg = segs[item];
@@ -103,10 +107,11 @@ __global__ __launch_bounds__(NT) void k_rbgs(const T *__restrict__ xin, T *__res
         }
     };
     // registers -> LDS ring slot of plane k (zeros where invalid)
+    auto slot3 = [](int k) { return (k + 3) % 3; };  // k >= -2
     auto commit = [&](const PlaneRegs<T, FINE> &r, int k) {
         T *dx = sx[k & 3];
-        T *df = sf[k & 3];
-        T *dd = sd[k & 3];
+        T *df = sf[slot3(k)];
+        DT *dd = sd[slot3(k)];
 #pragma unroll
         for (int q = 0; q < XR; q++) {
             const int e = tid + q * NT;
@@ -117,11 +122,9 @@ __global__ __launch_bounds__(NT) void k_rbgs(const T *__restrict__ xin, T *__res
             const int e = tid + q * NT;
             if (e < QN) {
                 const bool ok = (r.ok >> (XR + q)) & 1u;
-                T dv;
-                if constexpr (FINE) dv = r.d[q] == CODE_OFF ? T(0) : T(12 - (int)r.d[q]);
-                else dv = r.d[q];
                 df[e] = ok ? r.f[q] : T(0);
-                dd[e] = ok ? dv : T(0);
+                if constexpr (FINE) dd[e] = ok ? r.d[q] : CODE_OFF;
+                else dd[e] = ok ? r.d[q] : T(0);
             }
         }
     };
@@ -132,16 +135,23 @@ __global__ __launch_bounds__(NT) void k_rbgs(const T *__restrict__ xin, T *__res
         T *c = sx[k & 3];
         const T *dn = sx[(k - 1) & 3];
         const T *up = sx[(k + 1) & 3];
-        const T *fq = sf[k & 3];
-        const T *dq = sd[k & 3];
+        const T *fq = sf[slot3(k)];
+        const DT *dq = sd[slot3(k)];
         const int half = (PX - 2 * lo) >> 1;
         const int rows = PY - 2 * lo;
         for (int e = tid; e < half * rows; e += NT) {
             const int v = lo + e / half;
             const int u = lo + ((col + gy0 + v + k + gx0 + lo) & 1) + 2 * (e % half);
             const int qq = (v - 1) * QX + (u - 1);
-            const T d = dq[qq];
-            if (d == T(0)) continue;  // inactive or outside the box
+            T d;
+            if constexpr (FINE) {
+                const uint8_t cd = dq[qq];
+                if (cd == CODE_OFF) continue;  // inactive or outside the box
+                d = T(12 - (int)cd);
+            } else {
+                d = dq[qq];
+                if (d == T(0)) continue;  // inactive or outside the box
+            }
             const int q = v * PX + u;
             const T s = (c[q - 1] + c[q + 1]) + (c[q - PX] + c[q + PX]) + (dn[q] + up[q]);
             c[q] = (s - h2 * fq[qq]) / d;
@@ -157,39 +167,32 @@ __global__ __launch_bounds__(NT) void k_rbgs(const T *__restrict__ xin, T *__res
         }
     };
 
-    PlaneRegs<T, FINE> ra, rb;
-    fetch(ra, z0 - 2);
-    fetch(rb, z0 - 1);
-    commit(ra, z0 - 2);
-    commit(rb, z0 - 1);
-    fetch(ra, z0);
-    fetch(rb, z0 + 1);
-    commit(ra, z0);
-    commit(rb, z0 + 1);
-    fetch(ra, z0 + 2);
-    fetch(rb, z0 + 3);
-    __syncthreads();
-    relax(z0 - 1, 0, 1);
-    relax(z0, 0, 1);
-    __syncthreads();
-    for (int k = z0; k < z1; k += 2) {
-        commit(ra, k + 2);
-        fetch(ra, k + 4);
+    // Fully unrolled march over at most SEGZ planes (shorter items skip the
+    // stores past z1): planes z0-2 .. z0+SEGZ+1 are committed one per step,
+    // each refilled register set fetching the plane PF steps ahead, so PF
+    // planes of loads stay in flight and every wait count is exact.
+    constexpr int NSTEP = SEGZ + 4;
+    PlaneRegs<T, FINE> r[PF];
+#pragma unroll
+    for (int q = 0; q < PF; q++) fetch(r[q], z0 - 2 + q);
+#pragma unroll
+    for (int st = 0; st < NSTEP; st++) {
+        const int pk = z0 - 2 + st;  // plane committed in this step
+        commit(r[st % PF], pk);
+        if (st + PF < NSTEP) fetch(r[st % PF], pk + PF);
         __syncthreads();
-        relax(k + 1, 0, 1);
-        __syncthreads();
-        relax(k, 1, 2);
-        __syncthreads();
-        store(k);
-        if (k + 1 >= z1) break;
-        commit(rb, k + 3);
-        fetch(rb, k + 5);
-        __syncthreads();
-        relax(k + 2, 0, 1);
-        __syncthreads();
-        relax(k + 1, 1, 2);
-        __syncthreads();
-        store(k + 1);
+        if (st == 3) {
+            relax(z0 - 1, 0, 1);
+            relax(z0, 0, 1);
+            __syncthreads();
+        } else if (st > 3) {
+            const int k = pk - 2;
+            relax(k + 1, 0, 1);
+            __syncthreads();
+            relax(k, 1, 2);
+            __syncthreads();
+            if (k < z1) store(k);
+        }
     }
 }
 
@@ -202,10 +205,10 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
     if (od.nsegs == 0) return;
     const double h2 = L.h * L.h;
     if (level == 0)
-        k_rbgs<double, true><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
+        k_rbgs<double, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
                                                              od.segs, od.nsegs);
     else
-        k_rbgs<double, false><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz, h2,
+        k_rbgs<double, false, SEG_TILES_COARSE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz, h2,
                                                               od.segs, od.nsegs);
 }
 
@@ -214,10 +217,10 @@ void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *
     if (od.nsegs == 0) return;
     const float h2 = (float)(L.h * L.h);
     if (level == 0)
-        k_rbgs<float, true><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
+        k_rbgs<float, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
                                                             od.segs, od.nsegs);
     else
-        k_rbgs<float, false><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d32, L.nx, L.ny, L.nz, h2,
+        k_rbgs<float, false, SEG_TILES_COARSE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d32, L.nx, L.ny, L.nz, h2,
                                                              od.segs, od.nsegs);
 }
 
