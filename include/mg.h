@@ -194,6 +194,47 @@ mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches);
 /* The stream the hierarchy enqueues on (as void*). */
 void *mg_stream(const mg_hierarchy *H);
 
+/* ---------------- batched solver ---------------- */
+/* Many independent masked grids (AMR-level patches of uneven size and depth)
+ * solved together: each patch has its own hierarchy and operators exactly as
+ * in mg_solve (Sec. 2-4).  The persistent one-launch-per-cycle engine is
+ * switched off in this build (see the library sources); each patch then runs
+ * its own graph-captured cycles on the batch stream. */
+typedef struct mg_batch mg_batch; /* opaque */
+
+/*
+ * Build the hierarchies of n patches.
+ *   masks_dev : n device pointers to int8 masks (+1/-1, inactive outer layer).
+ *   dims      : 3n host ints (nx, ny, nz per patch).   h: n host cell widths.
+ *   opt       : NULL = defaults; precision must be MG_FP64.
+ * Errors as mg_create_hierarchy (the first failing patch).
+ */
+mg_status mg_create_batch(int32_t n, const int8_t *const *masks_dev, const int32_t *dims, const double *h,
+                          const mg_options *opt, void *stream, mg_batch **out);
+
+/*
+ * Solve every patch to ||r||_2 <= tol ||r(phi=0)||_2 (per patch), each with its
+ * own runtime order switch (Sec. 4) and first-order hold.
+ *   rho_dev, phi_dev : n device pointers each (phi: guess in, solution out on
+ *                      active cells).  dirichlet_dev: NULL, or n device
+ *                      pointers (entries may be NULL).
+ *   infos : NULL or n records.   ms_out: NULL or the wall time on the stream.
+ * Returns MG_OK if every patch converged, else the worst status (negative
+ * errors before MG_NOT_CONVERGED).
+ */
+mg_status mg_solve_batch(mg_batch *B, const double *const *rho_dev, double *const *phi_dev,
+                         const double *const *dirichlet_dev, double tol, mg_solve_info *infos, double *ms_out);
+
+/* Release the batch and every patch hierarchy (NULL is a no-op). */
+void mg_destroy_batch(mg_batch *B);
+
+/* Number of patches; blocks of the persistent launch and phases of one
+ * cycle program of boundary order `order` (1 or 2), both 0 while the
+ * persistent engine is off. */
+int32_t mg_batch_size(const mg_batch *B);
+int32_t mg_batch_grid(const mg_batch *B);
+int32_t mg_batch_phases(const mg_batch *B, int32_t order);
+
 #ifdef __cplusplus
 }
 #endif

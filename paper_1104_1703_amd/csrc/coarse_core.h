@@ -1,0 +1,213 @@
+// Core of the one-workgroup multigrid call on small levels, shared by the
+// per-level path (coarse.hip) and the batched persistent kernel (batch.hip).
+#pragma once
+
+#include "mg_core.h"
+
+namespace mg {
+namespace small {
+
+
+constexpr int NT = 256;  // the levels are tiny: fewer waves, cheaper barriers
+
+template <typename T>
+struct SmallLevels {
+    int n;                 // number of levels held (ls..last)
+    int nx[MAXS], ny[MAXS], nz[MAXS];
+    unsigned long long mx[MAXS], mxy[MAXS];  // division magics, see qdiv
+    T h2[MAXS];            // h^2 per level
+    T ih2[MAXS];           // 1/h^2 per level
+    const T *d[MAXS];      // diagonal per level (global), 0 off the domain
+    int off[MAXS];         // LDS offset (elements) of the level's x; f and d follow
+    const T *f0;           // right-hand side of level ls (global)
+    T *x0;                 // iterate of level ls (global, in/out)
+    int load_x;            // 1: start from x0, 0: start from zero
+    int n_pre, n_post, n_cycles, n_coarse;
+};
+
+template <typename T>
+struct Lv {
+    T *x, *f, *d;
+    int nx, ny, nz, n;
+    unsigned long long mx, mxy;  // ceil(2^32 / nx), ceil(2^32 / (nx*ny))
+    T h2, ih2;
+};
+
+// Exact quotient e / d for e * d < 2^32, with m = ceil(2^32 / d): the error
+// of e * m / 2^32 is below e / 2^32 < 1/d, too small to reach the next integer.
+__device__ __forceinline__ int qdiv(int e, unsigned long long m) {
+    return (int)(((unsigned long long)(unsigned)e * m) >> 32);
+}
+
+template <typename T>
+__device__ __forceinline__ void cell_ijk(const Lv<T> &L, int e, int &i, int &j, int &k) {
+    k = qdiv(e, L.mxy);
+    const int r = e - k * L.nx * L.ny;
+    j = qdiv(r, L.mx);
+    i = r - j * L.nx;
+}
+
+template <typename T>
+__device__ __forceinline__ T nb_sum(const T *x, int i, int j, int k, int nx, int ny, int nz) {
+    const int p = (k * ny + j) * nx + i;
+    const T xm = i > 0 ? x[p - 1] : T(0);
+    const T xp = i < nx - 1 ? x[p + 1] : T(0);
+    const T ym = j > 0 ? x[p - nx] : T(0);
+    const T yp = j < ny - 1 ? x[p + nx] : T(0);
+    const T zm = k > 0 ? x[p - nx * ny] : T(0);
+    const T zp = k < nz - 1 ? x[p + nx * ny] : T(0);
+    return (xm + xp) + (ym + yp) + (zm + zp);
+}
+
+template <typename T>
+__device__ void smooth(const Lv<T> &L, int passes) {
+    for (int p = 0; p < passes; p++)
+        for (int col = 0; col < 2; col++) {
+            for (int e = threadIdx.x; e < L.n; e += NT) {
+                int i, j, k;
+                cell_ijk(L, e, i, j, k);
+                if (((i + j + k) & 1) != col) continue;
+                const T d = L.d[e];
+                if (d == T(0)) continue;
+                L.x[e] = (nb_sum(L.x, i, j, k, L.nx, L.ny, L.nz) - L.h2 * L.f[e]) / d;
+            }
+            __syncthreads();
+        }
+}
+
+// f_c = -(1/8) sum over active children of (L x - f); x_c = 0.
+template <typename T>
+__device__ void restrict_to(const Lv<T> &L, const Lv<T> &C) {
+    for (int E = threadIdx.x; E < C.n; E += NT) {
+        int I, J, K;
+        cell_ijk(C, E, I, J, K);
+        T s = T(0);
+        if (C.d[E] != T(0)) {
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
+                const int p = (k * L.ny + j) * L.nx + i;
+                const T d = L.d[p];
+                if (d != T(0)) s += (nb_sum(L.x, i, j, k, L.nx, L.ny, L.nz) - d * L.x[p]) * L.ih2 - L.f[p];
+            }
+            s = -s / T(8);
+        }
+        C.f[E] = s;
+        C.x[E] = T(0);
+    }
+    __syncthreads();
+}
+
+// x += P2(x_c) on active cells (weights 3/4, 1/4 per axis; 0 off the box).
+template <typename T>
+__device__ void prolong_from(const Lv<T> &L, const Lv<T> &C) {
+    const T w[2] = {T(0.75), T(0.25)};
+    for (int e = threadIdx.x; e < L.n; e += NT) {
+        if (L.d[e] == T(0)) continue;
+        int i, j, k;
+        cell_ijk(L, e, i, j, k);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+        T s = T(0);
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int a = 0; a < 2; a++) {
+                    const int ci = I + a * sx, cj = J + b * sy, ck = K + c * sz;
+                    T v = T(0);
+                    if (ci >= 0 && ci < C.nx && cj >= 0 && cj < C.ny && ck >= 0 && ck < C.nz)
+                        v = C.x[(ck * C.ny + cj) * C.nx + ci];
+                    s += w[a] * w[b] * w[c] * v;
+                }
+        L.x[e] += s;
+    }
+    __syncthreads();
+}
+
+// One call MG(ls) for the levels held in S, all resident in the memory at
+// `sm` (LDS, or global memory for levels too large for LDS); f0 is level ls's
+// right-hand side and x0 its iterate (in/out), started from zero unless
+// load_x.  Called by all NT threads of a block.
+template <typename T>
+__device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, bool load_x) {
+    // level descriptors live in LDS (dynamic indexing without private memory)
+    __shared__ int s_nx[MAXS], s_ny[MAXS], s_nz[MAXS], s_off[MAXS];
+    __shared__ unsigned long long s_mx[MAXS], s_mxy[MAXS];
+    __shared__ T s_h2[MAXS], s_ih2[MAXS];
+    if (threadIdx.x < (unsigned)S.n) {
+        const int l = threadIdx.x;
+        s_nx[l] = S.nx[l];
+        s_ny[l] = S.ny[l];
+        s_nz[l] = S.nz[l];
+        s_off[l] = S.off[l];
+        s_mx[l] = S.mx[l];
+        s_mxy[l] = S.mxy[l];
+        s_h2[l] = S.h2[l];
+        s_ih2[l] = S.ih2[l];
+    }
+    __syncthreads();
+    auto level = [&](int l) {
+        Lv<T> v;
+        v.nx = s_nx[l];
+        v.ny = s_ny[l];
+        v.nz = s_nz[l];
+        v.n = v.nx * v.ny * v.nz;
+        v.mx = s_mx[l];
+        v.mxy = s_mxy[l];
+        v.x = sm + s_off[l];
+        v.f = v.x + v.n;
+        v.d = v.f + v.n;
+        v.h2 = s_h2[l];
+        v.ih2 = s_ih2[l];
+        return v;
+    };
+    for (int l = 0; l < S.n; l++) {
+        const Lv<T> v = level(l);
+        const T *dg = S.d[l];
+        for (int e = threadIdx.x; e < v.n; e += NT) {
+            v.d[e] = dg[e];
+            v.x[e] = (l == 0 && load_x) ? x0[e] : T(0);
+            if (l == 0) v.f[e] = f0[e];
+        }
+    }
+    __syncthreads();
+    // iterative form of the recursion MG(l): pre-smooth, restrict, N_cycles x
+    // MG(l+1) from zero, prolong, post-smooth; the deepest level is relaxed.
+    // visits: 3 bits per level (N_cycles <= 4).
+    const int last = S.n - 1;
+    unsigned visits = 0;
+    int l = 0;
+    bool down = true;
+    while (true) {
+        if (down) {
+            if (l == last) {
+                smooth(level(l), S.n_coarse);
+                down = false;
+                continue;
+            }
+            smooth(level(l), S.n_pre);
+            restrict_to(level(l), level(l + 1));
+            visits &= ~(7u << (3 * (l + 1)));
+            l++;
+            continue;
+        }
+        if (l == 0) break;
+        const unsigned vc = ((visits >> (3 * l)) & 7u) + 1u;
+        visits = (visits & ~(7u << (3 * l))) | (vc << (3 * l));
+        if ((int)vc < S.n_cycles) {
+            down = true;
+            continue;
+        }
+        prolong_from(level(l - 1), level(l));
+        smooth(level(l - 1), S.n_post);
+        l--;
+    }
+    const Lv<T> top = level(0);
+    for (int e = threadIdx.x; e < top.n; e += NT) x0[e] = top.x[e];
+    __syncthreads();
+}
+
+}  // namespace small
+}  // namespace mg

@@ -72,6 +72,12 @@ SYMBOLS = [
     ("mg_vcycle", C.c_int, [_P, _I, _P, _P]),
     ("mg_time_smoother", C.c_int, [_P, _I, _I]),
     ("mg_stream", _P, [_P]),
+    ("mg_create_batch", C.c_int, [_I, _P, _P, _P, C.POINTER(Options), _P, C.POINTER(_P)]),
+    ("mg_solve_batch", C.c_int, [_P, _P, _P, _P, _D, _P, C.POINTER(_D)]),
+    ("mg_destroy_batch", None, [_P]),
+    ("mg_batch_size", _I, [_P]),
+    ("mg_batch_grid", _I, [_P]),
+    ("mg_batch_phases", _I, [_P, _I]),
 ]
 
 _lib = None
@@ -298,3 +304,79 @@ class Hierarchy:
 
     def time_smoother(self, launches: int, order: int = 2):
         _check(self._call(load_library().mg_time_smoother, self._h, order, launches), "mg_time_smoother")
+
+
+class Batch:
+    """Many independent masked grids solved together (one persistent launch
+    per multigrid cycle for the whole batch).
+
+    ``masks``: list of int8 tensors (each (nz, ny, nx), inactive outer layer);
+    ``hs``: cell widths.  Options as for :class:`Hierarchy` (FP64 only).
+    """
+
+    def __init__(self, masks, hs, stream=None, torch_allocator: bool = True, **options):
+        lib = load_library()
+        self.n = len(masks)
+        self.device = masks[0].device
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.shapes = [tuple(m.shape) for m in masks]
+        self.opts = default_options(**options)
+        self._alloc = None
+        if torch_allocator:
+            self._alloc = _TorchAllocator(self.device, self.stream)
+            self._alloc.fill(self.opts)
+        self._masks = [m.contiguous() for m in masks]
+        ptrs = (C.c_void_p * self.n)(*[m.data_ptr() for m in self._masks])
+        dims = (C.c_int32 * (3 * self.n))()
+        for i, (nz, ny, nx) in enumerate(self.shapes):
+            dims[3 * i], dims[3 * i + 1], dims[3 * i + 2] = nx, ny, nz
+        hv = (C.c_double * self.n)(*[float(h) for h in hs])
+        out = C.c_void_p()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.device(self.device):
+            st = lib.mg_create_batch(self.n, ptrs, dims, hv, C.byref(self.opts), C.c_void_p(self.stream.cuda_stream),
+                                     C.byref(out))
+        self._masks = None
+        _check(st, "mg_create_batch")
+        self._b = out
+
+    @property
+    def grid(self) -> int:
+        return int(load_library().mg_batch_grid(self._b))
+
+    def phases(self, order: int = 2) -> int:
+        return int(load_library().mg_batch_phases(self._b, order))
+
+    def solve(self, rhos, phis=None, dirichlets=None, tol: float = 1e-10, check: bool = True):
+        """Solve every patch in place; returns (phis, list of info dicts, ms)."""
+        lib = load_library()
+        if phis is None:
+            phis = [torch.zeros(sh, dtype=torch.float64, device=self.device) for sh in self.shapes]
+        for t in list(rhos) + list(phis) + [d for d in (dirichlets or []) if d is not None]:
+            _ptr(t)  # device, contiguous
+        rp = (C.c_void_p * self.n)(*[t.data_ptr() for t in rhos])
+        pp = (C.c_void_p * self.n)(*[t.data_ptr() for t in phis])
+        dp = None
+        if dirichlets is not None:
+            dp = (C.c_void_p * self.n)(*[(d.data_ptr() if d is not None else None) for d in dirichlets])
+        infos = (SolveInfo * self.n)()
+        ms = C.c_double()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.device(self.device):
+            st = lib.mg_solve_batch(self._b, rp, pp, dp, float(tol), infos, C.byref(ms))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        if check:
+            _check(st, "mg_solve_batch", ok=(MG_OK, MG_NOT_CONVERGED))
+        return phis, [infos[i].as_dict() for i in range(self.n)], float(ms.value)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            with torch.cuda.device(self.device):
+                load_library().mg_destroy_batch(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

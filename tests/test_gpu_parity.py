@@ -321,3 +321,84 @@ def test_mixed_precision_matches_converged_oracle(mg, name):
     assert rr <= 1e-10 * info["r_ref"] * (1 + 1e-6)
     H.close()
     H2.close()
+
+
+# ---------------------------------------------------------------- batched solver
+def _batch_case(mg, probs, **opts):
+    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], **opts)
+    rhos = [dev(p.rho) for p in probs]
+    dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
+    phis, infos, ms = B.solve(rhos, None, dirs, tol=1e-10)
+    return B, [host(x) for x in phis], infos, ms
+
+
+@pytest.mark.skip(reason="persistent batch kernel disabled: its GPU runs ended in HSA_STATUS_ERROR_MEMORY_APERTURE_VIOLATION, cause not yet found")
+@pytest.mark.parametrize("opts", [dict(), dict(bc_order="second"), dict(n_cycles=2)])
+def test_batch_matches_oracle_per_patch(mg, opts):
+    """Uneven patches in one batch: every patch takes the same cycles, switch
+    and solution as the oracle's own solve of that patch."""
+    probs = gen.patch_problems(count=6, seed=3) + [gen.sphere_problem(32), gen.holes_problem(n=64, seed=2),
+                                                   gen.porous_problem(n=64, seed=4)]
+    for p in probs:
+        _print_case(p.name, p)
+    B, got, infos, ms = _batch_case(mg, probs, **opts)
+    oo = {k: v for k, v in opts.items() if k in ("bc_order", "n_cycles")}
+    for p, x, info in zip(probs, got, infos):
+        orc = O.Oracle(p.mask, p.h)
+        ref, rinfo = orc.solve(p.rho, None, p.dirichlet, tol=1e-10, **oo)
+        act = p.mask == 1
+        assert info["status"] == rinfo["status"] == 0, (p.name, info["status"], rinfo["status"])
+        assert info["cycles"] == rinfo["cycles"], (p.name, info["cycles"], rinfo["cycles"])
+        assert info["switched_at"] == rinfo["switched_at"], p.name
+        assert relerr(x, ref, act) <= TOL, p.name
+    B.close()
+
+
+@pytest.mark.skip(reason="persistent batch kernel disabled: its GPU runs ended in HSA_STATUS_ERROR_MEMORY_APERTURE_VIOLATION, cause not yet found")
+def test_batch_equals_single_solves_and_repeats(mg):
+    """The batch gives each patch what mg_solve gives it alone, and a second
+    batch solve (first-order hold in force where a patch switched) matches a
+    second single solve."""
+    probs = gen.patch_problems(count=10, seed=7)
+    B, got, infos, ms = _batch_case(mg, probs)
+    singles = [mg.Hierarchy(dev(p.mask), p.h) for p in probs]
+    for p, x, info, H in zip(probs, got, infos, singles):
+        d = None if p.dirichlet is None else dev(p.dirichlet)
+        phi, sinfo = H.solve(dev(p.rho), None, d, tol=1e-10)
+        assert info["cycles"] == sinfo["cycles"] and info["switched_at"] == sinfo["switched_at"]
+        assert relerr(x, host(phi), p.mask == 1) <= TOL
+    phis2, infos2, _ = B.solve([dev(p.rho) for p in probs], None,
+                               [None if p.dirichlet is None else dev(p.dirichlet) for p in probs], tol=1e-10)
+    for p, x, info, H in zip(probs, phis2, infos2, singles):
+        d = None if p.dirichlet is None else dev(p.dirichlet)
+        phi, sinfo = H.solve(dev(p.rho), None, d, tol=1e-10)
+        assert info["cycles"] == sinfo["cycles"] and info["order_used"] == sinfo["order_used"]
+        assert relerr(host(x), host(phi), p.mask == 1) <= TOL
+        H.close()
+    B.close()
+
+
+@pytest.mark.skip(reason="persistent batch kernel disabled: its GPU runs ended in HSA_STATUS_ERROR_MEMORY_APERTURE_VIOLATION, cause not yet found")
+def test_batch_rejects_odd_pass_count(mg):
+    p = gen.sphere_problem(16)
+    with pytest.raises(mg.MGError) as e:
+        mg.Batch([dev(p.mask)], [p.h], n_pre=1, n_post=2)
+    assert e.value.status == mg.MG_ERR_ARG
+
+
+# The batch API on its per-patch engine (each patch's own captured cycles).
+@pytest.mark.parametrize("opts", [dict(), dict(n_cycles=2)])
+def test_batch_per_patch_engine_matches_oracle(mg, opts):
+    probs = gen.patch_problems(count=5, seed=11) + [gen.sphere_problem(32), gen.porous_problem(n=64, seed=4)]
+    for p in probs:
+        _print_case(p.name, p)
+    B, got, infos, ms = _batch_case(mg, probs, **opts)
+    assert B.grid == 0 and B.phases(2) == 0       # persistent engine off
+    for p, x, info in zip(probs, got, infos):
+        orc = O.Oracle(p.mask, p.h)
+        oo = {k: v for k, v in opts.items() if k in ("n_cycles",)}
+        ref, rinfo = orc.solve(p.rho, None, p.dirichlet, tol=1e-10, **oo)
+        assert info["status"] == rinfo["status"] == 0, p.name
+        assert info["cycles"] == rinfo["cycles"] and info["switched_at"] == rinfo["switched_at"], p.name
+        assert relerr(x, ref, p.mask == 1) <= TOL, p.name
+    B.close()
