@@ -235,6 +235,137 @@ int32_t mg_batch_size(const mg_batch *B);
 int32_t mg_batch_grid(const mg_batch *B);
 int32_t mg_batch_phases(const mg_batch *B, int32_t order);
 
+/* ---------------- learned first guess (U-Net) ----------------
+ * The iteration of Sec. 2 converges from any first guess, and the paper's
+ * convergence is insensitive to it (Sec. 2, Sec. 6); these calls produce a
+ * guess phi0 from (rho, mask, B) with a 3D U-Net, then mg_solve takes phi0 as
+ * its initial phi.  The stopping target (tol times the zero-guess residual
+ * norm) is the same for every guess.
+ *
+ * Network: 4 resolutions with 16, 32, 64, 128 channels; per stage two 3x3x3
+ * convolutions (zero padding) each followed by ReLU; 2x2x2 mean pooling;
+ * nearest up-sampling concatenated (up-sampled channels first) with the
+ * encoder tensor of the same resolution; a 1x1x1 head to one channel.
+ * Convolutions run on the BF16 matrix cores with FP32 accumulation; tensors
+ * are BF16 channels-last; master weights, gradients and AdamW moments are
+ * FP32.
+ * Input (16 channels): rho / s on active cells (0 elsewhere), the mask
+ * (+1/-1), B / s, zeros; s = root mean square of rho over the sample's active
+ * cells (1 if zero).  Output: phi0 = s * y / 256 on active cells, 0 elsewhere.
+ * Parameters (float32, mg_unet_num_params of them): per layer in the order
+ * enc1a enc1b enc2a enc2b enc3a enc3b mid4a mid4b dec3a dec3b dec2a dec2b
+ * dec1a dec1b, weights [27][cout][cin] (tap = 9(dz+1) + 3(dy+1) + (dx+1))
+ * then bias [cout]; last the head weights [16] and bias [1].
+ * A network object is not re-entrant; all its work goes to its stream.
+ */
+typedef struct mg_unet mg_unet; /* opaque */
+
+/* Create a network with He-normal weights drawn from `seed` (zero biases).
+ * alloc: NULL = hipMalloc.  stream: 0 = a stream of its own. */
+mg_status mg_unet_create(uint64_t seed, const mg_allocator *alloc, void *stream, mg_unet **out);
+void mg_unet_destroy(mg_unet *U);
+int64_t mg_unet_num_params(const mg_unet *U);
+void *mg_unet_stream(const mg_unet *U);
+/* AdamW steps taken since the parameters were last set. */
+int32_t mg_unet_step(const mg_unet *U);
+
+/* Copy parameters in / out (host float32, count = mg_unet_num_params).
+ * Setting resets the AdamW moments and step.  Synchronous. */
+mg_status mg_unet_set_params(mg_unet *U, const float *params_host, int64_t count);
+mg_status mg_unet_get_params(mg_unet *U, float *params_host, int64_t count);
+/* Gradient of the loss of the last mg_unet_loss_grad / mg_unet_train_step. */
+mg_status mg_unet_get_grads(mg_unet *U, float *grads_host, int64_t count);
+
+/* Save / load parameters and AdamW state as a safetensors file (float32
+ * tensors "params", "adam_m", "adam_v"; metadata "step").  Loading a file
+ * with "params" only resets the optimizer.  MG_ERR_ARG on I/O or shape
+ * mismatch. */
+mg_status mg_unet_save(mg_unet *U, const char *path);
+mg_status mg_unet_load(mg_unet *U, const char *path);
+
+/*
+ * Loss and gradient for a batch of n samples: loss = mean over all active
+ * cells of the batch of (y - 256 phi_target / s_n)^2.
+ *   rho_dev, dirichlet_dev (NULL = 0), phi_target_dev : float64 (n, nz, ny, nx);
+ *   mask_dev : int8 (n, nz, ny, nx).  nx, ny, nz multiples of 8.
+ *   loss_out : host, receives the loss (the call synchronises the stream).
+ */
+mg_status mg_unet_loss_grad(mg_unet *U, int32_t n, const double *rho_dev, const int8_t *mask_dev,
+                            const double *dirichlet_dev, const double *phi_target_dev, int32_t nx, int32_t ny,
+                            int32_t nz, double *loss_out);
+
+/* mg_unet_loss_grad followed by one AdamW update (beta1 0.9, beta2 0.999,
+ * eps 1e-8, decoupled weight decay, bias-corrected moments).  loss_out may be
+ * NULL (no synchronisation). */
+mg_status mg_unet_train_step(mg_unet *U, int32_t n, const double *rho_dev, const int8_t *mask_dev,
+                             const double *dirichlet_dev, const double *phi_target_dev, int32_t nx, int32_t ny,
+                             int32_t nz, float lr, float weight_decay, double *loss_out);
+
+/*
+ * First guess for one problem (nz, ny, nx), written to phi0_dev (float64,
+ * every cell; 0 off the active set).  The network runs on the 1/stride grid
+ * (stride 1, 2, 4 or 8; dims multiples of 8 * stride): each coarse cell takes
+ * the mean of rho over its active fine cells, +1 when more than half of them
+ * are active, and the mean of B; the output is brought back to the fine grid
+ * by repeated linear up-sampling by 2 (per axis 3/4 of the parent, 1/4 of the
+ * next coarse cell, the edge cell repeated past the array end).  Enqueued on
+ * the network's stream; no synchronisation.
+ */
+mg_status mg_unet_infer(mg_unet *U, const double *rho_dev, const int8_t *mask_dev, const double *dirichlet_dev,
+                        int32_t nx, int32_t ny, int32_t nz, int32_t stride, double *phi0_dev);
+
+/*
+ * Coarse copy of a problem, for an interpolated first guess: the problem
+ * solved on the stride-times coarser grid (Sec. 6 compares against
+ * interpolated starts).  mask_c: +1 when more than half of the block is
+ * active, the outermost coarse layer -1; rho_c: mean of rho over the active
+ * cells of the block (0 if none); dirichlet_c: mean of B (written only if
+ * dirichlet_dev is not NULL).  Dims must be multiples of stride (>= 2).
+ */
+mg_status mg_coarsen_problem(const double *rho_dev, const int8_t *mask_dev, const double *dirichlet_dev, int32_t nx,
+                             int32_t ny, int32_t nz, int32_t stride, double *rho_c_dev, int8_t *mask_c_dev,
+                             double *dirichlet_c_dev, void *stream);
+
+/* phi = linear up-sampling by 2 of phi_c (dims nxc, nyc, nzc) on the active
+ * cells of mask (dims 2nxc, 2nyc, 2nzc), 0 elsewhere. */
+mg_status mg_upsample_guess(const double *phi_c_dev, int32_t nxc, int32_t nyc, int32_t nzc, const int8_t *mask_dev,
+                            double *phi_dev, void *stream);
+
+/* ---- network kernels, exported for tests (BF16 channels-last tensors) ---- */
+/* out = [ReLU](conv3x3x3(concat(up2?(in_a), in_b)) + bias).  in_a: ca
+ * channels, read at half resolution (nearest) when up_a; in_b: cb channels
+ * or NULL; w: BF16 [27][cout][ca+cb]; bias: float32 [cout] or NULL.  ca, cb
+ * multiples of 8, cout of 16. */
+mg_status mg_nn_conv3d_fwd(const void *in_a, int32_t ca, int32_t up_a, const void *in_b, int32_t cb, const void *w,
+                           const float *bias, void *out, int32_t cout, int32_t relu, int32_t n, int32_t d, int32_t h,
+                           int32_t wd, void *stream);
+/* dw[27][cout][ca+cb] += sum_v dout[v][co] x[v + tap][ci]; dbias[cout] (or
+ * NULL) += sum_v dout[v][co] (float32, accumulated).  ca+cb in {16, 32, 48,
+ * 64, 96, 128, 192}. */
+mg_status mg_nn_conv3d_bwd_weight(const void *dout, int32_t cout, const void *in_a, int32_t ca, int32_t up_a,
+                                  const void *in_b, int32_t cb, float *dw, float *dbias, int32_t n, int32_t d,
+                                  int32_t h, int32_t wd, void *stream);
+/* wt[26 - tap][ci][co] = w[tap][co][ci] (the input-gradient convolution's weights). */
+mg_status mg_nn_weight_flip(const void *w, int32_t cout, int32_t cin, void *wt, void *stream);
+/* dy[i] = 0 where y[i] <= 0. */
+mg_status mg_nn_relu_bwd(void *dy, const void *y, int64_t count, void *stream);
+/* 2x2x2 mean pooling of (n, d, h, wd, c); and its gradient, din += dout / 8. */
+mg_status mg_nn_pool2(const void *in, void *out, int32_t c, int32_t n, int32_t d, int32_t h, int32_t wd, void *stream);
+mg_status mg_nn_pool2_bwd(const void *dout, void *din, int32_t c, int32_t n, int32_t d, int32_t h, int32_t wd,
+                          void *stream);
+/* Gradient of a concatenated input (n, d, h, wd, ca+cb): dup (half
+ * resolution, ca channels) = sum over the 8 children, dskip = the last cb
+ * channels. */
+mg_status mg_nn_split_grad(const void *dx, int32_t ca, int32_t cb, void *dup, void *dskip, int32_t n, int32_t d,
+                           int32_t h, int32_t wd, void *stream);
+/* AdamW on float32 params (optional BF16 copy refreshed). */
+mg_status mg_nn_adamw(float *param, void *param_bf16, const float *grad, float *m, float *v, int64_t count, float lr,
+                      float beta1, float beta2, float eps, float weight_decay, int32_t step, void *stream);
+/* Writes the 16 x 16 product of the matrix-core self-test (row-major float32)
+ * to out_dev: a[m][k] = (3m + k) mod 7 - 3, b[k][n] = (5k + 2n) mod 9 - 4,
+ * k < 32. */
+mg_status mg_nn_mfma_selftest(float *out_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

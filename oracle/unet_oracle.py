@@ -135,25 +135,34 @@ def up2_nearest_backward(dy):
 
 
 # ------------------------------------------------------------- network
-def forward(params, x, keep=False):
+def _exact(t):
+    return t
+
+
+def forward(params, x, keep=False, store=_exact):
     """U-Net forward; returns the head output ``y`` of shape (N, D, H, W)
-    and, if ``keep``, every intermediate activation."""
+    and, if ``keep``, every intermediate activation.
+
+    ``store`` maps each tensor that is kept between layers (convolution and
+    pooling outputs) to the values actually kept; the default keeps them
+    exactly.  Tests pass a rounding to a storage format to model a device
+    that keeps activations in that format."""
     P = unpack(params)
     a = {"x": x}
 
     def conv(name, inp):
         w, b = P[name]
-        return conv3d(inp, w, b, relu=True)
+        return store(conv3d(inp, w, b, relu=True))
 
     a["enc1a"] = conv("enc1a", x)
     a["enc1b"] = conv("enc1b", a["enc1a"])
-    a["pool1"] = pool2(a["enc1b"])
+    a["pool1"] = store(pool2(a["enc1b"]))
     a["enc2a"] = conv("enc2a", a["pool1"])
     a["enc2b"] = conv("enc2b", a["enc2a"])
-    a["pool2"] = pool2(a["enc2b"])
+    a["pool2"] = store(pool2(a["enc2b"]))
     a["enc3a"] = conv("enc3a", a["pool2"])
     a["enc3b"] = conv("enc3b", a["enc3a"])
-    a["pool3"] = pool2(a["enc3b"])
+    a["pool3"] = store(pool2(a["enc3b"]))
     a["mid4a"] = conv("mid4a", a["pool3"])
     a["mid4b"] = conv("mid4b", a["mid4a"])
     a["cat3"] = np.concatenate([up2_nearest(a["mid4b"]), a["enc3b"]], axis=-1)
@@ -177,13 +186,15 @@ def loss(params, x, active, target):
     return float((d * d).mean())
 
 
-def loss_and_grad(params, x, active, target):
+def loss_and_grad(params, x, active, target, store=_exact):
     """Loss and its gradient with respect to the flat parameter vector, by
-    the chain rule through each layer (reverse order of ``forward``)."""
+    the chain rule through each layer (reverse order of ``forward``).
+    ``store`` as in ``forward``, applied also to each activation gradient
+    kept between layers."""
     P = unpack(params)
     lay, total = param_layout()
     g = np.zeros(total)
-    y, a = forward(params, x, keep=True)
+    y, a = forward(params, x, keep=True, store=store)
     cnt = int(active.sum())
     d = np.where(active, y - target, 0.0)
     L = float((d * d).sum() / cnt)
@@ -192,7 +203,7 @@ def loss_and_grad(params, x, active, target):
     wo, bo, _, _ = lay["head"]
     g[wo:wo + 16] = (a["dec1b"] * dy[..., None]).reshape(-1, 16).sum(axis=0)
     g[bo] = dy.sum()
-    grad = {"dec1b": dy[..., None] * hw}
+    grad = {"dec1b": store(dy[..., None] * hw)}
 
     def conv_back(name, inp_key, out_grad):
         """ReLU then convolution backward; returns the input gradient."""
@@ -202,10 +213,10 @@ def loss_and_grad(params, x, active, target):
         wo_, bo_, cin, co = lay[name]
         g[wo_:bo_] = dw.ravel()
         g[bo_:bo_ + co] = db
-        return dx
+        return store(dx)
 
     def split(dcat, c_up):
-        return up2_nearest_backward(dcat[..., :c_up]), dcat[..., c_up:]
+        return store(up2_nearest_backward(dcat[..., :c_up])), dcat[..., c_up:]
 
     grad["dec1a"] = conv_back("dec1b", "dec1a", grad["dec1b"])
     d_up, d_skip1 = split(conv_back("dec1a", "cat1", grad["dec1a"]), 32)
@@ -218,13 +229,13 @@ def loss_and_grad(params, x, active, target):
     grad["mid4b"] = d_up
     grad["mid4a"] = conv_back("mid4b", "mid4a", grad["mid4b"])
     d_pool3 = conv_back("mid4a", "pool3", grad["mid4a"])
-    grad["enc3b"] = d_skip3 + pool2_backward(d_pool3)
+    grad["enc3b"] = store(d_skip3 + pool2_backward(d_pool3))
     grad["enc3a"] = conv_back("enc3b", "enc3a", grad["enc3b"])
     d_pool2 = conv_back("enc3a", "pool2", grad["enc3a"])
-    grad["enc2b"] = d_skip2 + pool2_backward(d_pool2)
+    grad["enc2b"] = store(d_skip2 + pool2_backward(d_pool2))
     grad["enc2a"] = conv_back("enc2b", "enc2a", grad["enc2b"])
     d_pool1 = conv_back("enc2a", "pool1", grad["enc2a"])
-    grad["enc1b"] = d_skip1 + pool2_backward(d_pool1)
+    grad["enc1b"] = store(d_skip1 + pool2_backward(d_pool1))
     grad["enc1a"] = conv_back("enc1b", "enc1a", grad["enc1b"])
     conv_back("enc1a", "x", grad["enc1a"])
     return L, g

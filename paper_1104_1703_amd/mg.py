@@ -78,6 +78,32 @@ SYMBOLS = [
     ("mg_batch_size", _I, [_P]),
     ("mg_batch_grid", _I, [_P]),
     ("mg_batch_phases", _I, [_P, _I]),
+    # learned first guess
+    ("mg_unet_create", C.c_int, [C.c_uint64, _P, _P, C.POINTER(_P)]),
+    ("mg_unet_destroy", None, [_P]),
+    ("mg_unet_num_params", C.c_int64, [_P]),
+    ("mg_unet_stream", _P, [_P]),
+    ("mg_unet_step", _I, [_P]),
+    ("mg_unet_set_params", C.c_int, [_P, _P, C.c_int64]),
+    ("mg_unet_get_params", C.c_int, [_P, _P, C.c_int64]),
+    ("mg_unet_get_grads", C.c_int, [_P, _P, C.c_int64]),
+    ("mg_unet_save", C.c_int, [_P, C.c_char_p]),
+    ("mg_unet_load", C.c_int, [_P, C.c_char_p]),
+    ("mg_unet_loss_grad", C.c_int, [_P, _I, _P, _P, _P, _P, _I, _I, _I, C.POINTER(_D)]),
+    ("mg_unet_train_step", C.c_int, [_P, _I, _P, _P, _P, _P, _I, _I, _I, C.c_float, C.c_float, C.POINTER(_D)]),
+    ("mg_unet_infer", C.c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _P]),
+    ("mg_coarsen_problem", C.c_int, [_P, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P]),
+    ("mg_upsample_guess", C.c_int, [_P, _I, _I, _I, _P, _P, _P]),
+    ("mg_nn_conv3d_fwd", C.c_int, [_P, _I, _I, _P, _I, _P, _P, _P, _I, _I, _I, _I, _I, _I, _P]),
+    ("mg_nn_conv3d_bwd_weight", C.c_int, [_P, _I, _P, _I, _I, _P, _I, _P, _P, _I, _I, _I, _I, _P]),
+    ("mg_nn_weight_flip", C.c_int, [_P, _I, _I, _P, _P]),
+    ("mg_nn_relu_bwd", C.c_int, [_P, _P, C.c_int64, _P]),
+    ("mg_nn_pool2", C.c_int, [_P, _P, _I, _I, _I, _I, _I, _P]),
+    ("mg_nn_pool2_bwd", C.c_int, [_P, _P, _I, _I, _I, _I, _I, _P]),
+    ("mg_nn_split_grad", C.c_int, [_P, _I, _I, _P, _P, _I, _I, _I, _I, _P]),
+    ("mg_nn_adamw", C.c_int, [_P, _P, _P, _P, _P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                              C.c_float, _I, _P]),
+    ("mg_nn_mfma_selftest", C.c_int, [_P, _P]),
 ]
 
 _lib = None
@@ -380,3 +406,222 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------- learned guess
+class UNet:
+    """The learned first-guess network (a 3D U-Net run by the library's BF16
+    matrix-core kernels).  Parameters live on the device; ``params`` /
+    ``set_params`` copy them as float32 host arrays."""
+
+    def __init__(self, seed: int = 0, device=None, stream=None, torch_allocator: bool = True):
+        lib = load_library()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self._alloc = None
+        ap = None
+        if torch_allocator:
+            self._alloc = _TorchAllocator(self.device, self.stream)
+            self._astruct = Allocator(self._alloc.alloc_fn, self._alloc.free_fn, None)
+            ap = C.byref(self._astruct)
+        out = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.mg_unet_create(int(seed), ap, C.c_void_p(self.stream.cuda_stream), C.byref(out))
+        _check(st, "mg_unet_create")
+        self._u = out
+        self.num_params = int(lib.mg_unet_num_params(self._u))
+
+    def _call(self, fn, *args):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.device(self.device):
+            st = fn(*args)
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return st
+
+    @property
+    def step(self) -> int:
+        return int(load_library().mg_unet_step(self._u))
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.num_params, np.float32)
+        _check(self._call(load_library().mg_unet_get_params, self._u, out.ctypes.data_as(C.c_void_p),
+                          self.num_params), "mg_unet_get_params")
+        return out
+
+    def grads(self):
+        import numpy as np
+        out = np.empty(self.num_params, np.float32)
+        _check(self._call(load_library().mg_unet_get_grads, self._u, out.ctypes.data_as(C.c_void_p),
+                          self.num_params), "mg_unet_get_grads")
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(self._call(load_library().mg_unet_set_params, self._u, p.ctypes.data_as(C.c_void_p), p.size),
+               "mg_unet_set_params")
+
+    def save(self, path: str):
+        _check(self._call(load_library().mg_unet_save, self._u, os.fsencode(path)), "mg_unet_save")
+
+    def load(self, path: str):
+        _check(self._call(load_library().mg_unet_load, self._u, os.fsencode(path)), "mg_unet_load")
+
+    @staticmethod
+    def _batch(rho, mask, dirichlet, target):
+        if rho.dim() == 3:
+            rho, mask, target = rho[None], mask[None], target[None]
+            dirichlet = None if dirichlet is None else dirichlet[None]
+        n, nz, ny, nx = rho.shape
+        return n, nz, ny, nx, rho, mask, dirichlet, target
+
+    def loss_grad(self, rho, mask, target, dirichlet=None) -> float:
+        """Loss and gradients (kept on the device) for a batch (n, nz, ny, nx)."""
+        n, nz, ny, nx, rho, mask, dirichlet, target = self._batch(rho, mask, dirichlet, target)
+        loss = C.c_double()
+        _check(self._call(load_library().mg_unet_loss_grad, self._u, n, _ptr(rho), _ptr(mask), _ptr(dirichlet),
+                          _ptr(target), nx, ny, nz, C.byref(loss)), "mg_unet_loss_grad")
+        return float(loss.value)
+
+    def train_step(self, rho, mask, target, dirichlet=None, lr: float = 1e-3, weight_decay: float = 0.0,
+                   sync: bool = True):
+        """One AdamW step on a batch; returns the loss (None if not sync)."""
+        n, nz, ny, nx, rho, mask, dirichlet, target = self._batch(rho, mask, dirichlet, target)
+        loss = C.c_double()
+        _check(self._call(load_library().mg_unet_train_step, self._u, n, _ptr(rho), _ptr(mask), _ptr(dirichlet),
+                          _ptr(target), nx, ny, nz, float(lr), float(weight_decay),
+                          C.byref(loss) if sync else None), "mg_unet_train_step")
+        return float(loss.value) if sync else None
+
+    def infer(self, rho, mask, dirichlet=None, stride: int = 1, out=None):
+        """First guess phi0 (float64, shape of rho) from the network at 1/stride resolution."""
+        nz, ny, nx = rho.shape
+        if out is None:
+            out = torch.empty(rho.shape, dtype=torch.float64, device=self.device)
+        _check(self._call(load_library().mg_unet_infer, self._u, _ptr(rho), _ptr(mask), _ptr(dirichlet), nx, ny, nz,
+                          int(stride), _ptr(out)), "mg_unet_infer")
+        return out
+
+    def close(self):
+        if getattr(self, "_u", None):
+            with torch.cuda.device(self.device):
+                load_library().mg_unet_destroy(self._u)
+            self._u = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def coarsen_problem(rho, mask, dirichlet=None, stride: int = 2):
+    """Coarse copy (rho_c, mask_c, dirichlet_c) of a problem on the 1/stride grid."""
+    nz, ny, nx = rho.shape
+    shp = (nz // stride, ny // stride, nx // stride)
+    rho_c = torch.empty(shp, dtype=torch.float64, device=rho.device)
+    mask_c = torch.empty(shp, dtype=torch.int8, device=rho.device)
+    b_c = None if dirichlet is None else torch.empty(shp, dtype=torch.float64, device=rho.device)
+    st = load_library().mg_coarsen_problem(_ptr(rho), _ptr(mask), _ptr(dirichlet), nx, ny, nz, int(stride),
+                                           _ptr(rho_c), _ptr(mask_c), _ptr(b_c),
+                                           C.c_void_p(torch.cuda.current_stream(rho.device).cuda_stream))
+    _check(st, "mg_coarsen_problem")
+    return rho_c, mask_c, b_c
+
+
+def upsample_guess(phi_c, mask, out=None):
+    """Linear up-sampling by 2 of phi_c onto the active cells of ``mask``."""
+    nzc, nyc, nxc = phi_c.shape
+    if out is None:
+        out = torch.empty(mask.shape, dtype=torch.float64, device=phi_c.device)
+    st = load_library().mg_upsample_guess(_ptr(phi_c), nxc, nyc, nzc, _ptr(mask), _ptr(out),
+                                          C.c_void_p(torch.cuda.current_stream(phi_c.device).cuda_stream))
+    _check(st, "mg_upsample_guess")
+    return out
+
+
+class nn:
+    """Thin wrappers of the exported network kernels (BF16 channels-last
+    tensors; every call enqueues on torch's current stream)."""
+
+    @staticmethod
+    def _s(t):
+        return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+    @staticmethod
+    def conv3d(a, w, bias=None, b=None, up_a=False, relu=True):
+        """Output (n, d, h, wd, cout) at the resolution of ``b`` (if given) or of ``a``."""
+        if up_a and b is None:
+            raise ValueError("an up-sampled input needs the full-resolution input for its shape")
+        n, d, h, wd = (b if b is not None else a).shape[:4]
+        cb = 0 if b is None else b.shape[-1]
+        cout = w.shape[1]
+        out = torch.empty((n, d, h, wd, cout), dtype=torch.bfloat16, device=a.device)
+        st = load_library().mg_nn_conv3d_fwd(_ptr(a), a.shape[-1], int(up_a), _ptr(b), cb, _ptr(w), _ptr(bias),
+                                             _ptr(out), cout, int(relu), n, d, h, wd, nn._s(a))
+        _check(st, "mg_nn_conv3d_fwd")
+        return out
+
+    @staticmethod
+    def conv3d_bwd_weight(dout, a, b=None, up_a=False, dw=None, dbias=None):
+        n, d, h, wd, cout = dout.shape
+        cin = a.shape[-1] + (0 if b is None else b.shape[-1])
+        if dw is None:
+            dw = torch.zeros((27, cout, cin), dtype=torch.float32, device=dout.device)
+        if dbias is None:
+            dbias = torch.zeros(cout, dtype=torch.float32, device=dout.device)
+        st = load_library().mg_nn_conv3d_bwd_weight(_ptr(dout), cout, _ptr(a), a.shape[-1], int(up_a), _ptr(b),
+                                                    0 if b is None else b.shape[-1], _ptr(dw), _ptr(dbias), n, d, h,
+                                                    wd, nn._s(dout))
+        _check(st, "mg_nn_conv3d_bwd_weight")
+        return dw, dbias
+
+    @staticmethod
+    def weight_flip(w):
+        _, cout, cin = w.shape
+        wt = torch.empty((27, cin, cout), dtype=w.dtype, device=w.device)
+        _check(load_library().mg_nn_weight_flip(_ptr(w), cout, cin, _ptr(wt), nn._s(w)), "mg_nn_weight_flip")
+        return wt
+
+    @staticmethod
+    def relu_bwd(dy, y):
+        dy = dy.clone()
+        _check(load_library().mg_nn_relu_bwd(_ptr(dy), _ptr(y), dy.numel(), nn._s(dy)), "mg_nn_relu_bwd")
+        return dy
+
+    @staticmethod
+    def pool2(x):
+        n, d, h, wd, c = x.shape
+        out = torch.empty((n, d // 2, h // 2, wd // 2, c), dtype=x.dtype, device=x.device)
+        _check(load_library().mg_nn_pool2(_ptr(x), _ptr(out), c, n, d, h, wd, nn._s(x)), "mg_nn_pool2")
+        return out
+
+    @staticmethod
+    def pool2_bwd(dout, din):
+        n, d, h, wd, c = din.shape
+        din = din.clone()
+        _check(load_library().mg_nn_pool2_bwd(_ptr(dout), _ptr(din), c, n, d, h, wd, nn._s(din)), "mg_nn_pool2_bwd")
+        return din
+
+    @staticmethod
+    def split_grad(dx, ca):
+        n, d, h, wd, cin = dx.shape
+        cb = cin - ca
+        dup = torch.empty((n, d // 2, h // 2, wd // 2, ca), dtype=dx.dtype, device=dx.device)
+        dskip = torch.empty((n, d, h, wd, cb), dtype=dx.dtype, device=dx.device) if cb else None
+        _check(load_library().mg_nn_split_grad(_ptr(dx), ca, cb, _ptr(dup), _ptr(dskip), n, d, h, wd, nn._s(dx)),
+               "mg_nn_split_grad")
+        return dup, dskip
+
+    @staticmethod
+    def adamw(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, p_bf16=None):
+        _check(load_library().mg_nn_adamw(_ptr(p), _ptr(p_bf16), _ptr(g), _ptr(m), _ptr(v), p.numel(), float(lr),
+                                          float(beta1), float(beta2), float(eps), float(weight_decay), int(step),
+                                          nn._s(p)), "mg_nn_adamw")
+
+    @staticmethod
+    def mfma_selftest(device="cuda"):
+        out = torch.zeros((16, 16), dtype=torch.float32, device=device)
+        _check(load_library().mg_nn_mfma_selftest(_ptr(out), nn._s(out)), "mg_nn_mfma_selftest")
+        return out
