@@ -9,8 +9,12 @@ Also measured here, for the dominant kernel (the finest-level smoother):
 its average launch duration with HIP events on the solver's stream, and the
 oracle (plain FP64 C, host cores) on a bounded sample of the same workload.
 
+Beside it (not part of `value`): the same solve with FP32 inner cycles in
+FP64 iterative refinement, from an interpolated (coarse-solve) guess and from
+the learned U-Net guess, each timed whole (guess included).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       [--variants mixed] [--no-cpu-baseline]
+       [--variants mixed,interp,learned,learned_mixed] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -57,7 +61,11 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--variants", default="mixed", help="comma list of extra variants timed beside fp64: mixed")
+    ap.add_argument("--variants", default="mixed,interp,learned,learned_mixed",
+                    help="comma list of extra variants timed beside fp64: mixed (FP32 inner / FP64 outer), "
+                         "interp (coarse-solve guess), learned (U-Net guess), learned_mixed")
+    ap.add_argument("--learned-stride", type=int, default=4, help="U-Net runs on the 1/stride grid")
+    ap.add_argument("--weights", default=None, help="U-Net weights (default: the package's trained file)")
     ap.add_argument("--smoother-launches", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2)
@@ -140,9 +148,12 @@ def main():
     rho = torch.from_numpy(p.rho).to(dev)
     phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
 
-    def time_solves(H):
+    def time_solves(H, make_guess=None):
         def step():
-            phi.zero_()
+            if make_guess is None:
+                phi.zero_()
+            else:
+                make_guess(phi)
             return H.solve(rho, phi, None, tol=args.tol)[1]
         for _ in range(args.warmup):
             step()
@@ -176,14 +187,46 @@ def main():
     H.close()
 
     variants = {}
+    net = None
     for v in [x for x in args.variants.split(",") if x]:
-        Hv = mg.Hierarchy(mask, p.h, precision=v)
-        v_wall, v_events, v_last = time_solves(Hv)
+        precision = "mixed" if v in ("mixed", "learned_mixed") else "fp64"
+        make_guess, extra, ig = None, {}, None
+        if v == "interp":
+            from paper_1104_1703_amd import guess
+            ig = guess.InterpolatedGuess(mask, p.h)
+            make_guess = lambda out: ig(rho, out=out)
+            extra["guess"] = "problem coarsened by 2 per axis, FP64 multigrid to 1e-4, linear up-sampling"
+        elif v in ("learned", "learned_mixed"):
+            from paper_1104_1703_amd import guess
+            if net is None:
+                try:
+                    net = guess.load_network(args.weights or guess.WEIGHTS)
+                except FileNotFoundError as e:
+                    variants[v] = {"skipped": str(e)}
+                    continue
+            stride = args.learned_stride
+            make_guess = lambda out: net.infer(rho, mask, stride=stride, out=out)
+            for _ in range(3):
+                make_guess(phi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(10):
+                make_guess(phi)
+            torch.cuda.synchronize()
+            extra["guess"] = f"U-Net at 1/{stride} resolution, linear up-sampling"
+            extra["guess_ms"] = round((time.perf_counter() - t0) / 10 * 1e3, 4)
+        elif v != "mixed":
+            raise SystemExit(f"unknown variant {v}")
+        Hv = mg.Hierarchy(mask, p.h, precision=precision)
+        v_wall, v_events, v_last = time_solves(Hv, make_guess)
         diff = float((phi - phi64).abs().max() / phi64.abs().max())
         variants[v] = {"ms": round(v_wall, 4), "speedup_vs_fp64": round(ms_wall / v_wall, 3),
                        "cycles": v_last["cycles"], "final_rel_residual": v_last["r_final"] / v_last["r_ref"],
-                       "max_rel_diff_vs_fp64_solution": diff}
+                       "initial_rel_residual": v_last["r0"] / v_last["r_ref"],
+                       "max_rel_diff_vs_fp64_solution": diff, **extra}
         Hv.close()
+        if ig is not None:
+            ig.close()
 
     traffic = measured_traffic() if args.n == 256 and args.seed == 2 else None
     out = {

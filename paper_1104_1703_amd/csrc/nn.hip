@@ -4,13 +4,14 @@
 // element (n, z, y, x, c) at ((((n*D + z)*H + y)*W + x)*C + c).
 //
 // Convolution (3x3x3, zero padding, stride 1) as a GEMM: M = voxels,
-// N = output channels, K = 27 taps x input channels.  A wave owns MT x 16
+// N = output channels, K = 27 taps x input channels.  A wave owns 4 x 16
 // voxels by NTC x 16 output channels.  At each K step of 32, lane l supplies
 // row (l mod 16) of A and column (l mod 16) of B as 8 consecutive K entries
 // starting at 8*(l div 16); with channels-last tensors and [tap][co][ci]
-// weights both are single 16-byte loads.  The input may be the channel
-// concatenation of a tensor read at half resolution (nearest upsampling,
-// fused into the gather) and a full-resolution tensor.
+// weights both are single 16-byte reads (A from a halo tile in LDS, B from
+// global memory).  The input may be the channel concatenation of a tensor
+// read at half resolution (nearest up-sampling, resolved while the tile is
+// staged) and a full-resolution tensor.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,71 +39,124 @@ __device__ __forceinline__ f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f3
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// ---------------------------------------------------------------- conv fwd
-template <int NTC, int MT>
-__global__ __launch_bounds__(NTH) void k_conv_fwd(const bf16 *__restrict__ ina, int ca, int upa,
-                                                   const bf16 *__restrict__ inb, int cb, const bf16 *__restrict__ wt,
-                                                   const float *__restrict__ bias, bf16 *__restrict__ out, int cout,
-                                                   int relu, int D, int H, int W, long long V) {
+// ------------------------------------------------------ conv fwd, LDS tiles
+// out = [ReLU](conv3x3x3(concat(up2?(ina), inb)) + bias) as an implicit GEMM
+// (M = voxels, N = output channels, K = 27 taps x input channels), organised
+// around LDS: a block owns an
+// 8 x 8 x 4 tile of output voxels of one sample and, for each chunk of CK
+// input channels, stages the 10 x 10 x 6 halo of its input in LDS (zeros
+// outside the box, nearest up-sampling and the skip concatenation resolved
+// while staging).  The tap loop then reads every A fragment from LDS at a
+// uniform tap offset, with no bounds tests.  Wave w computes z-plane w of
+// the tile; its fragment mt covers rows y = 2 mt, 2 mt + 1, lane row r the
+// voxel x = r mod 8, y = 2 mt + r div 8.
+constexpr int TX = 8, TY = 8, TZ = 4;
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HV = HX * HY * HZ;
+
+template <int CK, int NTC>
+__global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina, int ca, int upa,
+                                                    const bf16 *__restrict__ inb, int cb, const bf16 *__restrict__ wt,
+                                                    const float *__restrict__ bias, bf16 *__restrict__ out, int cout,
+                                                    int relu, int D, int H, int W, int ntx, int nty, int ntz,
+                                                    int nblk) {
+    constexpr int CKP = CK + 8;  // padded LDS row: spreads a fragment's 16 voxels over the banks
+    constexpr int MT = 4;
+    __shared__ __attribute__((aligned(16))) bf16 tile[HV * CKP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, grp = lane >> 4;
-    const int cin = ca + cb;
-    const long long vbase = ((long long)blockIdx.x * (NTH / 64) + wave) * (MT * 16);
+    // the 8 XCDs take contiguous runs of tiles, so neighbouring halos share an L2
+    int b = blockIdx.x;
+    if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+    const int tx = b % ntx;
+    int t = b / ntx;
+    const int ty = t % nty;
+    t /= nty;
+    const int tz = t % ntz;
+    const int n = t / ntz;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int co_base = blockIdx.y * NTC * 16;
+    const int cin = ca + cb;
     const int Dc = D >> 1, Hc = H >> 1, Wc = W >> 1;
-    int vx[MT], vy[MT], vz[MT], vn[MT];
-    bool vok[MT];
+    int hb[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; mt++) {
-        const long long v = vbase + mt * 16 + row;
-        vok[mt] = v < V;
-        long long t = vok[mt] ? v : 0;
-        vx[mt] = (int)(t % W);
-        t /= W;
-        vy[mt] = (int)(t % H);
-        t /= H;
-        vz[mt] = (int)(t % D);
-        vn[mt] = (int)(t / D);
-    }
+    for (int mt = 0; mt < MT; mt++) hb[mt] = ((wave + 1) * HY + 2 * mt + (row >> 3) + 1) * HX + (row & 7) + 1;
     f32x4 acc[MT][NTC];
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
         for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int ksteps = (27 * cin + 31) / 32;
-    for (int s = 0; s < ksteps; ++s) {
-        const int kk = s * 32 + grp * 8;
-        const int tap = kk / cin, ci0 = kk - tap * cin;
-        const bool tok = tap < 27;
-        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        bf16x8 bfr[NTC];
-#pragma unroll
-        for (int nt = 0; nt < NTC; nt++) {
-            const int co = co_base + nt * 16 + row;
-            bfr[nt] = tok ? *(const bf16x8 *)(wt + ((size_t)tap * cout + co) * cin + ci0) : zero8();
-        }
-        const bool from_a = ci0 < ca;
-#pragma unroll
-        for (int mt = 0; mt < MT; mt++) {
-            const int z = vz[mt] + dz, y = vy[mt] + dy, x = vx[mt] + dx;
-            const bool ok = vok[mt] && tok && z >= 0 && z < D && y >= 0 && y < H && x >= 0 && x < W;
-            bf16x8 afr = zero8();
-            if (ok) {
-                if (from_a) {
-                    size_t vox;
-                    if (upa) vox = (((size_t)vn[mt] * Dc + (z >> 1)) * Hc + (y >> 1)) * Wc + (x >> 1);
-                    else vox = (((size_t)vn[mt] * D + z) * H + y) * W + x;
-                    afr = *(const bf16x8 *)(ina + vox * ca + ci0);
+
+    for (int c0 = 0; c0 < cin; c0 += CK) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < HV * (CK / 8); e += NTH) {
+            const int hv = e / (CK / 8), c8 = (e - hv * (CK / 8)) * 8;
+            const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+            const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+            const int c = c0 + c8;
+            bf16x8 v = zero8();
+            if (c < cin && gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
+                if (c < ca) {
+                    const size_t vox = upa ? (((size_t)n * Dc + (gz >> 1)) * Hc + (gy >> 1)) * Wc + (gx >> 1)
+                                           : (((size_t)n * D + gz) * H + gy) * W + gx;
+                    v = *(const bf16x8 *)(ina + vox * ca + c);
                 } else {
-                    const size_t vox = (((size_t)vn[mt] * D + z) * H + y) * W + x;
-                    afr = *(const bf16x8 *)(inb + vox * cb + (ci0 - ca));
+                    const size_t vox = (((size_t)n * D + gz) * H + gy) * W + gx;
+                    v = *(const bf16x8 *)(inb + vox * cb + (c - ca));
                 }
             }
+            *(bf16x8 *)(tile + hv * CKP + c8) = v;
+        }
+        __syncthreads();
+        if constexpr (CK == 32) {
+            const int cw = c0 + grp * 8;  // this lane's 8 K entries: channels cw .. cw + 7 of one tap
+            const bool cok = cw < cin;
+#pragma unroll 1
+            for (int tzy = 0; tzy < 9; ++tzy) {  // (dz, dy) rows of taps; the 3 dx taps unrolled
+                const int rowoff = ((tzy / 3 - 1) * HY + tzy % 3 - 1) * HX;
 #pragma unroll
-            for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = mfma(afr, bfr[nt], acc[mt][nt]);
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int tap = tzy * 3 + dx;
+                    const int toff = rowoff + dx - 1;
+                    bf16x8 bfr[NTC];
+#pragma unroll
+                    for (int nt = 0; nt < NTC; nt++) {
+                        const int co = co_base + nt * 16 + row;
+                        bfr[nt] = cok ? *(const bf16x8 *)(wt + ((size_t)tap * cout + co) * cin + cw) : zero8();
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < MT; mt++) {
+                        const bf16x8 afr = *(const bf16x8 *)(tile + (hb[mt] + toff) * CKP + grp * 8);
+#pragma unroll
+                        for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = mfma(afr, bfr[nt], acc[mt][nt]);
+                    }
+                }
+            }
+        } else {
+            // 16 channels per tap: one K step of 32 covers taps 2p (lane groups 0, 1) and 2p + 1 (2, 3)
+            const int half = grp >> 1, cl = (grp & 1) * 8, cw = c0 + cl;
+            const bool cok = cw < cin;
+#pragma unroll 2
+            for (int p = 0; p < 14; ++p) {
+                const int tap = 2 * p + half;
+                const bool tok = cok && tap < 27;
+                const int toff = tap < 27 ? ((tap / 9 - 1) * HY + (tap / 3) % 3 - 1) * HX + tap % 3 - 1 : 0;
+                bf16x8 bfr[NTC];
+#pragma unroll
+                for (int nt = 0; nt < NTC; nt++) {
+                    const int co = co_base + nt * 16 + row;
+                    bfr[nt] = tok ? *(const bf16x8 *)(wt + ((size_t)tap * cout + co) * cin + cw) : zero8();
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; mt++) {
+                    const bf16x8 afr = tok ? *(const bf16x8 *)(tile + (hb[mt] + toff) * CKP + cl) : zero8();
+#pragma unroll
+                    for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = mfma(afr, bfr[nt], acc[mt][nt]);
+                }
+            }
         }
     }
-    // lane l holds D[4*(l div 16) + r][l mod 16] of each 16 x 16 tile
+    // lane l holds D[4 (l div 16) + r][l mod 16]: voxel m = 4 grp + r of fragment mt, channel row
+    const int z = z0 + wave;
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
@@ -111,11 +165,12 @@ __global__ __launch_bounds__(NTH) void k_conv_fwd(const bf16 *__restrict__ ina, 
             const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const long long v = vbase + mt * 16 + grp * 4 + r;
-                if (v < V) {
+                const int m = grp * 4 + r;
+                const int x = x0 + (m & 7), y = y0 + 2 * mt + (m >> 3);
+                if (x < W && y < H && z < D) {
                     float val = acc[mt][nt][r] + bv;
                     if (relu) val = fmaxf(val, 0.f);
-                    out[v * cout + co] = (bf16)val;
+                    out[((((size_t)n * D + z) * H + y) * W + x) * cout + co] = (bf16)val;
                 }
             }
         }
@@ -605,15 +660,6 @@ inline unsigned blocks_for(long long n, int per = 256) {
     return (unsigned)(g > 0 ? g : 1);
 }
 
-template <int NTC>
-void launch_fwd_ntc(const bf16 *ina, int ca, int upa, const bf16 *inb, int cb, const bf16 *w, const float *bias,
-                    bf16 *out, int cout, int relu, int D, int H, int W, long long V, hipStream_t s) {
-    constexpr int MT = 4;
-    const long long per_block = (NTH / 64) * MT * 16;
-    dim3 grid((unsigned)((V + per_block - 1) / per_block), (unsigned)(cout / (16 * NTC)));
-    k_conv_fwd<NTC, MT><<<grid, NTH, 0, s>>>(ina, ca, upa, inb, cb, w, bias, out, cout, relu, D, H, W, V);
-}
-
 template <int NCI>
 void launch_bww(const bf16 *dout, int cout, const bf16 *ina, int ca, int upa, const bf16 *inb, int cb, float *dw,
                 float *db, int D, int H, int W, long long V, hipStream_t s) {
@@ -631,6 +677,29 @@ void launch_bww(const bf16 *dout, int cout, const bf16 *ina, int ca, int upa, co
 // ------------------------------------------------ host launchers (nn_core.h)
 static bool dims_ok(int n, int d, int h, int w) { return n > 0 && d > 0 && h > 0 && w > 0; }
 
+template <int CK, int NTC>
+void launch_tile(const bf16 *ina, int ca, int upa, const bf16 *inb, int cb, const bf16 *w, const float *bias, bf16 *out,
+                 int cout, int relu, int n, int D, int H, int W, hipStream_t s) {
+    const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY, ntz = (D + TZ - 1) / TZ;
+    const int nblk = n * ntx * nty * ntz;
+    dim3 grid((unsigned)nblk, (unsigned)(cout / (16 * NTC)));
+    k_conv_tile<CK, NTC><<<grid, NTH, 0, s>>>(ina, ca, upa, inb, cb, w, bias, out, cout, relu, D, H, W, ntx, nty, ntz,
+                                              nblk);
+}
+
+template <int CK>
+void launch_tile_ck(const bf16 *ina, int ca, int upa, const bf16 *inb, int cb, const bf16 *w, const float *bias,
+                    bf16 *out, int cout, int relu, int n, int D, int H, int W, hipStream_t s) {
+    // widest output tiling that still gives about 1024 blocks
+    const long long nblk = (long long)n * ((W + TX - 1) / TX) * ((H + TY - 1) / TY) * ((D + TZ - 1) / TZ);
+    const int tiles = cout / 16;
+    int ntc = tiles % 4 == 0 ? 4 : tiles % 2 == 0 ? 2 : 1;
+    while (ntc > 1 && nblk * (tiles / ntc) < 1024) ntc /= 2;
+    if (ntc == 4) launch_tile<CK, 4>(ina, ca, upa, inb, cb, w, bias, out, cout, relu, n, D, H, W, s);
+    else if (ntc == 2) launch_tile<CK, 2>(ina, ca, upa, inb, cb, w, bias, out, cout, relu, n, D, H, W, s);
+    else launch_tile<CK, 1>(ina, ca, upa, inb, cb, w, bias, out, cout, relu, n, D, H, W, s);
+}
+
 bool conv_fwd(const void *in_a, int ca, int up_a, const void *in_b, int cb, const void *w, const float *bias,
               void *out, int cout, int relu, int n, int d, int h, int wd, hipStream_t s) {
     if (!in_a || !w || !out || ca <= 0 || cb < 0 || (cb > 0 && !in_b) || ca % 8 || cb % 8 || cout <= 0 ||
@@ -638,13 +707,10 @@ bool conv_fwd(const void *in_a, int ca, int up_a, const void *in_b, int cb, cons
         set_error("conv3d: invalid arguments (input channels multiples of 8, output channels of 16)");
         return false;
     }
-    const long long V = (long long)n * d * h * wd;
     const bf16 *A = (const bf16 *)in_a, *B = (const bf16 *)in_b, *W = (const bf16 *)w;
     bf16 *O = (bf16 *)out;
-    const int tiles = cout / 16;
-    if (tiles % 4 == 0) launch_fwd_ntc<4>(A, ca, up_a, B, cb, W, bias, O, cout, relu, d, h, wd, V, s);
-    else if (tiles % 2 == 0) launch_fwd_ntc<2>(A, ca, up_a, B, cb, W, bias, O, cout, relu, d, h, wd, V, s);
-    else launch_fwd_ntc<1>(A, ca, up_a, B, cb, W, bias, O, cout, relu, d, h, wd, V, s);
+    if (ca + cb <= 16) launch_tile_ck<16>(A, ca, up_a, B, cb, W, bias, O, cout, relu, n, d, h, wd, s);
+    else launch_tile_ck<32>(A, ca, up_a, B, cb, W, bias, O, cout, relu, n, d, h, wd, s);
     return hip_ok(hipGetLastError(), "conv3d launch");
 }
 

@@ -76,6 +76,9 @@ CONV_CASES = [
     (1, 8, 6, 10, 64, 32, 32, True),
     (1, 12, 8, 8, 32, 16, 16, True),
     (1, 4, 4, 4, 16, 0, 192, False),
+    (1, 16, 24, 16, 16, 0, 16, False),   # 24 tiles: XCD-ordered blocks
+    (2, 16, 16, 16, 64, 32, 32, True),   # 32 tiles, up-sampled concatenation
+    (1, 2, 8, 8, 32, 0, 16, False),      # depth below one tile
 ]
 
 
@@ -379,3 +382,27 @@ def test_learned_guess_then_solve_meets_fp64_bar(mg):
         err = np.abs(host(phi) - ref).max() / np.abs(ref).max()
         print(f"  stride {stride}: cycles {info['cycles']} err {err:.2e}", flush=True)
         assert err <= 1e-9
+
+
+def test_trained_network_saves_cycles(mg):
+    """What the shipped network gains: fewer multigrid cycles to the same
+    1e-10 target than the zero guess, on held-out 64^3 samples (network at
+    full resolution) and on the 256^3 holes workload (network on the 64^3
+    grid, the resolution it was trained at), with the solution unchanged."""
+    from paper_1104_1703_amd import guess
+    net = guess.load_network()
+    cases = [(gen.holes_problem(n=64, seed=s), 1) for s in (30000, 30001, 30002)]
+    cases.append((gen.holes_problem(n=256, seed=2), 4))
+    for p, stride in cases:
+        _case("trained guess", name=p.name, stride=stride)
+        rho = torch.from_numpy(p.rho).cuda()
+        mask = torch.from_numpy(p.mask).cuda()
+        H = mg.Hierarchy(mask, p.h)
+        phi0, i0 = H.solve(rho, tol=1e-10)
+        phi1, i1 = H.solve(rho, phi=net.infer(rho, mask, stride=stride), tol=1e-10)
+        diff = float((phi1 - phi0).abs().max() / phi0.abs().max())
+        print(f"  cycles zero {i0['cycles']} learned {i1['cycles']}  diff {diff:.1e}", flush=True)
+        assert i0["status"] == 0 and i1["status"] == 0
+        assert i1["cycles"] <= i0["cycles"] - 2
+        assert diff <= 1e-9
+        H.close()
