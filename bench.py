@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -68,11 +70,14 @@ def parse():
     ap.add_argument("--weights", default=None, help="U-Net weights (default: the package's trained file)")
     ap.add_argument("--smoother-launches", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=2)
+    ap.add_argument("--cpu-solves", type=int, default=2, help="complete oracle solves timed for cpu_baseline")
     ap.add_argument("--profile-smoother", type=int, default=0, metavar="N",
                     help="counter runs: build the 256^3 hierarchy, launch only the finest smoother N times, exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="counter runs: 4 plain device copies of MIB MiB (known bytes), exit")
+    ap.add_argument("--profile-unet", type=int, default=0, metavar="N",
+                    help="kernel runs: N U-Net inferences (256^3 holes, --learned-stride) and N training steps "
+                         "(batch 8 of 64^3), exit")
     return ap.parse_args()
 
 
@@ -104,26 +109,86 @@ def copy_calibration(args):
                       "copies": 4}), flush=True)
 
 
-def cpu_baseline(p, gpu_cycles, cycles):
-    """The oracle as it stands, on `cycles` multigrid cycles of the same
-    workload, scaled to the GPU solve's cycle count."""
+def profile_unet(args):
+    import torch
+
+    from paper_1104_1703_amd import gen, mg
+    net = mg.UNet(seed=0)
+    p = gen.holes_problem(n=args.n, seed=args.seed)
+    rho = torch.from_numpy(p.rho).cuda()
+    mask = torch.from_numpy(p.mask).cuda()
+    out = net.infer(rho, mask, stride=args.learned_stride)
+    tr = [gen.training_sample(64, 10000 + i) for i in range(8)]
+    r8 = torch.from_numpy(np.stack([t.rho for t in tr])).cuda()
+    m8 = torch.from_numpy(np.stack([t.mask for t in tr])).cuda()
+    for _ in range(args.profile_unet):
+        net.infer(rho, mask, stride=args.learned_stride, out=out)
+    for _ in range(args.profile_unet):
+        net.train_step(r8, m8, r8 * 1e-3, lr=1e-4, sync=False)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "profile-unet", "inferences": args.profile_unet, "stride": args.learned_stride,
+                      "train_steps": args.profile_unet}), flush=True)
+
+
+UNET_CONV = ("dec1a", 32, 16, 16)  # layer, up-sampled channels, skip channels, output channels
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def unet_conv_roofline():
+    """The widest convolution of a training step (dec1a: 32 up-sampled + 16
+    skip channels -> 16, on 8 x 64^3 voxels), timed with HIP events on the
+    stream it is launched on, against the dense BF16 matrix-core peak."""
+    import torch
+
+    from paper_1104_1703_amd import mg
+    name, ca, cb, cout = UNET_CONV
+    n, d = 8, 64
+    g = torch.Generator(device="cpu").manual_seed(0)
+    a = torch.randn((n, d // 2, d // 2, d // 2, ca), generator=g).to(torch.bfloat16).cuda()
+    b = torch.randn((n, d, d, d, cb), generator=g).to(torch.bfloat16).cuda()
+    w = (torch.randn((27, cout, ca + cb), generator=g) * 0.05).to(torch.bfloat16).cuda()
+    bias = torch.zeros(cout, dtype=torch.float32).cuda()
+    for _ in range(5):
+        mg.nn.conv3d(a, w, bias, b=b, up_a=True)
+    launches = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        mg.nn.conv3d(a, w, bias, b=b, up_a=True)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    flops = 2.0 * 27 * (ca + cb) * cout * n * d ** 3
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "kernel": f"k_conv_tile ({name}: {ca} up-sampled + {cb} skip -> {cout} channels, "
+                                       f"{n} x {d}^3 voxels)",
+            "achieved": round(tf, 1), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_BF16_TFLOPS, 4),
+            "traffic": None, "avg_launch_us": round(ms * 1e3, 2), "algorithmic_flops_per_launch": flops}
+
+
+def cpu_baseline(p, repeats):
+    """The oracle as it stands: its complete solve of the same workload (same
+    recipe, zero guess, same 1e-10 target, its own order switch), repeated
+    `repeats` times on the host cores; the mean wall time per solve."""
     import numpy as np
 
     from oracle import oracle as O
     threads = min(os.cpu_count() or 1, 16)
     O.set_threads(threads)
     orc = O.Oracle(p.mask, p.h)
-    t0 = time.perf_counter()
-    _, info = orc.solve(p.rho, np.zeros(p.shape), None, tol=1e-300, bc_order="second", max_cycles=cycles)
-    dt = time.perf_counter() - t0
-    per_cycle = dt / max(1, info["cycles"])
+    times, cycles = [], []
+    for _ in range(max(1, repeats)):
+        t0 = time.perf_counter()
+        _, info = orc.solve(p.rho, np.zeros(p.shape), None, tol=1e-10)
+        times.append(time.perf_counter() - t0)
+        cycles.append(info["cycles"])
     return {
-        "value": per_cycle * gpu_cycles * 1e3,
+        "value": float(np.mean(times)) * 1e3,
         "unit": "ms",
         "cores": O.num_threads(),
         "kind": "oracle",
-        "sample": f"{info['cycles']} second-order cycles (plus the two reference norms) of the {p.shape[0]}^3 "
-                  f"holes workload in {dt:.2f} s, scaled to the GPU solve's {gpu_cycles} cycles",
+        "sample": f"{len(times)} complete oracle solves of the {p.shape[0]}^3 holes workload to 1e-10 "
+                  f"({cycles} cycles, {sum(times):.1f} s in all); value = mean wall time per solve",
     }
 
 
@@ -133,6 +198,8 @@ def main():
         return profile_smoother(args)
     if args.copy_calibration:
         return copy_calibration(args)
+    if args.profile_unet:
+        return profile_unet(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
               "(domain decomposition is described, not implemented).", file=sys.stderr)
@@ -268,8 +335,12 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per,
         },
     }
+    try:
+        out["unet_conv_roofline"] = unet_conv_roofline()
+    except Exception as e:  # reported, never hidden
+        out["unet_conv_roofline"] = {"error": str(e)}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, last["cycles"], args.cpu_cycles)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_solves)
     print(json.dumps(out), flush=True)
 
 
