@@ -375,80 +375,124 @@ double read_norm(mg_hierarchy *H) {
     return sqrt(H->norm_host[0]);
 }
 
-mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol, mg_solve_info *info) {
+// The solve loop in phases, so that many hierarchies sharing a stream can
+// advance together with one host synchronisation per cycle (batch.hip):
+// begin (fold, two reference norms) | start (after a sync) | cycle enqueue |
+// cycle finish (after a sync) | end (store).
+void solve_begin(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol, mg_solve_info *info,
+                 SolveState &S) {
     const mg_options &o = H->opt;
-    mg_solve_info tmp;
-    if (!info) info = &tmp;
     memset(info, 0, sizeof(*info));
     info->switched_at_cycle = -1;
-    int order;
+    S = SolveState{};
+    S.info = info;
+    S.phi = phi;
+    S.tol = tol;
     if (o.bc_order == MG_BC_FIRST || o.bc_order == MG_BC_SECOND) {
-        order = o.bc_order;
+        S.order = o.bc_order;
     } else if (H->hold_left > 0) {
-        order = 1;
+        S.order = 1;
         H->hold_left--;
     } else {
-        order = 2;
+        S.order = 2;
     }
-    const bool mixed = o.precision == MG_MIXED;
+    S.mixed = o.precision == MG_MIXED;
     Level &L0 = H->lev[0];
-    const OrderData &od0 = odata(H, 0, order);
+    const OrderData &od0 = odata(H, 0, S.order);
     hipStream_t s = H->stream;
-    ensure_coarse_clean(H, order);
+    ensure_coarse_clean(H, S.order);
     HIPCHK(hipEventRecord(H->ev0, s));
     launch_fold(L0, od0, rho, B, phi, L0.f, L0.x[0], s);
     launch_resnorm(L0, 0, od0, nullptr, L0.f, H->part, H->norm_dev, 1, s);
-    if (mixed) launch_resnorm32(L0, od0, L0.x[0], L0.f, L0.f32, H->part, H->norm_dev, 0, s);
+    if (S.mixed) launch_resnorm32(L0, od0, L0.x[0], L0.f, L0.f32, H->part, H->norm_dev, 0, s);
     else launch_resnorm(L0, 0, od0, L0.x[0], L0.f, H->part, H->norm_dev, 0, s);
     HIPCHK(hipMemcpyAsync(H->norm_host, H->norm_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    double rprev = sqrt(H->norm_host[0]);
-    double rref = sqrt(H->norm_host[1]);
-    info->r0 = rprev;
-    if (rref == 0.0) rref = rprev;
-    info->r_ref = rref;
-    info->history[0] = rprev;
-    info->order_used = order;
-    info->r_final = rprev;
-    mg_status st = MG_NOT_CONVERGED;
-    int parity = 0;
-    if (!(rprev > tol * rref)) {
-        st = std::isfinite(rprev) ? MG_OK : MG_ERR_DIVERGED;
-    } else {
-        for (int n = 1; n <= o.max_cycles; n++) {
-            int np = parity;
-            run_cycle(H, order, parity, mixed, &np);
-            parity = np;
-            const double rn = read_norm(H);
-            info->cycles = n;
-            info->r_final = rn;
-            if (n < 257) info->history[n] = rn;
-            if (!std::isfinite(rn)) {
-                st = MG_ERR_DIVERGED;
-                break;
-            }
-            if (rn <= tol * rref) {
-                st = MG_OK;
-                break;
-            }
-            if (o.bc_order == MG_BC_AUTO && order == 2 && rn / rprev > o.eta) {
-                order = 1;
-                H->hold_left = o.first_order_hold;
-                info->switched_at_cycle = n;
-                info->order_used = 1;
-                ensure_coarse_clean(H, order);
-            }
-            rprev = rn;
-        }
+}
+
+// After the stream has been synchronised: the reference norms.
+void solve_start(mg_hierarchy *H, SolveState &S) {
+    mg_solve_info *info = S.info;
+    S.rprev = sqrt(H->norm_host[0]);
+    S.rref = sqrt(H->norm_host[1]);
+    info->r0 = S.rprev;
+    if (S.rref == 0.0) S.rref = S.rprev;
+    info->r_ref = S.rref;
+    info->history[0] = S.rprev;
+    info->order_used = S.order;
+    info->r_final = S.rprev;
+    S.st = MG_NOT_CONVERGED;
+    S.parity = 0;
+    S.n = 0;
+    S.active = true;
+    if (!(S.rprev > S.tol * S.rref)) {
+        S.st = std::isfinite(S.rprev) ? MG_OK : MG_ERR_DIVERGED;
+        S.active = false;
+    } else if (H->opt.max_cycles < 1) {
+        S.active = false;
     }
-    launch_store(L0, od0, L0.x[parity], phi, s);
-    HIPCHK(hipEventRecord(H->ev1, s));
+}
+
+void solve_cycle_enqueue(mg_hierarchy *H, SolveState &S) {
+    int np = S.parity;
+    run_cycle(H, S.order, S.parity, S.mixed, &np);
+    S.parity = np;
+}
+
+// After the stream has been synchronised: stop test and order switch (Sec. 4).
+void solve_cycle_finish(mg_hierarchy *H, SolveState &S) {
+    const mg_options &o = H->opt;
+    mg_solve_info *info = S.info;
+    const int n = ++S.n;
+    const double rn = sqrt(H->norm_host[0]);
+    info->cycles = n;
+    info->r_final = rn;
+    if (n < 257) info->history[n] = rn;
+    if (!std::isfinite(rn)) {
+        S.st = MG_ERR_DIVERGED;
+        S.active = false;
+        return;
+    }
+    if (rn <= S.tol * S.rref) {
+        S.st = MG_OK;
+        S.active = false;
+        return;
+    }
+    if (o.bc_order == MG_BC_AUTO && S.order == 2 && rn / S.rprev > o.eta) {
+        S.order = 1;
+        H->hold_left = o.first_order_hold;
+        info->switched_at_cycle = n;
+        info->order_used = 1;
+        ensure_coarse_clean(H, S.order);
+    }
+    S.rprev = rn;
+    if (n >= o.max_cycles) S.active = false;
+}
+
+void solve_end(mg_hierarchy *H, SolveState &S) {
+    Level &L0 = H->lev[0];
+    launch_store(L0, odata(H, 0, S.order), L0.x[S.parity], S.phi, H->stream);
+    HIPCHK(hipEventRecord(H->ev1, H->stream));
+    S.info->status = S.st;
+}
+
+mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol, mg_solve_info *info) {
+    mg_solve_info tmp;
+    if (!info) info = &tmp;
+    SolveState S;
+    solve_begin(H, rho, phi, B, tol, info, S);
+    HIPCHK(hipStreamSynchronize(H->stream));
+    solve_start(H, S);
+    while (S.active) {
+        solve_cycle_enqueue(H, S);
+        HIPCHK(hipStreamSynchronize(H->stream));
+        solve_cycle_finish(H, S);
+    }
+    solve_end(H, S);
     HIPCHK(hipEventSynchronize(H->ev1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, H->ev0, H->ev1));
     info->ms = ms;
-    info->status = st;
-    return st;
+    return S.st;
 }
 
 mg_status check_level(const mg_hierarchy *H, int level, int order, bool need_coarser) {
@@ -484,6 +528,43 @@ mg_status guarded(F &&fn) {
 }
 
 }  // namespace
+
+mg_status phase_begin(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol,
+                      mg_solve_info *info, SolveState &S) {
+    return guarded([&]() {
+        solve_begin(H, rho, phi, B, tol, info, S);
+        return MG_OK;
+    });
+}
+
+mg_status phase_start(mg_hierarchy *H, SolveState &S) {
+    return guarded([&]() {
+        solve_start(H, S);
+        return MG_OK;
+    });
+}
+
+mg_status phase_cycle_enqueue(mg_hierarchy *H, SolveState &S) {
+    return guarded([&]() {
+        solve_cycle_enqueue(H, S);
+        return MG_OK;
+    });
+}
+
+mg_status phase_cycle_finish(mg_hierarchy *H, SolveState &S) {
+    return guarded([&]() {
+        solve_cycle_finish(H, S);
+        return MG_OK;
+    });
+}
+
+mg_status phase_end(mg_hierarchy *H, SolveState &S) {
+    return guarded([&]() {
+        solve_end(H, S);
+        return MG_OK;
+    });
+}
+
 }  // namespace mg
 
 using namespace mg;

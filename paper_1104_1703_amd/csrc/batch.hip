@@ -28,9 +28,12 @@ namespace {
 // The persistent cooperative kernel below is switched off: its first GPU runs
 // ended in HSA_STATUS_ERROR_MEMORY_APERTURE_VIOLATION (a generic-address
 // access out of every aperture) and the faulting access has not been found.
-// With it off, mg_solve_batch advances each patch with its own graph-captured
-// cycles (the single-grid path, same kernels and results).
+// With it off, mg_solve_batch advances all patches in lockstep: each round
+// enqueues one graph-captured cycle (the single-grid path, same kernels and
+// results) of every unconverged patch, spread over a few streams, and then
+// synchronises once for all of them.
 constexpr bool kPersistentEnabled = false;
+constexpr int kPatchStreams = 4;  // hardware queues of one process
 constexpr int BNT = 256;
 constexpr int BSEGZ = TZ;  // batch smoother items are one tile deep
 constexpr unsigned long long BARRIER_SPIN_LIMIT = 1ull << 24;
@@ -272,6 +275,9 @@ struct mg_batch {
     const double **pin_ptrs = nullptr;  // [3n]: rho, dirichlet, phi
     int *pin_state = nullptr;           // [3n]: fold/store, order 2, order 1
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // lockstep engine: patch p runs on pstreams[p % size]
+    std::vector<hipStream_t> pstreams;
+    std::vector<hipEvent_t> pevents;
 };
 
 namespace mg {
@@ -413,14 +419,30 @@ mg_batch::Prog finish(mg_batch *B, Planner &P) {
 
 void build_batch(mg_batch *B, const int8_t *const *masks, const int32_t *dims, const double *h) {
     const int n = B->n;
-    // per-patch hierarchies (their own kernels are not used by the batch)
+    BHIP(hipEventCreate(&B->ev0));
+    BHIP(hipEventCreate(&B->ev1));
+    if (!kPersistentEnabled) {
+        // patch streams (default priority), ordered after the batch stream
+        BHIP(hipEventRecord(B->ev0, B->stream));
+        for (int k = 0; k < std::min(n, kPatchStreams); k++) {
+            hipStream_t ps = nullptr;
+            BHIP(hipStreamCreate(&ps));
+            B->pstreams.push_back(ps);
+            hipEvent_t ev = nullptr;
+            BHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            B->pevents.push_back(ev);
+            BHIP(hipStreamWaitEvent(ps, B->ev0, 0));
+        }
+    }
+    // per-patch hierarchies (their own kernels are not used by the persistent engine)
     B->patches.resize(n, nullptr);
     for (int p = 0; p < n; p++) {
         mg_options o = B->opt;
         o.use_graph = kPersistentEnabled ? 0 : 1;
         mg_hierarchy *H = nullptr;
+        void *ps = kPersistentEnabled ? (void *)B->stream : (void *)B->pstreams[p % B->pstreams.size()];
         const mg_status st = mg_create_hierarchy(masks[p], dims[3 * p], dims[3 * p + 1], dims[3 * p + 2], h[p], &o,
-                                                 (void *)B->stream, &H);
+                                                 ps, &H);
         if (st != MG_OK) throw BFail{st};
         B->patches[p] = H;
         if (kPersistentEnabled && (H->nlev[1] < 2 || H->nlev[2] < 2)) {
@@ -429,8 +451,7 @@ void build_batch(mg_batch *B, const int8_t *const *masks, const int32_t *dims, c
         }
     }
     if (!kPersistentEnabled) {
-        BHIP(hipEventCreate(&B->ev0));
-        BHIP(hipEventCreate(&B->ev1));
+        for (hipStream_t ps : B->pstreams) BHIP(hipStreamSynchronize(ps));
         BHIP(hipStreamSynchronize(B->stream));
         return;
     }
@@ -540,8 +561,6 @@ void build_batch(mg_batch *B, const int8_t *const *masks, const int32_t *dims, c
     B->hold.assign(n, 0);
     BHIP(hipHostMalloc((void **)&B->pin_ptrs, 3 * (size_t)n * sizeof(double *), hipHostMallocDefault));
     BHIP(hipHostMalloc((void **)&B->pin_state, 3 * (size_t)n * sizeof(int), hipHostMallocDefault));
-    BHIP(hipEventCreate(&B->ev0));
-    BHIP(hipEventCreate(&B->ev1));
     BHIP(hipStreamSynchronize(B->stream));
 }
 
@@ -589,34 +608,74 @@ void clean_coarse(mg_batch *B, int p) {
             BHIP(hipMemsetAsync(H->lev[l].x[b], 0, H->lev[l].n * sizeof(double), B->stream));
 }
 
-// Batch solve on the single-grid path: every patch runs its own captured
-// cycles on the batch stream, one patch after the other.
-mg_status solve_batch_per_patch(mg_batch *B, const double *const *rho, double *const *phi, const double *const *dir,
-                                double tol, mg_solve_info *infos, double *ms_out) {
+// Batch solve on the single-grid path in lockstep: every round enqueues one
+// cycle of each unconverged patch (its captured graph and 8-byte norm copy)
+// on the patch's stream, then synchronises all patch streams once and
+// applies each patch's stop test and order switch (Sec. 2, Sec. 4).
+mg_status solve_batch_lockstep(mg_batch *B, const double *const *rho, double *const *phi, const double *const *dir,
+                               double tol, mg_solve_info *infos, double *ms_out) {
     const int n = B->n;
     std::vector<mg_solve_info> tmp;
     if (!infos) {
         tmp.resize(n);
         infos = tmp.data();
     }
+    std::vector<SolveState> S(n);
+    auto sync_all = [&]() {
+        for (hipStream_t ps : B->pstreams) BHIP(hipStreamSynchronize(ps));
+    };
     BHIP(hipEventRecord(B->ev0, B->stream));
-    mg_status worst = MG_OK;
+    for (hipStream_t ps : B->pstreams) BHIP(hipStreamWaitEvent(ps, B->ev0, 0));
     for (int p = 0; p < n; p++) {
-        const mg_status st = mg_solve(B->patches[p], rho[p], phi[p], dir ? dir[p] : nullptr, tol, &infos[p]);
-        if (st == MG_ERR_ARG || st == MG_ERR_HIP || st == MG_ERR_ALLOC) return st;
-        if (st < 0 || (st == MG_NOT_CONVERGED && worst == MG_OK)) worst = st;
+        const mg_status st = phase_begin(B->patches[p], rho[p], phi[p], dir ? dir[p] : nullptr, tol, &infos[p], S[p]);
+        if (st != MG_OK) return st;
+    }
+    sync_all();
+    for (int p = 0; p < n; p++) {
+        const mg_status st = phase_start(B->patches[p], S[p]);
+        if (st != MG_OK) return st;
+    }
+    std::vector<int> run;
+    while (true) {
+        run.clear();
+        for (int p = 0; p < n; p++)
+            if (S[p].active) run.push_back(p);
+        if (run.empty()) break;
+        for (int p : run) {
+            const mg_status st = phase_cycle_enqueue(B->patches[p], S[p]);
+            if (st != MG_OK) return st;
+        }
+        sync_all();
+        for (int p : run) {
+            const mg_status st = phase_cycle_finish(B->patches[p], S[p]);
+            if (st != MG_OK) return st;
+        }
+    }
+    for (int p = 0; p < n; p++) {
+        const mg_status st = phase_end(B->patches[p], S[p]);
+        if (st != MG_OK) return st;
+    }
+    for (size_t k = 0; k < B->pstreams.size(); k++) {
+        BHIP(hipEventRecord(B->pevents[k], B->pstreams[k]));
+        BHIP(hipStreamWaitEvent(B->stream, B->pevents[k], 0));
     }
     BHIP(hipEventRecord(B->ev1, B->stream));
     BHIP(hipEventSynchronize(B->ev1));
     float ms = 0.f;
     BHIP(hipEventElapsedTime(&ms, B->ev0, B->ev1));
     if (ms_out) *ms_out = ms;
+    mg_status worst = MG_OK;
+    for (int p = 0; p < n; p++) {
+        infos[p].ms = ms;
+        const mg_status st = S[p].st;
+        if (st < 0 || (st == MG_NOT_CONVERGED && worst == MG_OK)) worst = st;
+    }
     return worst;
 }
 
 mg_status solve_batch(mg_batch *B, const double *const *rho, double *const *phi, const double *const *dir, double tol,
                       mg_solve_info *infos, double *ms_out) {
-    if (!kPersistentEnabled) return solve_batch_per_patch(B, rho, phi, dir, tol, infos, ms_out);
+    if (!kPersistentEnabled) return solve_batch_lockstep(B, rho, phi, dir, tol, infos, ms_out);
     const int n = B->n;
     const mg_options &o = B->opt;
     std::vector<mg_solve_info> tmp;
@@ -744,7 +803,10 @@ extern "C" {
 void mg_destroy_batch(mg_batch *B) {
     if (!B) return;
     if (B->stream) (void)hipStreamSynchronize(B->stream);
+    for (hipStream_t ps : B->pstreams) (void)hipStreamSynchronize(ps);
     for (mg_hierarchy *H : B->patches) mg_destroy_hierarchy(H);
+    for (hipEvent_t ev : B->pevents) (void)hipEventDestroy(ev);
+    for (hipStream_t ps : B->pstreams) (void)hipStreamDestroy(ps);
     for (void *p : B->allocs) {
         if (B->opt.allocator.free) B->opt.allocator.free(p, B->opt.allocator.ctx);
         else if (!B->opt.allocator.alloc) (void)hipFree(p);

@@ -13,23 +13,14 @@
 
 #include "mg.h"
 
+#include "tiles.h"
+
 namespace mg {
 
-constexpr int TX = 32;          // tile width along x (one 256-byte row of doubles)
-constexpr int TY = 8;
-constexpr int TZ = 8;
-constexpr int SEG_TILES_FINE = 2;    // z-tiles per smoother work item on the finest level
-constexpr int SEG_TILES_COARSE = 1;  // ... and on coarse levels (shorter chains, more items)
 constexpr int MAXL = 16;
 constexpr int MAXS = 8;                    // levels handled by the one-workgroup kernel
 constexpr size_t SMALL_MAX_CELLS = 4096;   // first level handled there has at most this many cells
 constexpr int SMALL_LDS_MAX = 160 * 1024;  // LDS of one gfx950 workgroup
-constexpr uint8_t CODE_OFF = 255;
-
-// Smoother work item: origin of an xy tile and a z range [z0, z1).
-struct Seg {
-    int x0, y0, z0, z1;
-};
 
 // Per boundary order data of one level (index 1 = first order, 2 = second).
 struct OrderData {
@@ -86,6 +77,32 @@ struct mg_hierarchy {
 };
 
 namespace mg {
+
+// -------- the solve loop in phases (api.hip) --------
+// State of one solve (Sec. 2 iteration with the Sec. 4 order switch) between
+// its phases; see phase_begin.
+struct SolveState {
+    mg_solve_info *info = nullptr;
+    double *phi = nullptr;
+    double tol = 0.0;
+    int order = 2;
+    bool mixed = false;
+    int parity = 0;
+    int n = 0;  // cycles done
+    double rprev = 0.0, rref = 0.0;
+    mg_status st = MG_NOT_CONVERGED;
+    bool active = false;  // another cycle is due
+};
+// begin: enqueue fold and the two reference norms; start: read them (the
+// caller has synchronised the hierarchy's stream); cycle_enqueue: one cycle
+// with its norm copy; cycle_finish: stop test and order switch (stream
+// synchronised); end: enqueue the store of phi and the end event.
+mg_status phase_begin(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol,
+                      mg_solve_info *info, SolveState &S);
+mg_status phase_start(mg_hierarchy *H, SolveState &S);
+mg_status phase_cycle_enqueue(mg_hierarchy *H, SolveState &S);
+mg_status phase_cycle_finish(mg_hierarchy *H, SolveState &S);
+mg_status phase_end(mg_hierarchy *H, SolveState &S);
 
 // -------- allocation / errors (api.hip) --------
 void *dev_alloc(mg_hierarchy *H, size_t bytes);

@@ -18,6 +18,7 @@
 // steps ahead are in flight in registers while a step computes, so the
 // compute phases touch LDS only.  Net HBM traffic per pass: one read of x, f,
 // code/diagonal and one write of x.
+#include "mg_core.h"
 #include "smooth_core.h"
 
 namespace mg {

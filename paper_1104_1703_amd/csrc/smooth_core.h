@@ -4,7 +4,9 @@
 
 #include <type_traits>
 
-#include "mg_core.h"
+#include <hip/hip_runtime.h>
+
+#include "tiles.h"
 
 namespace mg {
 namespace rb {

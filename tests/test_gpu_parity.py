@@ -402,3 +402,26 @@ def test_batch_per_patch_engine_matches_oracle(mg, opts):
         assert info["cycles"] == rinfo["cycles"] and info["switched_at"] == rinfo["switched_at"], p.name
         assert relerr(x, ref, p.mask == 1) <= TOL, p.name
     B.close()
+
+
+def test_batch_lockstep_equals_single_solves_and_repeats(mg):
+    """24 patches over the engine's streams, solved twice (the second solve
+    starts in first order where the first switched): every patch equals its
+    own single-grid solve bit for bit, with the same cycles and switch."""
+    probs = gen.patch_problems(count=22, seed=12) + [gen.porous_problem(n=64, seed=4), gen.sphere_problem(32)]
+    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs])
+    singles = [mg.Hierarchy(dev(p.mask), p.h) for p in probs]
+    rhos = [dev(p.rho) for p in probs]
+    dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
+    for rep in range(2):
+        print(f"[case] lockstep batch of {len(probs)}, solve {rep}", flush=True)
+        got, infos, ms = B.solve(rhos, dirichlets=dirs, tol=1e-10)
+        assert ms > 0
+        for p, H, x, info, r, d in zip(probs, singles, got, infos, rhos, dirs):
+            ref, rinfo = H.solve(r, None, d, tol=1e-10)
+            assert info["status"] == rinfo["status"] == 0, p.name
+            assert (info["cycles"], info["switched_at"], info["order_used"]) == \
+                (rinfo["cycles"], rinfo["switched_at"], rinfo["order_used"]), p.name
+            assert np.array_equal(host(x), host(ref)), p.name
+    assert any(i["switched_at"] > 0 for i in infos) or any(i["order_used"] == 1 for i in infos)
+    B.close()

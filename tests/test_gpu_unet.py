@@ -394,7 +394,7 @@ def test_trained_network_saves_cycles(mg):
     cases = [(gen.holes_problem(n=64, seed=s), 1) for s in (30000, 30001, 30002)]
     cases.append((gen.holes_problem(n=256, seed=2), 4))
     for p, stride in cases:
-        _case("trained guess", name=p.name, stride=stride)
+        _case("trained guess", problem=p.name, stride=stride)
         rho = torch.from_numpy(p.rho).cuda()
         mask = torch.from_numpy(p.mask).cuda()
         H = mg.Hierarchy(mask, p.h)
