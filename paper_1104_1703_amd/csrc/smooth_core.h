@@ -35,15 +35,18 @@ struct PlaneRegs {
     unsigned ok;  // validity bits: x elements in bits 0..XR-1, f/d elements above
 };
 
-// LDS of one work item: a 4-plane ring of x (2-cell halo), and 3-plane rings
+// LDS of one work item: a 5-plane ring of x (2-cell halo), and 4-plane rings
 // of f and the diagonal (1-cell halo; the finest level keeps its 1-byte
-// neighbour code instead of a diagonal).
+// neighbour code instead of a diagonal).  One ring plane more than a step
+// touches lets a step commit its new plane while the previous step's black
+// half-sweep may still read the oldest one, so a step needs two barriers.
+constexpr int XS = 5, FS = 4;
 template <typename T, bool FINE>
 struct RbgsLds {
     using DT = typename std::conditional<FINE, uint8_t, T>::type;
-    T x[4][PN];
-    T f[3][QN];
-    DT d[3][QN];
+    T x[XS][PN];
+    T f[FS][QN];
+    DT d[FS][QN];
 };
 
 // One full red-black pass over one work item (see the file comment of
@@ -100,11 +103,12 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
         }
     };
     // registers -> LDS ring slot of plane k (zeros where invalid)
-    auto slot3 = [](int k) { return (k + 3) % 3; };  // k >= -2
+    auto xslot = [](int k) { return (k + 2 * XS) % XS; };  // k >= -2
+    auto fslot = [](int k) { return (k + 2 * FS) % FS; };
     auto commit = [&](const PlaneRegs<T, FINE> &r, int k) {
-        T *dx = sx[k & 3];
-        T *df = sf[slot3(k)];
-        DT *dd = sd[slot3(k)];
+        T *dx = sx[xslot(k)];
+        T *df = sf[fslot(k)];
+        DT *dd = sd[fslot(k)];
 #pragma unroll
         for (int q = 0; q < XR; q++) {
             const int e = tid + q * NT;
@@ -125,11 +129,11 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
     // Relax colour `col` of plane k on [lo, PX-lo) x [lo, PY-lo) (x-plane coords).
     auto relax = [&](int k, int col, int lo) {
         if (k < 0 || k >= nz) return;
-        T *c = sx[k & 3];
-        const T *dn = sx[(k - 1) & 3];
-        const T *up = sx[(k + 1) & 3];
-        const T *fq = sf[slot3(k)];
-        const DT *dq = sd[slot3(k)];
+        T *c = sx[xslot(k)];
+        const T *dn = sx[xslot(k - 1)];
+        const T *up = sx[xslot(k + 1)];
+        const T *fq = sf[fslot(k)];
+        const DT *dq = sd[fslot(k)];
         const int half = (PX - 2 * lo) >> 1;
         const int rows = PY - 2 * lo;
         for (int e = tid; e < half * rows; e += NT) {
@@ -152,7 +156,7 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
     };
 
     auto store = [&](int k) {
-        const T *c = sx[k & 3];
+        const T *c = sx[xslot(k)];
         for (int e = tid; e < BX * BY; e += NT) {
             const int u = 2 + e % BX, v = 2 + e / BX;
             const int gx = gx0 + u, gy = gy0 + v;
@@ -163,28 +167,33 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
     // Fully unrolled march over at most SEGZ planes (shorter items skip the
     // stores past z1): planes z0-2 .. z0+SEGZ+1 are committed one per step,
     // each refilled register set fetching the plane PF steps ahead, so PF
-    // planes of loads stay in flight and every wait count is exact.
+    // planes of loads stay in flight and every wait count is exact.  Step k+2
+    // commits plane k+2, relaxes red of plane k+1 and stores plane k-1 (black
+    // since the previous step), then relaxes black of plane k; the last step
+    // only stores.
     constexpr int NSTEP = SEGZ + 4;
     PlaneRegs<T, FINE> r[PF];
 #pragma unroll
     for (int q = 0; q < PF; q++) fetch(r[q], z0 - 2 + q);
 #pragma unroll
-    for (int st = 0; st < NSTEP; st++) {
+    for (int st = 0; st <= NSTEP; st++) {
         const int pk = z0 - 2 + st;  // plane committed in this step
-        commit(r[st % PF], pk);
-        if (st + PF < NSTEP) fetch(r[st % PF], pk + PF);
+        const int k = pk - 2;
+        if (st < NSTEP) {
+            commit(r[st % PF], pk);
+            if (st + PF < NSTEP) fetch(r[st % PF], pk + PF);
+        }
         __syncthreads();
         if (st == 3) {
             relax(z0 - 1, 0, 1);
             relax(z0, 0, 1);
-            __syncthreads();
         } else if (st > 3) {
-            const int k = pk - 2;
-            relax(k + 1, 0, 1);
+            if (st < NSTEP) relax(k + 1, 0, 1);
+            if (k - 1 >= z0 && k - 1 < z1) store(k - 1);
+        }
+        if (st > 3 && st < NSTEP) {
             __syncthreads();
             relax(k, 1, 2);
-            __syncthreads();
-            if (k < z1) store(k);
         }
     }
 }
