@@ -497,8 +497,10 @@ void build_batch(mg_batch *B, const int8_t *const *masks, const int32_t *dims, c
             for (int q = 0; q < S.n; q++) {
                 const Level &L = H->lev[ls + q];
                 S.nx[q] = L.nx; S.ny[q] = L.ny; S.nz[q] = L.nz;
-                S.mx[q] = (0x100000000ull + (unsigned)L.nx - 1) / (unsigned)L.nx;
-                S.mxy[q] = (0x100000000ull + (unsigned)(L.nx * L.ny) - 1) / (unsigned)(L.nx * L.ny);
+                S.mx[q] = small::div_magic((unsigned)L.nx);
+                S.mxy[q] = small::div_magic((unsigned)(L.nx * L.ny));
+                S.mh[q] = small::div_magic((unsigned)((L.nx + 1) / 2));
+                S.mhy[q] = small::div_magic((unsigned)((L.nx + 1) / 2 * L.ny));
                 S.h2[q] = L.h * L.h;
                 S.ih2[q] = 1.0 / (L.h * L.h);
                 S.d[q] = L.od[o].d;

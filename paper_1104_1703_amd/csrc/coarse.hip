@@ -4,7 +4,7 @@
 // one launch per half-sweep would cost more than the work.  This kernel runs
 // one whole multigrid call MG(ls) (Sec. 2 enumerated recipe, with N_cycles
 // recursive calls per level and n_coarse passes on the deepest level) for the
-// levels ls..last inside one 256-thread workgroup, with every level's x, f
+// levels ls..last inside one 1024-thread workgroup, with every level's x, f
 // and diagonal resident in LDS.  Red-black Gauss-Seidel is done in place with
 // a barrier between the colours (a colour only reads the other colour).
 #include <algorithm>
@@ -17,10 +17,12 @@ namespace {
 
 using namespace small;
 
+constexpr int NTC = 1024;  // 16 waves: four per SIMD to hide LDS and FP64 latency
+
 template <typename T>
-__global__ __launch_bounds__(NT) void k_coarse(SmallLevels<T> S) {
+__global__ __launch_bounds__(NTC) void k_coarse(SmallLevels<T> S) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    small_tail<T>(reinterpret_cast<T *>(smem_raw), S, S.f0, S.x0, S.load_x != 0);
+    small_tail<T, NTC>(reinterpret_cast<T *>(smem_raw), S, S.f0, S.x0, S.load_x != 0);
 }
 
 template <typename T>
@@ -35,8 +37,10 @@ void launch_impl(const mg_hierarchy *H, int order, int ls, bool zero_start, cons
         S.nx[q] = L.nx;
         S.ny[q] = L.ny;
         S.nz[q] = L.nz;
-        S.mx[q] = (0x100000000ull + (unsigned)L.nx - 1) / (unsigned)L.nx;
-        S.mxy[q] = (0x100000000ull + (unsigned)(L.nx * L.ny) - 1) / (unsigned)(L.nx * L.ny);
+        S.mx[q] = div_magic((unsigned)L.nx);
+        S.mxy[q] = div_magic((unsigned)(L.nx * L.ny));
+        S.mh[q] = div_magic((unsigned)((L.nx + 1) / 2));
+        S.mhy[q] = div_magic((unsigned)((L.nx + 1) / 2 * L.ny));
         S.h2[q] = (T)(L.h * L.h);
         S.ih2[q] = (T)(1.0 / (L.h * L.h));
         S.d[q] = f32 ? (const T *)L.od[order].d32 : (const T *)L.od[order].d;
@@ -51,7 +55,7 @@ void launch_impl(const mg_hierarchy *H, int order, int ls, bool zero_start, cons
     S.n_cycles = H->opt.n_cycles;
     S.n_coarse = H->opt.n_coarse_sweeps;
     const size_t bytes = (size_t)off * sizeof(T);
-    k_coarse<T><<<1, NT, bytes, s>>>(S);
+    k_coarse<T><<<1, NTC, bytes, s>>>(S);
 }
 
 }  // namespace

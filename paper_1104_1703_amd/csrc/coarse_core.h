@@ -15,6 +15,7 @@ struct SmallLevels {
     int n;                 // number of levels held (ls..last)
     int nx[MAXS], ny[MAXS], nz[MAXS];
     unsigned long long mx[MAXS], mxy[MAXS];  // division magics, see qdiv
+    unsigned long long mh[MAXS], mhy[MAXS];  // ... of hx = ceil(nx / 2) and hx * ny
     T h2[MAXS];            // h^2 per level
     T ih2[MAXS];           // 1/h^2 per level
     const T *d[MAXS];      // diagonal per level (global), 0 off the domain
@@ -30,8 +31,13 @@ struct Lv {
     T *x, *f, *d;
     int nx, ny, nz, n;
     unsigned long long mx, mxy;  // ceil(2^32 / nx), ceil(2^32 / (nx*ny))
+    int hx;                      // cells of one colour per row, at most: ceil(nx / 2)
+    unsigned long long mh, mhy;  // ceil(2^32 / hx), ceil(2^32 / (hx*ny))
     T h2, ih2;
 };
+
+// Division magics of a level for the host: ceil(2^32 / v).
+inline unsigned long long div_magic(unsigned v) { return (0x100000000ull + v - 1) / v; }
 
 // Exact quotient e / d for e * d < 2^32, with m = ceil(2^32 / d): the error
 // of e * m / 2^32 is below e / 2^32 < 1/d, too small to reach the next integer.
@@ -59,14 +65,20 @@ __device__ __forceinline__ T nb_sum(const T *x, int i, int j, int k, int nx, int
     return (xm + xp) + (ym + yp) + (zm + zp);
 }
 
-template <typename T>
+// Red-black passes; each half-sweep visits only the cells of its colour
+// (slot m of row (j, k) is cell i = 2m + ((col + j + k) mod 2)).
+template <typename T, int NTH>
 __device__ void smooth(const Lv<T> &L, int passes) {
+    const int slots = L.hx * L.ny * L.nz;
     for (int p = 0; p < passes; p++)
         for (int col = 0; col < 2; col++) {
-            for (int e = threadIdx.x; e < L.n; e += NT) {
-                int i, j, k;
-                cell_ijk(L, e, i, j, k);
-                if (((i + j + k) & 1) != col) continue;
+            for (int s = threadIdx.x; s < slots; s += NTH) {
+                const int k = qdiv(s, L.mhy);
+                const int r = s - k * L.hx * L.ny;
+                const int j = qdiv(r, L.mh);
+                const int i = 2 * (r - j * L.hx) + ((col + j + k) & 1);
+                if (i >= L.nx) continue;
+                const int e = (k * L.ny + j) * L.nx + i;
                 const T d = L.d[e];
                 if (d == T(0)) continue;
                 L.x[e] = (nb_sum(L.x, i, j, k, L.nx, L.ny, L.nz) - L.h2 * L.f[e]) / d;
@@ -76,9 +88,9 @@ __device__ void smooth(const Lv<T> &L, int passes) {
 }
 
 // f_c = -(1/8) sum over active children of (L x - f); x_c = 0.
-template <typename T>
+template <typename T, int NTH>
 __device__ void restrict_to(const Lv<T> &L, const Lv<T> &C) {
-    for (int E = threadIdx.x; E < C.n; E += NT) {
+    for (int E = threadIdx.x; E < C.n; E += NTH) {
         int I, J, K;
         cell_ijk(C, E, I, J, K);
         T s = T(0);
@@ -99,10 +111,10 @@ __device__ void restrict_to(const Lv<T> &L, const Lv<T> &C) {
 }
 
 // x += P2(x_c) on active cells (weights 3/4, 1/4 per axis; 0 off the box).
-template <typename T>
+template <typename T, int NTH>
 __device__ void prolong_from(const Lv<T> &L, const Lv<T> &C) {
     const T w[2] = {T(0.75), T(0.25)};
-    for (int e = threadIdx.x; e < L.n; e += NT) {
+    for (int e = threadIdx.x; e < L.n; e += NTH) {
         if (L.d[e] == T(0)) continue;
         int i, j, k;
         cell_ijk(L, e, i, j, k);
@@ -129,12 +141,12 @@ __device__ void prolong_from(const Lv<T> &L, const Lv<T> &C) {
 // One call MG(ls) for the levels held in S, all resident in the memory at
 // `sm` (LDS, or global memory for levels too large for LDS); f0 is level ls's
 // right-hand side and x0 its iterate (in/out), started from zero unless
-// load_x.  Called by all NT threads of a block.
-template <typename T>
+// load_x.  Called by all NTH threads of a block.
+template <typename T, int NTH = NT>
 __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, bool load_x) {
     // level descriptors live in LDS (dynamic indexing without private memory)
     __shared__ int s_nx[MAXS], s_ny[MAXS], s_nz[MAXS], s_off[MAXS];
-    __shared__ unsigned long long s_mx[MAXS], s_mxy[MAXS];
+    __shared__ unsigned long long s_mx[MAXS], s_mxy[MAXS], s_mh[MAXS], s_mhy[MAXS];
     __shared__ T s_h2[MAXS], s_ih2[MAXS];
     if (threadIdx.x < (unsigned)S.n) {
         const int l = threadIdx.x;
@@ -144,6 +156,8 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
         s_off[l] = S.off[l];
         s_mx[l] = S.mx[l];
         s_mxy[l] = S.mxy[l];
+        s_mh[l] = S.mh[l];
+        s_mhy[l] = S.mhy[l];
         s_h2[l] = S.h2[l];
         s_ih2[l] = S.ih2[l];
     }
@@ -156,6 +170,9 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
         v.n = v.nx * v.ny * v.nz;
         v.mx = s_mx[l];
         v.mxy = s_mxy[l];
+        v.hx = (v.nx + 1) >> 1;
+        v.mh = s_mh[l];
+        v.mhy = s_mhy[l];
         v.x = sm + s_off[l];
         v.f = v.x + v.n;
         v.d = v.f + v.n;
@@ -166,7 +183,7 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
     for (int l = 0; l < S.n; l++) {
         const Lv<T> v = level(l);
         const T *dg = S.d[l];
-        for (int e = threadIdx.x; e < v.n; e += NT) {
+        for (int e = threadIdx.x; e < v.n; e += NTH) {
             v.d[e] = dg[e];
             v.x[e] = (l == 0 && load_x) ? x0[e] : T(0);
             if (l == 0) v.f[e] = f0[e];
@@ -183,12 +200,12 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
     while (true) {
         if (down) {
             if (l == last) {
-                smooth(level(l), S.n_coarse);
+                smooth<T, NTH>(level(l), S.n_coarse);
                 down = false;
                 continue;
             }
-            smooth(level(l), S.n_pre);
-            restrict_to(level(l), level(l + 1));
+            smooth<T, NTH>(level(l), S.n_pre);
+            restrict_to<T, NTH>(level(l), level(l + 1));
             visits &= ~(7u << (3 * (l + 1)));
             l++;
             continue;
@@ -200,12 +217,12 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
             down = true;
             continue;
         }
-        prolong_from(level(l - 1), level(l));
-        smooth(level(l - 1), S.n_post);
+        prolong_from<T, NTH>(level(l - 1), level(l));
+        smooth<T, NTH>(level(l - 1), S.n_post);
         l--;
     }
     const Lv<T> top = level(0);
-    for (int e = threadIdx.x; e < top.n; e += NT) x0[e] = top.x[e];
+    for (int e = threadIdx.x; e < top.n; e += NTH) x0[e] = top.x[e];
     __syncthreads();
 }
 
