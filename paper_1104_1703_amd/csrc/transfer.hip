@@ -112,6 +112,119 @@ __global__ __launch_bounds__(NT) void k_restrict(const int *__restrict__ ctiles,
                            x, f, fc);
 }
 
+// Residual and R1 restriction from the finest level as a march: one block per
+// smoother work item (a TX x TY column of cells over a z range of tile
+// pairs), thread (u, v) of the tile cross-section owning one cell per plane.
+// Planes of x pass through a 4-plane LDS ring with a 1-cell halo (each loaded
+// once per item, PF planes of loads in flight); f and the neighbour code of
+// the thread's own cell stay in registers.  Each cell's residual is summed
+// with its x and y partners by lane exchanges (the two rows of a wave are the
+// two y children), and planes 2K and 2K+1 complete coarse plane K:
+// f_c = -(1/8) sum of the 8 children's residuals on active coarse cells, 0 on
+// inactive ones.  Only coarse cells above active finest tiles are written.
+namespace rm {
+constexpr int PX = TX + 2, PY = TY + 2, PN = PX * PY;  // x plane, 1-cell halo
+constexpr int XR = (PN + NT - 1) / NT;
+constexpr int PF = 4;
+constexpr int XS = 4;
+}  // namespace rm
+
+template <typename T, int SEGZ>
+__global__ __launch_bounds__(NT) void k_restrict_march(const T *__restrict__ x, const T *__restrict__ f,
+                                                       const uint8_t *__restrict__ code, int nx, int ny, int nz,
+                                                       T ih2, const Seg *__restrict__ segs, int nsegs,
+                                                       const T *__restrict__ cd, int cnx, int cny,
+                                                       T *__restrict__ fc) {
+    using namespace rm;
+    __shared__ T xs[XS][PN];
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= nsegs) return;
+    const Seg sg = segs[item];
+    const int tid = threadIdx.x;
+    const int gx0 = sg.x0 - 1, gy0 = sg.y0 - 1;
+    const int z0 = max(sg.z0, 0), z1 = min(sg.z1, nz);
+    const size_t plane = (size_t)nx * ny;
+    // plane elements of this thread (x with halo) and its own cell
+    int xoff[XR];
+    unsigned okx = 0;
+#pragma unroll
+    for (int q = 0; q < XR; q++) {
+        const int e = min(tid + q * NT, PN - 1);
+        const int gx = gx0 + e % PX, gy = gy0 + e / PX;
+        okx |= (unsigned)((tid + q * NT < PN) && gx >= 0 && gx < nx && gy >= 0 && gy < ny) << q;
+        xoff[q] = min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1);
+    }
+    const int u = tid % TX, v = tid / TX;
+    const int ci = sg.x0 + u, cj = sg.y0 + v;
+    const bool own = ci < nx && cj < ny;
+    const int coff = min(cj, ny - 1) * nx + min(ci, nx - 1);
+    const int q0 = (v + 1) * PX + (u + 1);  // own cell in the x plane
+
+    struct Regs {
+        T x[XR];
+        T f;
+        uint8_t c;
+        bool kin;
+    };
+    auto fetch = [&](Regs &r, int k) {
+        r.kin = k >= 0 && k < nz;
+        const size_t base = (size_t)min(max(k, 0), nz - 1) * plane;
+#pragma unroll
+        for (int q = 0; q < XR; q++) r.x[q] = x[base + xoff[q]];
+        r.f = f[base + coff];
+        r.c = code[base + coff];
+    };
+    auto commit = [&](const Regs &r, int k) {
+        T *d = xs[(k + XS) % XS];
+#pragma unroll
+        for (int q = 0; q < XR; q++)
+            if (tid + q * NT < PN) d[tid + q * NT] = (r.kin && ((okx >> q) & 1u)) ? r.x[q] : T(0);
+    };
+
+    // steps commit planes z0-1 .. z1; step of plane p computes the residual
+    // of plane p-1 (f and code of plane p-1 held from the previous step)
+    constexpr int NSTEP = SEGZ + 2;
+    Regs r[PF];
+#pragma unroll
+    for (int q = 0; q < PF; q++) fetch(r[q], z0 - 1 + q);
+    T hold_f = T(0), acc = T(0);
+    uint8_t hold_c = CODE_OFF;
+#pragma unroll
+    for (int st = 0; st < NSTEP; st++) {
+        const int p = z0 - 1 + st;
+        const T fprev = hold_f;
+        const uint8_t cprev = hold_c;
+        hold_f = r[st % PF].f;
+        hold_c = (r[st % PF].kin && own) ? r[st % PF].c : CODE_OFF;
+        commit(r[st % PF], p);
+        if (st + PF < NSTEP) fetch(r[st % PF], p + PF);
+        __syncthreads();
+        const int k = p - 1;
+        if (k >= z0 && k < z1) {  // uniform; k = z0 .. z1-1 at steps 2 .. z1-z0+1
+            const T *xc = xs[(k + XS) % XS];
+            const T *xd = xs[(k - 1 + XS) % XS];
+            const T *xu = xs[(k + 1 + XS) % XS];
+            T rr = T(0);
+            if (cprev != CODE_OFF) {
+                const T d = T(12 - (int)cprev);
+                const T sum = ((xc[q0 - 1] + xc[q0 + 1]) + (xc[q0 - PX] + xc[q0 + PX])) + (xd[q0] + xu[q0]);
+                rr = (sum - d * xc[q0]) * ih2 - fprev;
+            }
+            T s2 = rr + __shfl_xor(rr, 1);
+            s2 += __shfl_xor(s2, 32);
+            if ((k & 1) == 0) {
+                acc = s2;
+            } else {
+                acc += s2;
+                if ((u & 1) == 0 && (v & 1) == 0 && own) {
+                    const size_t P = ((size_t)(k >> 1) * cny + (cj >> 1)) * cnx + (ci >> 1);
+                    fc[P] = cd[P] != T(0) ? -acc / T(8) : T(0);
+                }
+            }
+        }
+    }
+}
+
 template <typename T, bool FINE>
 __global__ __launch_bounds__(NT) void k_prolong(const int *__restrict__ tiles, int ntiles, int ntx, int nty, int nx,
                                                 int ny, int nz, const uint8_t *__restrict__ code,
@@ -213,11 +326,12 @@ void launch_restrict(const Level &L, const Level &C, int level, int order, const
     const OrderData &co = C.od[order];
     if (!co.ntiles) return;
     const double ih2 = 1.0 / (L.h * L.h);
-    if (level == 0)
-        k_restrict<double, true><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny, C.nz,
-                                                                 co.d, L.nx, L.ny, L.nz, ih2, L.code, nullptr, x, f,
-                                                                 fc);
-    else
+    if (level == 0) {
+        const OrderData &fo = L.od[2];
+        if (fo.nsegs)
+            k_restrict_march<double, SEG_TILES_FINE * TZ><<<grid8(fo.nsegs), NT, 0, s>>>(
+                x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.nsegs, co.d, C.nx, C.ny, fc);
+    } else
         k_restrict<double, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny,
                                                                   C.nz, co.d, L.nx, L.ny, L.nz, ih2, nullptr,
                                                                   L.od[order].d, x, f, fc);
@@ -228,11 +342,12 @@ void launch_restrict32(const Level &L, const Level &C, int level, int order, con
     const OrderData &co = C.od[order];
     if (!co.ntiles) return;
     const float ih2 = (float)(1.0 / (L.h * L.h));
-    if (level == 0)
-        k_restrict<float, true><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny, C.nz,
-                                                                co.d32, L.nx, L.ny, L.nz, ih2, L.code, nullptr, x, f,
-                                                                fc);
-    else
+    if (level == 0) {
+        const OrderData &fo = L.od[2];
+        if (fo.nsegs)
+            k_restrict_march<float, SEG_TILES_FINE * TZ><<<grid8(fo.nsegs), NT, 0, s>>>(
+                x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.nsegs, co.d32, C.nx, C.ny, fc);
+    } else
         k_restrict<float, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny, C.nz,
                                                                  co.d32, L.nx, L.ny, L.nz, ih2, nullptr,
                                                                  L.od[order].d32, x, f, fc);
