@@ -225,6 +225,68 @@ __global__ __launch_bounds__(NT) void k_restrict_march(const T *__restrict__ x, 
     }
 }
 
+// P2 prolongation and correction onto the finest level as one block per
+// smoother work item: the coarse planes the item needs (its 16 x 4 coarse
+// footprint with a 1-cell halo, planes z0/2 - 1 .. z1/2) are staged in LDS
+// once; thread (u, v) owns one fine column, issues the loads of its whole
+// column first, then adds the interpolated correction on active cells (same
+// weights and summation order as prolong_col).
+template <typename T, int SEGZ>
+__global__ __launch_bounds__(NT) void k_prolong_march(const uint8_t *__restrict__ code, const T *__restrict__ xc,
+                                                      int cnx, int cny, int cnz, T *__restrict__ x, int nx, int ny,
+                                                      int nz, const Seg *__restrict__ segs, int nsegs) {
+    constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CP = CX * CY;
+    constexpr int NCZ = SEGZ / 2 + 2;
+    __shared__ T cs[NCZ][CP];
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= nsegs) return;
+    const Seg sg = segs[item];
+    const int tid = threadIdx.x;
+    const int z0 = max(sg.z0, 0), z1 = min(sg.z1, nz);  // even (tile-aligned, even dims)
+    const int I0 = sg.x0 / 2 - 1, J0 = sg.y0 / 2 - 1, K0 = z0 / 2 - 1;
+    const size_t cpl = (size_t)cnx * cny, pl = (size_t)nx * ny;
+    for (int e = tid; e < NCZ * CP; e += NT) {
+        const int kz = e / CP, r = e - kz * CP;
+        const int ci = I0 + r % CX, cj = J0 + r / CX, K = K0 + kz;
+        const bool ok = ci >= 0 && ci < cnx && cj >= 0 && cj < cny && K >= 0 && K < cnz;
+        const size_t P = (size_t)clampi(K, cnz - 1) * cpl + (size_t)clampi(cj, cny - 1) * cnx + clampi(ci, cnx - 1);
+        const T vv = xc[P];
+        cs[kz][r] = ok ? vv : T(0);
+    }
+    const int u = tid % TX, v = tid / TX;
+    const int i = sg.x0 + u, j = sg.y0 + v;
+    const bool own = i < nx && j < ny;
+    const size_t c0 = (size_t)min(j, ny - 1) * nx + min(i, nx - 1);
+    T xv[SEGZ];
+    uint8_t cv[SEGZ];
+#pragma unroll
+    for (int q = 0; q < SEGZ; q++) {
+        const size_t b = (size_t)min(z0 + q, nz - 1) * pl;
+        xv[q] = x[b + c0];
+        cv[q] = code[b + c0];
+    }
+    __syncthreads();
+    const int a0 = u / 2 + 1, b0 = v / 2 + 1;  // parent in the staged footprint
+    const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1;
+    const T w4[2] = {T(0.75), T(0.25)};
+#pragma unroll
+    for (int q = 0; q < SEGZ; q++) {
+        const int k = z0 + q;
+        if (!own || k >= z1 || cv[q] == CODE_OFF) continue;
+        const int pk = (k >> 1) - K0;
+        const int nk = pk + ((k & 1) ? 1 : -1);
+        T s = T(0);
+#pragma unroll
+        for (int cz = 0; cz < 2; cz++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+                    s += w4[a] * w4[b] * w4[cz] * cs[cz ? nk : pk][(b0 + b * sy) * CX + (a0 + a * sx)];
+        x[(size_t)k * pl + c0] = xv[q] + s;
+    }
+}
+
 template <typename T, bool FINE>
 __global__ __launch_bounds__(NT) void k_prolong(const int *__restrict__ tiles, int ntiles, int ntx, int nty, int nx,
                                                 int ny, int nz, const uint8_t *__restrict__ code,
@@ -357,10 +419,11 @@ void launch_prolong(const Level &L, const Level &C, int level, int order, const 
                     hipStream_t s) {
     const OrderData &od = L.od[level == 0 ? 2 : order];
     if (!od.ntiles) return;
-    if (level == 0)
-        k_prolong<double, true><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
-                                                                L.code, nullptr, xc, C.nx, C.ny, C.nz, x);
-    else
+    if (level == 0) {
+        if (od.nsegs)
+            k_prolong_march<double, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(L.code, xc, C.nx, C.ny, C.nz, x,
+                                                                                   L.nx, L.ny, L.nz, od.segs, od.nsegs);
+    } else
         k_prolong<double, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
                                                                  nullptr, od.d, xc, C.nx, C.ny, C.nz, x);
 }
@@ -369,10 +432,11 @@ void launch_prolong32(const Level &L, const Level &C, int level, int order, cons
                       hipStream_t s) {
     const OrderData &od = L.od[level == 0 ? 2 : order];
     if (!od.ntiles) return;
-    if (level == 0)
-        k_prolong<float, true><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
-                                                               L.code, nullptr, xc, C.nx, C.ny, C.nz, x);
-    else
+    if (level == 0) {
+        if (od.nsegs)
+            k_prolong_march<float, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(L.code, xc, C.nx, C.ny, C.nz, x,
+                                                                                   L.nx, L.ny, L.nz, od.segs, od.nsegs);
+    } else
         k_prolong<float, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
                                                                 nullptr, od.d32, xc, C.nx, C.ny, C.nz, x);
 }
