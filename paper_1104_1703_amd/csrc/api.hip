@@ -80,9 +80,15 @@ void build_lists(mg_hierarchy *H, int l, int order) {
                     continue;
                 }
                 int t1 = tz;
-                const int seg_tiles = (l == 0) ? SEG_TILES_FINE : SEG_TILES_COARSE;
-                while (t1 < L.ntz && hf[(t1 * L.nty + ty) * L.ntx + tx] && t1 - tz < seg_tiles) t1++;
-                segs.push_back(Seg{tx * TX, ty * TY, tz * TZ, std::min(L.nz, t1 * TZ)});
+                if (l == 0) {
+                    while (t1 < L.ntz && hf[(t1 * L.nty + ty) * L.ntx + tx] && t1 - tz < SEG_TILES_FINE) t1++;
+                    segs.push_back(Seg{tx * TX, ty * TY, tz * TZ, std::min(L.nz, t1 * TZ)});
+                } else {
+                    // coarse levels: one active tile cut into SEGZ_COARSE-plane items
+                    t1 = tz + 1;
+                    for (int z = tz * TZ; z < std::min(L.nz, t1 * TZ); z += SEGZ_COARSE)
+                        segs.push_back(Seg{tx * TX, ty * TY, z, std::min(std::min(L.nz, t1 * TZ), z + SEGZ_COARSE)});
+                }
                 tz = t1;
             }
         }

@@ -50,7 +50,7 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
         k_rbgs<double, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
                                                              od.segs, od.nsegs);
     else
-        k_rbgs<double, false, SEG_TILES_COARSE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz, h2,
+        k_rbgs<double, false, SEGZ_COARSE><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz, h2,
                                                               od.segs, od.nsegs);
 }
 
@@ -62,7 +62,7 @@ void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *
         k_rbgs<float, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
                                                             od.segs, od.nsegs);
     else
-        k_rbgs<float, false, SEG_TILES_COARSE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d32, L.nx, L.ny, L.nz, h2,
+        k_rbgs<float, false, SEGZ_COARSE><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d32, L.nx, L.ny, L.nz, h2,
                                                              od.segs, od.nsegs);
 }
 

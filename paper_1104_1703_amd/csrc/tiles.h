@@ -11,7 +11,7 @@ constexpr int TX = 32;  // tile width along x (one 256-byte row of doubles)
 constexpr int TY = 8;
 constexpr int TZ = 8;
 constexpr int SEG_TILES_FINE = 2;    // z-tiles per smoother work item on the finest level
-constexpr int SEG_TILES_COARSE = 1;  // ... and on coarse levels (shorter chains, more items)
+constexpr int SEGZ_COARSE = 4;       // planes per smoother work item on coarse levels (more items)
 constexpr uint8_t CODE_OFF = 255;    // finest-level code of an inactive cell
 
 // Smoother work item: origin of an xy tile and a z range [z0, z1).
