@@ -96,8 +96,9 @@ void mg_default_options(mg_options *o);
  *              read during the call; the caller may free it afterwards.
  *   h        : cell width (> 0).  opt: NULL = defaults.  out: receives the
  *              handle, to be released with mg_destroy_hierarchy.
- * Errors: MG_ERR_ARG for NULL pointers, non-positive dims or h, mask values
- * other than +-1, or a non-inactive outermost cell layer; MG_ERR_NO_ACTIVE
+ * Errors: MG_ERR_ARG for NULL pointers, non-positive dims or h, a box of
+ * 2^34 cells or more or a z-plane of 2^28 cells or more, mask values other
+ * than +-1, or a non-inactive outermost cell layer; MG_ERR_NO_ACTIVE
  * when no cell is +1; MG_ERR_ALLOC / MG_ERR_HIP.
  */
 mg_status mg_create_hierarchy(const int8_t *mask_dev, int32_t nx, int32_t ny, int32_t nz, double h,

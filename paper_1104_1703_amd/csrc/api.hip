@@ -106,6 +106,9 @@ void build_lists(mg_hierarchy *H, int l, int order) {
         HIPCHK(hipMemcpyAsync(od.tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, H->stream));
     if (!segs.empty())
         HIPCHK(hipMemcpyAsync(od.segs, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice, H->stream));
+    const int npl = item_planes(l);
+    od.pmask = alloc_n<unsigned long long>(H, std::max<size_t>(1, segs.size() * npl));
+    launch_item_masks(L, l, order, od, npl, od.pmask, H->stream);
     HIPCHK(hipStreamSynchronize(H->stream));
 }
 
@@ -636,8 +639,8 @@ mg_status mg_create_hierarchy(const int8_t *mask_dev, int32_t nx, int32_t ny, in
         set_error("invalid mask pointer, dims or h");
         return MG_ERR_ARG;
     }
-    if ((size_t)nx * ny * nz >= ((size_t)1 << 34)) {
-        set_error("box too large");
+    if ((size_t)nx * ny * nz >= ((size_t)1 << 34) || (size_t)nx * ny * sizeof(double) >= ((size_t)1 << 31)) {
+        set_error("box too large (at most 2^34 cells and 2^28 cells per z-plane)");
         return MG_ERR_ARG;
     }
     mg_hierarchy *H = new (std::nothrow) mg_hierarchy();
@@ -738,12 +741,12 @@ mg_status mg_level_diag(const mg_hierarchy *H, int32_t level, int32_t order, dou
     return guarded([&]() {
         const Level &L = H->lev[level];
         if (level == 0) {
-            // diagonal of the finest level from the neighbour code: 12 - code
+            // diagonal of the finest level: the cell code itself (0 if inactive)
             std::vector<uint8_t> code(L.n);
             std::vector<double> d(L.n);
             HIPCHK(hipMemcpyAsync(code.data(), L.code, L.n, hipMemcpyDeviceToHost, H->stream));
             HIPCHK(hipStreamSynchronize(H->stream));
-            for (size_t p = 0; p < L.n; p++) d[p] = code[p] == CODE_OFF ? 0.0 : 12.0 - code[p];
+            for (size_t p = 0; p < L.n; p++) d[p] = (double)code[p];
             HIPCHK(hipMemcpyAsync(d_dev, d.data(), L.n * sizeof(double), hipMemcpyHostToDevice, H->stream));
         } else {
             HIPCHK(hipMemcpyAsync(d_dev, L.od[order].d, L.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));

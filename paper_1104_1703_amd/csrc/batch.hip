@@ -145,10 +145,10 @@ __global__ __launch_bounds__(BNT) void k_batch(BatchArgs A) {
                     const double *xin = (w.sel & 2) ? nullptr : L.x[a];
                     if (P.type == PH_SMOOTH0)
                         rb::rbgs_item<double, true, BSEGZ>(lds.fine, xin, L.x[a ^ 1], L.f, L.code, nullptr, L.nx,
-                                                           L.ny, L.nz, L.h2, w.seg);
+                                                           L.ny, L.nz, L.h2, w.seg, nullptr);
                     else
                         rb::rbgs_item<double, false, BSEGZ>(lds.coarse, xin, L.x[a ^ 1], L.f, nullptr,
-                                                            L.d[A.order], L.nx, L.ny, L.nz, L.h2, w.seg);
+                                                            L.d[A.order], L.nx, L.ny, L.nz, L.h2, w.seg, nullptr);
                     __syncthreads();
                     break;
                 }

@@ -22,12 +22,16 @@ constexpr int MAXS = 8;                    // levels handled by the one-workgrou
 constexpr size_t SMALL_MAX_CELLS = 4096;   // first level handled there has at most this many cells
 constexpr int SMALL_LDS_MAX = 160 * 1024;  // LDS of one gfx950 workgroup
 
+// Planes per smoother work item (its z range plus the two-plane halo on each side).
+constexpr int item_planes(int level) { return (level == 0 ? SEG_TILES_FINE * TZ : SEGZ_COARSE) + 4; }
+
 // Per boundary order data of one level (index 1 = first order, 2 = second).
 struct OrderData {
     double *d = nullptr;   // operator diagonal (coarse levels), 0 off the active set
     float *d32 = nullptr;  // float copy for the mixed-precision inner cycle
     int *tiles = nullptr;  // active tile ids (device)
     Seg *segs = nullptr;   // smoother work items (device)
+    unsigned long long *pmask = nullptr;  // per item and plane activity masks (device)
     int ntiles = 0, nsegs = 0;
     int64_t nact = 0;
 };
@@ -38,7 +42,7 @@ struct Level {
     size_t n = 0;
     int ntx = 0, nty = 0, ntz = 0;
     int32_t *cnt = nullptr;   // active finest descendants per cell
-    uint8_t *code = nullptr;  // level 0: number of active neighbours, CODE_OFF if inactive
+    uint8_t *code = nullptr;  // level 0: diagonal of the cell equation (6..12), CODE_OFF (0) if inactive
     OrderData od[3];
     double *x[2] = {nullptr, nullptr};  // ping-pong iterate
     double *f = nullptr;                // right-hand side
@@ -117,6 +121,9 @@ void launch_code0(const Level &L, unsigned long long *nact, hipStream_t s);
 void launch_diag(const Level &L, int level, int order, double *d, unsigned long long *nact, hipStream_t s);
 void launch_tile_flags(const Level &L, int level, int order, uint8_t *flags, hipStream_t s);
 void launch_to_float(const double *a, float *b, size_t n, hipStream_t s);
+// Activity masks of the smoother work items of `od` (npl planes per item).
+void launch_item_masks(const Level &L, int level, int order, const OrderData &od, int npl, unsigned long long *pm,
+                       hipStream_t s);
 
 // -------- smoother (smooth.hip) --------
 // One red-black pass over the segments of `od`; xin == nullptr reads zero.

@@ -5,6 +5,7 @@
 // active finest descendants (m = 2c/8^l - 1), so the domain test m > 0 is
 // 2c > 8^l and the first-order test m = 1 (Sec. 4) is c = 8^l, both exact.
 #include "mg_core.h"
+#include "smooth_core.h"
 
 namespace mg {
 
@@ -54,9 +55,10 @@ __device__ __forceinline__ bool is_active(int32_t c, int level, int order) {
     return order == 2 ? (2 * (int64_t)c > N) : ((int64_t)c == N);
 }
 
-// Finest level: code = number of active face neighbours (0..6), CODE_OFF if
-// inactive.  With the boundary on the face (theta = 1/2) the diagonal of the
-// cell's equation is (#active) + 2 (#inactive) = 12 - code.
+// Finest level: with the boundary on the face (theta = 1/2) the diagonal of an
+// active cell's equation is (#active) + 2 (#inactive) = 12 - (#active face
+// neighbours); the code holds it (6..12), CODE_OFF (0) for an inactive cell,
+// so that a zero-filled (skipped) load reads as inactive.
 __global__ void k_code0(const int32_t *__restrict__ cnt, int nx, int ny, int nz, uint8_t *__restrict__ code,
                         unsigned long long *__restrict__ nact) {
     size_t n = (size_t)nx * ny * nz;
@@ -73,7 +75,7 @@ __global__ void k_code0(const int32_t *__restrict__ cnt, int nx, int ny, int nz,
             na += (j < ny - 1 && cnt[p + nx] == 1);
             na += (k > 0 && cnt[p - (size_t)nx * ny] == 1);
             na += (k < nz - 1 && cnt[p + (size_t)nx * ny] == 1);
-            code[p] = (uint8_t)na;
+            code[p] = (uint8_t)(12 - na);
         } else {
             code[p] = CODE_OFF;
         }
@@ -140,6 +142,32 @@ __global__ void k_tile_flags(const int32_t *__restrict__ cnt, int nx, int ny, in
     if (threadIdx.x == 0) flags[t] = (uint8_t)(c != 0);
 }
 
+// One block per smoother work item: its activity masks (one word per plane
+// z0-2 .. z0+npl-3; bit layout of rb::item_mask_bit).
+__global__ void k_item_masks(const int32_t *__restrict__ cnt, int nx, int ny, int nz, int level, int order,
+                             const Seg *__restrict__ segs, int npl, unsigned long long *__restrict__ pm) {
+    __shared__ unsigned rowbits[rb::MAXPL * rb::PY];
+    const Seg sg = segs[blockIdx.x];
+    for (int r = threadIdx.x; r < npl * rb::PY; r += blockDim.x) {
+        const int pi = r / rb::PY, v = r % rb::PY;
+        const int k = sg.z0 - 2 + pi, y = sg.y0 - 2 + v;
+        unsigned bits = 0;
+        if (k >= 0 && k < nz && k <= sg.z1 + 1 && y >= 0 && y < ny)
+            for (int u = 0; u < rb::PX; u++) {
+                const int x = sg.x0 - 2 + u;
+                if (x >= 0 && x < nx && is_active(cnt[((size_t)k * ny + y) * nx + x], level, order))
+                    bits |= 1u << (rb::item_mask_bit(u, v) - 4 * v);
+            }
+        rowbits[r] = bits;
+    }
+    __syncthreads();
+    for (int pi = threadIdx.x; pi < npl; pi += blockDim.x) {
+        unsigned long long w = 0;
+        for (int v = 0; v < rb::PY; v++) w |= (unsigned long long)rowbits[pi * rb::PY + v] << (4 * v);
+        pm[(size_t)blockIdx.x * npl + pi] = w;
+    }
+}
+
 __global__ void k_to_float(const double *__restrict__ a, float *__restrict__ b, size_t n) {
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x)
         b[p] = (float)a[p];
@@ -180,6 +208,12 @@ void launch_diag(const Level &L, int level, int order, double *d, unsigned long 
 void launch_tile_flags(const Level &L, int level, int order, uint8_t *flags, hipStream_t s) {
     int nt = L.ntx * L.nty * L.ntz;
     k_tile_flags<<<nt, 256, 0, s>>>(L.cnt, L.nx, L.ny, L.nz, L.ntx, L.nty, level, order, flags);
+}
+
+void launch_item_masks(const Level &L, int level, int order, const OrderData &od, int npl, unsigned long long *pm,
+                       hipStream_t s) {
+    if (od.nsegs == 0) return;
+    k_item_masks<<<od.nsegs, 256, 0, s>>>(L.cnt, L.nx, L.ny, L.nz, level, order, od.segs, npl, pm);
 }
 
 void launch_to_float(const double *a, float *b, size_t n, hipStream_t s) {

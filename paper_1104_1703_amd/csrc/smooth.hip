@@ -16,8 +16,12 @@
 // and writes go to `xout` (ping-pong), so concurrent work items never see
 // each other's results.  Global loads of the planes needed two and three
 // steps ahead are in flight in registers while a step computes, so the
-// compute phases touch LDS only.  Net HBM traffic per pass: one read of x, f,
-// code/diagonal and one write of x.
+// compute phases touch LDS only.  Loads go through buffer resources and are
+// masked per 16-cell row granule by the item's precomputed activity masks:
+// granules without an active cell (outside the domain, inside holes, halo rows
+// of inactive neighbours) are never fetched, and inactive cells are never
+// stored.  Net HBM traffic per pass: one read of x, f and the code/diagonal
+// and one write of x, on granules holding active cells.
 #include "mg_core.h"
 #include "smooth_core.h"
 
@@ -28,14 +32,16 @@ namespace {
 using namespace rb;
 
 template <typename T, bool FINE, int SEGZ>
-__global__ __launch_bounds__(NT) void k_rbgs(const T *__restrict__ xin, T *__restrict__ xout,
+__global__ __launch_bounds__(NT, 5) void k_rbgs(const T *__restrict__ xin, T *__restrict__ xout,
                                               const T *__restrict__ f, const uint8_t *__restrict__ code,
                                               const T *__restrict__ dco, int nx, int ny, int nz, T h2,
-                                              const Seg *__restrict__ segs, int nsegs) {
+                                              const Seg *__restrict__ segs, const unsigned long long *__restrict__ pm,
+                                              int nsegs) {
     __shared__ RbgsLds<T, FINE> lds;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= nsegs) return;
-    rbgs_item<T, FINE, SEGZ>(lds, xin, xout, f, code, dco, nx, ny, nz, h2, segs[item]);
+    rbgs_item<T, FINE, SEGZ>(lds, xin, xout, f, code, dco, nx, ny, nz, h2, segs[item],
+                             pm + (size_t)item * (SEGZ + 4));
 }
 
 inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
@@ -48,10 +54,10 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
     const double h2 = L.h * L.h;
     if (level == 0)
         k_rbgs<double, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
-                                                             od.segs, od.nsegs);
+                                                             od.segs, od.pmask, od.nsegs);
     else
         k_rbgs<double, false, SEGZ_COARSE><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz, h2,
-                                                              od.segs, od.nsegs);
+                                                              od.segs, od.pmask, od.nsegs);
 }
 
 void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
@@ -60,10 +66,10 @@ void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *
     const float h2 = (float)(L.h * L.h);
     if (level == 0)
         k_rbgs<float, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
-                                                            od.segs, od.nsegs);
+                                                            od.segs, od.pmask, od.nsegs);
     else
         k_rbgs<float, false, SEGZ_COARSE><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d32, L.nx, L.ny, L.nz, h2,
-                                                             od.segs, od.nsegs);
+                                                             od.segs, od.pmask, od.nsegs);
 }
 
 }  // namespace mg

@@ -18,7 +18,10 @@ constexpr int QX = BX + 2, QY = BY + 2, QN = QX * QY;  // f / diag plane with 1-
 constexpr int NT = 256;
 constexpr int XR = (PN + NT - 1) / NT;  // x elements per thread per plane
 constexpr int QR = (QN + NT - 1) / NT;  // f elements per thread per plane
-constexpr int PF = 4;                   // planes of global loads in flight
+// Planes of global loads in flight per block.  Double planes carry twice the
+// bytes of float planes; measured on the 256^3 workload, three are best for
+// doubles and more would only keep lines in L2 longer.
+constexpr int PF64 = 3, PF32 = 4;
 
 // Work items are dealt to the 8 XCDs round-robin by block id; give each XCD a
 // contiguous range of work items so that halo re-reads hit its own L2.
@@ -32,7 +35,6 @@ struct PlaneRegs {
     T x[XR];
     T f[QR];
     typename std::conditional<FINE, uint8_t, T>::type d[QR];  // raw code byte or diagonal
-    unsigned ok;  // validity bits: x elements in bits 0..XR-1, f/d elements above
 };
 
 // LDS of one work item: a 5-plane ring of x (2-cell halo), and 4-plane rings
@@ -40,21 +42,58 @@ struct PlaneRegs {
 // neighbour code instead of a diagonal).  One ring plane more than a step
 // touches lets a step commit its new plane while the previous step's black
 // half-sweep may still read the oldest one, so a step needs two barriers.
+// `m` holds the item's activity masks, one word per plane (see item_mask_bit).
 constexpr int XS = 5, FS = 4;
+constexpr int MAXPL = SEG_TILES_FINE * TZ + 4;  // planes touched by the longest work item
 template <typename T, bool FINE>
 struct RbgsLds {
     using DT = typename std::conditional<FINE, uint8_t, T>::type;
     T x[XS][PN];
     T f[FS][QN];
     DT d[FS][QN];
+    unsigned long long m[MAXPL];
 };
 
+// Activity mask of a work item: for each of its planes z0-2 .. z0+SEGZ+1, bit
+// 4 v + g is set when row v of the x plane (y = y0-2+v, v < PY) holds an
+// active cell in granule g, the granules being x0-2..x0-1, x0..x0+15,
+// x0+16..x0+31 and x0+32..x0+33 (each inside one 128-byte line of doubles).
+// Planes outside the box or above z1+1 are all zero.  Loads of a granule
+// without active cells are skipped: inactive cells hold x = 0 and their f and
+// diagonal are never used.
+__host__ __device__ constexpr int item_mask_bit(int u, int v) { return 4 * v + ((u + 14) >> 4); }
+
+// Buffer-resource access: a lane whose byte offset lies beyond the resource
+// size reads 0 and writes nothing without touching memory, so a masked lane
+// costs no traffic while every lane issues the same instructions (exact wait
+// counts in the unrolled march).
+constexpr int OFF_NONE = (int)0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+template <typename V>
+__device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, int off) {
+    if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else if constexpr (sizeof(V) == 4) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0));
+}
+template <typename V>
+__device__ __forceinline__ void bstore(V v, __amdgpu_buffer_rsrc_t r, int off) {
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(V) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0, 0);
+    else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
 // One full red-black pass over one work item (see the file comment of
-// smooth.hip).  Called by all 256 threads of a block.
+// smooth.hip).  Called by all 256 threads of a block.  `pm`: the item's
+// SEGZ + 4 activity masks, or nullptr to load every in-box cell.  A plane of
+// the level must hold fewer than 2^31 bytes.
 template <typename T, bool FINE, int SEGZ>
 __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restrict__ xin, T *__restrict__ xout,
                                           const T *__restrict__ f, const uint8_t *__restrict__ code,
-                                          const T *__restrict__ dco, int nx, int ny, int nz, T h2, const Seg sg) {
+                                          const T *__restrict__ dco, int nx, int ny, int nz, T h2, const Seg sg,
+                                          const unsigned long long *__restrict__ pm) {
+    static_assert(SEGZ + 4 <= MAXPL, "work item longer than the mask array");
     using DT = typename RbgsLds<T, FINE>::DT;
     auto &sx = L.x;
     auto &sf = L.f;
@@ -64,76 +103,93 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
     const int tid = threadIdx.x;
     const int z0 = max(sg.z0, 0), z1 = min(sg.z1, nz);  // a work item never leaves the box
 
+    if (tid < SEGZ + 4) L.m[tid] = pm ? pm[tid] : ~0ull;
+
     // Per-thread element positions are the same for every plane: precompute
-    // the clamped in-plane offsets and the in-box flags once.
+    // the in-plane byte offsets (OFF_NONE outside the box) and the mask bits
+    // of the thread's elements (one byte each) once.
     int xoff[XR], qoff[QR];
-    unsigned okxy = 0;
+    unsigned bits = 0;
 #pragma unroll
     for (int q = 0; q < XR; q++) {
         const int e = min(tid + q * NT, PN - 1);
-        const int gx = gx0 + e % PX, gy = gy0 + e / PX;
+        const int u = e % PX, v = e / PX;
+        const int gx = gx0 + u, gy = gy0 + v;
         const bool in = (tid + q * NT < PN) && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        okxy |= (unsigned)in << q;
-        xoff[q] = min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1);
+        xoff[q] = in ? (gy * nx + gx) * (int)sizeof(T) : OFF_NONE;
+        bits |= (unsigned)item_mask_bit(u, v) << (8 * q);
     }
 #pragma unroll
     for (int q = 0; q < QR; q++) {
         const int e = min(tid + q * NT, QN - 1);
-        const int gx = gx0 + 1 + e % QX, gy = gy0 + 1 + e / QX;
+        const int u = e % QX + 1, v = e / QX + 1;
+        const int gx = gx0 + u, gy = gy0 + v;
         const bool in = (tid + q * NT < QN) && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        okxy |= (unsigned)in << (XR + q);
-        qoff[q] = min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1);
+        qoff[q] = in ? (gy * nx + gx) * (int)sizeof(T) : OFF_NONE;
+        bits |= (unsigned)item_mask_bit(u, v) << (8 * (XR + q));
     }
+    static_assert(XR + QR <= 4, "mask bit indices are packed into one word");
+    const int pbytes = (int)(plane * sizeof(T));
+    constexpr int TSH = sizeof(T) == 8 ? 3 : 2;  // byte offset -> element offset
+    __syncthreads();  // masks
 
-    const T *xsrc = xin ? xin : f;  // any valid array of the same shape when x starts at zero
-    // global -> registers for plane k.  Loads are unconditional (clamped
-    // addresses); validity is applied at commit, so issuing never waits.
-    auto fetch = [&](PlaneRegs<T, FINE> &r, int k) {
+    auto mbit = [&](unsigned long long m, int j) { return (bool)((m >> ((bits >> (8 * j)) & 63u)) & 1ull); };
+    // f and the diagonal are read on planes z0-1 .. z1 only
+    auto fplane = [&](int k) { return k >= z0 - 1 && k <= z1 && k < nz; };
+    auto fload = [&](unsigned long long m, int k, int q) { return fplane(k) && qoff[q] >= 0 && mbit(m, XR + q); };
+
+    // global -> registers for plane k = z0 - 2 + pi (x on planes z0-2 .. z1+1)
+    auto fetch = [&](PlaneRegs<T, FINE> &r, int k, int pi) {
         const bool kin = k >= 0 && k < nz && k <= z1 + 1;
+        const unsigned long long m = kin ? L.m[pi] : 0ull;
         const size_t base = (size_t)min(max(k, 0), nz - 1) * plane;
-        r.ok = kin ? okxy : 0u;
-        if (!xin) r.ok &= ~((1u << XR) - 1u);  // zero iterate: loaded values are discarded
+        const __amdgpu_buffer_rsrc_t rx = rsrc(xin ? xin + base : f + base, xin ? pbytes : 0);
+        const __amdgpu_buffer_rsrc_t rf = rsrc(f + base, pbytes);
 #pragma unroll
-        for (int q = 0; q < XR; q++) r.x[q] = xsrc[base + xoff[q]];
+        for (int q = 0; q < XR; q++) r.x[q] = bload<T>(rx, mbit(m, q) ? xoff[q] : OFF_NONE);
 #pragma unroll
         for (int q = 0; q < QR; q++) {
-            if constexpr (FINE) r.d[q] = code[base + qoff[q]];
-            else r.d[q] = dco[base + qoff[q]];
-            r.f[q] = f[base + qoff[q]];
+            const bool p = fload(m, k, q);
+            r.f[q] = bload<T>(rf, p ? qoff[q] : OFF_NONE);
+            if constexpr (FINE) r.d[q] = bload<uint8_t>(rsrc(code + base, (int)plane), p ? qoff[q] >> TSH : OFF_NONE);
+            else r.d[q] = bload<T>(rsrc(dco + base, pbytes), p ? qoff[q] : OFF_NONE);
         }
     };
-    // registers -> LDS ring slot of plane k (zeros where invalid)
-    auto xslot = [](int k) { return (k + 2 * XS) % XS; };  // k >= -2
-    auto fslot = [](int k) { return (k + 2 * FS) % FS; };
-    auto commit = [&](const PlaneRegs<T, FINE> &r, int k) {
-        T *dx = sx[xslot(k)];
-        T *df = sf[fslot(k)];
-        DT *dd = sd[fslot(k)];
+    // Ring slots are indexed by a plane's position j = k - z0 in the item
+    // (j >= -2), a compile-time value in the unrolled march.
+    auto xslot = [](int j) { return (j + 2 * XS) % XS; };
+    auto fslot = [](int j) { return (j + 2 * FS) % FS; };
+    // registers -> LDS ring slot of plane z0 + j (skipped loads read zero,
+    // which is also the code of an inactive cell)
+    auto commit = [&](const PlaneRegs<T, FINE> &r, int j) {
+        T *dx = sx[xslot(j)];
+        T *df = sf[fslot(j)];
+        DT *dd = sd[fslot(j)];
 #pragma unroll
         for (int q = 0; q < XR; q++) {
             const int e = tid + q * NT;
-            if (e < PN) dx[e] = ((r.ok >> q) & 1u) ? r.x[q] : T(0);
+            if (e < PN) dx[e] = r.x[q];
         }
 #pragma unroll
         for (int q = 0; q < QR; q++) {
             const int e = tid + q * NT;
             if (e < QN) {
-                const bool ok = (r.ok >> (XR + q)) & 1u;
-                df[e] = ok ? r.f[q] : T(0);
-                if constexpr (FINE) dd[e] = ok ? r.d[q] : CODE_OFF;
-                else dd[e] = ok ? r.d[q] : T(0);
+                df[e] = r.f[q];
+                dd[e] = r.d[q];
             }
         }
     };
 
-    // Relax colour `col` of plane k on [lo, PX-lo) x [lo, PY-lo) (x-plane coords).
-    auto relax = [&](int k, int col, int lo) {
+    // Relax colour `col` of plane k = z0 + j on [lo, PX-lo) x [lo, PY-lo)
+    // (x-plane coords).  The diagonal is 0 on inactive and out-of-box cells.
+    auto relax = [&](int j, int col, int lo) {
+        const int k = z0 + j;
         if (k < 0 || k >= nz) return;
-        T *c = sx[xslot(k)];
-        const T *dn = sx[xslot(k - 1)];
-        const T *up = sx[xslot(k + 1)];
-        const T *fq = sf[fslot(k)];
-        const DT *dq = sd[fslot(k)];
+        T *c = sx[xslot(j)];
+        const T *dn = sx[xslot(j - 1)];
+        const T *up = sx[xslot(j + 1)];
+        const T *fq = sf[fslot(j)];
+        const DT *dq = sd[fslot(j)];
         const int half = (PX - 2 * lo) >> 1;
         const int rows = PY - 2 * lo;
         for (int e = tid; e < half * rows; e += NT) {
@@ -141,26 +197,26 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
             const int u = lo + ((col + gy0 + v + k + gx0 + lo) & 1) + 2 * (e % half);
             const int qq = (v - 1) * QX + (u - 1);
             T d;
-            if constexpr (FINE) {
-                const uint8_t cd = dq[qq];
-                if (cd == CODE_OFF) continue;  // inactive or outside the box
-                d = T(12 - (int)cd);
-            } else {
-                d = dq[qq];
-                if (d == T(0)) continue;  // inactive or outside the box
-            }
+            if constexpr (FINE) d = T((int)dq[qq]);
+            else d = dq[qq];
+            if (d == T(0)) continue;
             const int q = v * PX + u;
             const T s = (c[q - 1] + c[q + 1]) + (c[q - PX] + c[q + PX]) + (dn[q] + up[q]);
             c[q] = (s - h2 * fq[qq]) / d;
         }
     };
 
-    auto store = [&](int k) {
-        const T *c = sx[xslot(k)];
+    // LDS -> xout for the tile cells of plane z0 + j; inactive cells are not
+    // written (they hold zero in every iterate buffer).
+    auto store = [&](int j) {
+        const T *c = sx[xslot(j)];
+        const DT *dq = sd[fslot(j)];
+        const __amdgpu_buffer_rsrc_t ro = rsrc(xout + (size_t)(z0 + j) * plane, pbytes);
         for (int e = tid; e < BX * BY; e += NT) {
             const int u = 2 + e % BX, v = 2 + e / BX;
             const int gx = gx0 + u, gy = gy0 + v;
-            if (gx < nx && gy < ny) xout[(size_t)k * plane + (size_t)gy * nx + gx] = c[v * PX + u];
+            const bool act = dq[(v - 1) * QX + (u - 1)] != DT(0);
+            bstore<T>(c[v * PX + u], ro, act ? (gy * nx + gx) * (int)sizeof(T) : OFF_NONE);
         }
     };
 
@@ -172,28 +228,28 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
     // since the previous step), then relaxes black of plane k; the last step
     // only stores.
     constexpr int NSTEP = SEGZ + 4;
+    constexpr int PF = sizeof(T) == 8 ? PF64 : PF32;
     PlaneRegs<T, FINE> r[PF];
 #pragma unroll
-    for (int q = 0; q < PF; q++) fetch(r[q], z0 - 2 + q);
+    for (int q = 0; q < PF; q++) fetch(r[q], z0 - 2 + q, q);
 #pragma unroll
     for (int st = 0; st <= NSTEP; st++) {
-        const int pk = z0 - 2 + st;  // plane committed in this step
-        const int k = pk - 2;
+        const int j = st - 4;  // plane z0 + j is black-relaxed in this step
         if (st < NSTEP) {
-            commit(r[st % PF], pk);
-            if (st + PF < NSTEP) fetch(r[st % PF], pk + PF);
+            commit(r[st % PF], j + 2);
+            if (st + PF < NSTEP) fetch(r[st % PF], z0 + j + 2 + PF, st + PF);
         }
         __syncthreads();
         if (st == 3) {
-            relax(z0 - 1, 0, 1);
-            relax(z0, 0, 1);
+            relax(-1, 0, 1);
+            relax(0, 0, 1);
         } else if (st > 3) {
-            if (st < NSTEP) relax(k + 1, 0, 1);
-            if (k - 1 >= z0 && k - 1 < z1) store(k - 1);
+            if (st < NSTEP) relax(j + 1, 0, 1);
+            if (j - 1 >= 0 && z0 + j - 1 < z1) store(j - 1);
         }
         if (st > 3 && st < NSTEP) {
             __syncthreads();
-            relax(k, 1, 2);
+            relax(j, 1, 2);
         }
     }
 }

@@ -12,7 +12,9 @@ constexpr int TY = 8;
 constexpr int TZ = 8;
 constexpr int SEG_TILES_FINE = 2;    // z-tiles per smoother work item on the finest level
 constexpr int SEGZ_COARSE = 4;       // planes per smoother work item on coarse levels (more items)
-constexpr uint8_t CODE_OFF = 255;    // finest-level code of an inactive cell
+// Finest-level cell code: the diagonal of the cell's equation, 12 - (number
+// of active face neighbours) = 6..12 for an active cell, CODE_OFF if inactive.
+constexpr uint8_t CODE_OFF = 0;
 
 // Smoother work item: origin of an xy tile and a z range [z0, z1).
 struct Seg {

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_restrict_march(const T *__restrict__ x, 
             const T *xu = xs[(k + 1 + XS) % XS];
             T rr = T(0);
             if (cprev != CODE_OFF) {
-                const T d = T(12 - (int)cprev);
+                const T d = T((int)cprev);
                 const T sum = ((xc[q0 - 1] + xc[q0 + 1]) + (xc[q0 - PX] + xc[q0 + PX])) + (xd[q0] + xu[q0]);
                 rr = (sum - d * xc[q0]) * ih2 - fprev;
             }

@@ -66,7 +66,7 @@ template <typename T, bool FINE>
 __device__ __forceinline__ T diag_at(const uint8_t *code, const T *dco, size_t p) {
     if constexpr (FINE) {
         const uint8_t c = code[p];
-        return c == CODE_OFF ? T(0) : T(12 - (int)c);
+        return T((int)c);  // CODE_OFF is 0
     } else {
         return dco[p];
     }
@@ -120,7 +120,7 @@ __device__ __forceinline__ void column_residual(const T *__restrict__ x, const T
     for (int q = 0; q < NZ; q++) {
         const int k = k0 + q;
         T d;
-        if constexpr (FINE) d = dr[q] == CODE_OFF ? T(0) : T(12 - (int)dr[q]);
+        if constexpr (FINE) d = T((int)dr[q]);  // CODE_OFF is 0
         else d = dr[q];
         if (!okij || k >= nz) d = T(0);
         const T zm = k > 0 ? xs[q] : T(0);
@@ -151,7 +151,7 @@ __device__ __forceinline__ void fold_cell(const TileCoord &t, int nx, int ny, do
         return;
     }
     double fv = rho[p];
-    if (B && c < 6) {
+    if (B && c > 6) {  // some face neighbour is inactive
         const double bi = B[p];
         double g = 0.0;
         if (code[p - 1] == CODE_OFF) g += bi + B[p - 1];
