@@ -84,10 +84,11 @@ void build_lists(mg_hierarchy *H, int l, int order) {
                     while (t1 < L.ntz && hf[(t1 * L.nty + ty) * L.ntx + tx] && t1 - tz < SEG_TILES_FINE) t1++;
                     segs.push_back(Seg{tx * TX, ty * TY, tz * TZ, std::min(L.nz, t1 * TZ)});
                 } else {
-                    // coarse levels: one active tile cut into SEGZ_COARSE-plane items
+                    // coarse levels: one active tile cut into item_depth(l)-plane items
                     t1 = tz + 1;
-                    for (int z = tz * TZ; z < std::min(L.nz, t1 * TZ); z += SEGZ_COARSE)
-                        segs.push_back(Seg{tx * TX, ty * TY, z, std::min(std::min(L.nz, t1 * TZ), z + SEGZ_COARSE)});
+                    const int dz = item_depth(l);
+                    for (int z = tz * TZ; z < std::min(L.nz, t1 * TZ); z += dz)
+                        segs.push_back(Seg{tx * TX, ty * TY, z, std::min(std::min(L.nz, t1 * TZ), z + dz)});
                 }
                 tz = t1;
             }

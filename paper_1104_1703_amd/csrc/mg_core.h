@@ -23,7 +23,10 @@ constexpr size_t SMALL_MAX_CELLS = 4096;   // first level handled there has at m
 constexpr int SMALL_LDS_MAX = 160 * 1024;  // LDS of one gfx950 workgroup
 
 // Planes per smoother work item (its z range plus the two-plane halo on each side).
-constexpr int item_planes(int level) { return (level == 0 ? SEG_TILES_FINE * TZ : SEGZ_COARSE) + 4; }
+constexpr int item_depth(int level) {
+    return level == 0 ? SEG_TILES_FINE * TZ : level == 1 ? SEGZ_COARSE1 : SEGZ_COARSE;
+}
+constexpr int item_planes(int level) { return item_depth(level) + 4; }
 
 // Per boundary order data of one level (index 1 = first order, 2 = second).
 struct OrderData {

@@ -48,16 +48,29 @@ inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
 
 }  // namespace
 
+// Coarse levels: the kernel instance for the level's item depth.
+template <typename T>
+void launch_coarse(int depth, const T *xin, T *xout, const T *f, const T *d, const Level &L, const OrderData &od,
+                   T h2, hipStream_t s) {
+    if (depth == 8)
+        k_rbgs<T, false, 8><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs,
+                                                          od.pmask, od.nsegs);
+    else
+        k_rbgs<T, false, 4><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs,
+                                                          od.pmask, od.nsegs);
+}
+static_assert((SEGZ_COARSE1 == 4 || SEGZ_COARSE1 == 8) && (SEGZ_COARSE == 4 || SEGZ_COARSE == 8),
+              "coarse item depths have kernel instances for 4 and 8 planes");
+
 void launch_rbgs(const Level &L, int level, const OrderData &od, const double *xin, double *xout, const double *f,
                  hipStream_t s) {
     if (od.nsegs == 0) return;
     const double h2 = L.h * L.h;
     if (level == 0)
-        k_rbgs<double, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
-                                                             od.segs, od.pmask, od.nsegs);
+        k_rbgs<double, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
+            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs);
     else
-        k_rbgs<double, false, SEGZ_COARSE><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz, h2,
-                                                              od.segs, od.pmask, od.nsegs);
+        launch_coarse<double>(item_depth(level), xin, xout, f, od.d, L, od, h2, s);
 }
 
 void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
@@ -65,11 +78,10 @@ void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *
     if (od.nsegs == 0) return;
     const float h2 = (float)(L.h * L.h);
     if (level == 0)
-        k_rbgs<float, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
-                                                            od.segs, od.pmask, od.nsegs);
+        k_rbgs<float, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
+            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs);
     else
-        k_rbgs<float, false, SEGZ_COARSE><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, od.d32, L.nx, L.ny, L.nz, h2,
-                                                             od.segs, od.pmask, od.nsegs);
+        launch_coarse<float>(item_depth(level), xin, xout, f, od.d32, L, od, h2, s);
 }
 
 }  // namespace mg
