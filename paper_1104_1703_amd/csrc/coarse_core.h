@@ -65,24 +65,88 @@ __device__ __forceinline__ T nb_sum(const T *x, int i, int j, int k, int nx, int
     return (xm + xp) + (ym + yp) + (zm + zp);
 }
 
-// Red-black passes; each half-sweep visits only the cells of its colour
+// Red-black half-sweep of colour `col` over slots first, first + step, ...
 // (slot m of row (j, k) is cell i = 2m + ((col + j + k) mod 2)).
+template <typename T>
+__device__ __forceinline__ void half_sweep(const Lv<T> &L, int col, int first, int step) {
+    const int slots = L.hx * L.ny * L.nz;
+    for (int s = first; s < slots; s += step) {
+        const int k = qdiv(s, L.mhy);
+        const int r = s - k * L.hx * L.ny;
+        const int j = qdiv(r, L.mh);
+        const int i = 2 * (r - j * L.hx) + ((col + j + k) & 1);
+        if (i >= L.nx) continue;
+        const int e = (k * L.ny + j) * L.nx + i;
+        const T d = L.d[e];
+        if (d == T(0)) continue;
+        L.x[e] = (nb_sum(L.x, i, j, k, L.nx, L.ny, L.nz) - L.h2 * L.f[e]) / d;
+    }
+}
+
+// Levels with at most 64 cells of one colour are relaxed by the first wave
+// alone, each lane owning at most one cell per colour: its index, neighbour
+// validity, diagonal and h^2 f stay in registers for all passes.  A wave's LDS
+// accesses complete in order, so its half-sweeps need no workgroup barrier
+// between them (the other waves wait once at the end).
+constexpr int WAVE_SLOTS = 64;
+
+template <typename T>
+__device__ __forceinline__ void smooth_wave(const Lv<T> &L, int passes) {
+    const int lane = threadIdx.x;
+    const int nxy = L.nx * L.ny;
+    int e[2] = {-1, -1};
+    unsigned nb[2] = {0u, 0u};  // valid neighbours: -x, +x, -y, +y, -z, +z
+    T dg[2] = {T(1), T(1)}, rhs[2] = {T(0), T(0)};
+#pragma unroll
+    for (int col = 0; col < 2; col++) {
+        if (lane >= L.hx * L.ny * L.nz) continue;
+        const int k = qdiv(lane, L.mhy);
+        const int r = lane - k * L.hx * L.ny;
+        const int j = qdiv(r, L.mh);
+        const int i = 2 * (r - j * L.hx) + ((col + j + k) & 1);
+        if (i >= L.nx) continue;
+        const int c = (k * L.ny + j) * L.nx + i;
+        if (L.d[c] == T(0)) continue;
+        e[col] = c;
+        dg[col] = L.d[c];
+        rhs[col] = L.h2 * L.f[c];
+        nb[col] = (unsigned)(i > 0) | (unsigned)(i < L.nx - 1) << 1 | (unsigned)(j > 0) << 2 |
+                  (unsigned)(j < L.ny - 1) << 3 | (unsigned)(k > 0) << 4 | (unsigned)(k < L.nz - 1) << 5;
+    }
+    for (int p = 0; p < passes; p++)
+#pragma unroll
+        for (int col = 0; col < 2; col++) {
+            const int c = e[col];
+            if (c >= 0) {
+                const unsigned m = nb[col];
+                const T *x = L.x;
+                const T xm = (m & 1u) ? x[c - 1] : T(0);
+                const T xp = (m & 2u) ? x[c + 1] : T(0);
+                const T ym = (m & 4u) ? x[c - L.nx] : T(0);
+                const T yp = (m & 8u) ? x[c + L.nx] : T(0);
+                const T zm = (m & 16u) ? x[c - nxy] : T(0);
+                const T zp = (m & 32u) ? x[c + nxy] : T(0);
+                L.x[c] = (((xm + xp) + (ym + yp) + (zm + zp)) - rhs[col]) / dg[col];
+            }
+            // keep the next half-sweep's LDS reads behind this one's writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+}
+
+// Red-black passes; each half-sweep visits only the cells of its colour.
 template <typename T, int NTH>
 __device__ void smooth(const Lv<T> &L, int passes) {
     const int slots = L.hx * L.ny * L.nz;
+    if (slots <= WAVE_SLOTS) {
+        if (threadIdx.x < 64) smooth_wave(L, passes);
+        __syncthreads();
+        return;
+    }
     for (int p = 0; p < passes; p++)
         for (int col = 0; col < 2; col++) {
-            for (int s = threadIdx.x; s < slots; s += NTH) {
-                const int k = qdiv(s, L.mhy);
-                const int r = s - k * L.hx * L.ny;
-                const int j = qdiv(r, L.mh);
-                const int i = 2 * (r - j * L.hx) + ((col + j + k) & 1);
-                if (i >= L.nx) continue;
-                const int e = (k * L.ny + j) * L.nx + i;
-                const T d = L.d[e];
-                if (d == T(0)) continue;
-                L.x[e] = (nb_sum(L.x, i, j, k, L.nx, L.ny, L.nz) - L.h2 * L.f[e]) / d;
-            }
+            half_sweep(L, col, threadIdx.x, NTH);
             __syncthreads();
         }
 }
