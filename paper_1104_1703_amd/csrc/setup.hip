@@ -143,7 +143,7 @@ __global__ void k_tile_flags(const int32_t *__restrict__ cnt, int nx, int ny, in
 }
 
 // One block per smoother work item: its activity masks (one word per plane
-// z0-2 .. z0+npl-3; bit layout of rb::item_mask_bit).
+// z0-2 .. z0+npl-3; bit layout of item_mask_bit).
 __global__ void k_item_masks(const int32_t *__restrict__ cnt, int nx, int ny, int nz, int level, int order,
                              const Seg *__restrict__ segs, int npl, unsigned long long *__restrict__ pm) {
     __shared__ unsigned rowbits[rb::MAXPL * rb::PY];
@@ -156,7 +156,7 @@ __global__ void k_item_masks(const int32_t *__restrict__ cnt, int nx, int ny, in
             for (int u = 0; u < rb::PX; u++) {
                 const int x = sg.x0 - 2 + u;
                 if (x >= 0 && x < nx && is_active(cnt[((size_t)k * ny + y) * nx + x], level, order))
-                    bits |= 1u << (rb::item_mask_bit(u, v) - 4 * v);
+                    bits |= 1u << (item_mask_bit(u, v) - 4 * v);
             }
         rowbits[r] = bits;
     }

@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "masked.h"
 #include "tiles.h"
 
 namespace mg {
@@ -53,36 +54,6 @@ struct RbgsLds {
     DT d[FS][QN];
     unsigned long long m[MAXPL];
 };
-
-// Activity mask of a work item: for each of its planes z0-2 .. z0+SEGZ+1, bit
-// 4 v + g is set when row v of the x plane (y = y0-2+v, v < PY) holds an
-// active cell in granule g, the granules being x0-2..x0-1, x0..x0+15,
-// x0+16..x0+31 and x0+32..x0+33 (each inside one 128-byte line of doubles).
-// Planes outside the box or above z1+1 are all zero.  Loads of a granule
-// without active cells are skipped: inactive cells hold x = 0 and their f and
-// diagonal are never used.
-__host__ __device__ constexpr int item_mask_bit(int u, int v) { return 4 * v + ((u + 14) >> 4); }
-
-// Buffer-resource access: a lane whose byte offset lies beyond the resource
-// size reads 0 and writes nothing without touching memory, so a masked lane
-// costs no traffic while every lane issues the same instructions (exact wait
-// counts in the unrolled march).
-constexpr int OFF_NONE = (int)0x80000000u;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, int bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
-}
-template <typename V>
-__device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, int off) {
-    if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-    else if constexpr (sizeof(V) == 4) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-    else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0));
-}
-template <typename V>
-__device__ __forceinline__ void bstore(V v, __amdgpu_buffer_rsrc_t r, int off) {
-    using U2 = unsigned __attribute__((ext_vector_type(2)));
-    if constexpr (sizeof(V) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0, 0);
-    else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
-}
 
 // One full red-black pass over one work item (see the file comment of
 // smooth.hip).  Called by all 256 threads of a block.  `pm`: the item's

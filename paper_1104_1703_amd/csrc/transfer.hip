@@ -1,5 +1,6 @@
 // Residual, restriction, prolongation, norms and boundary folding: kernels
 // over the active tiles of one level (bodies in transfer_core.h).
+#include "masked.h"
 #include "transfer_core.h"
 
 namespace mg {
@@ -112,16 +113,23 @@ __global__ __launch_bounds__(NT) void k_restrict(const int *__restrict__ ctiles,
                            x, f, fc);
 }
 
-// Residual and R1 restriction from the finest level as a march: one block per
-// smoother work item (a TX x TY column of cells over a z range of tile
-// pairs), thread (u, v) of the tile cross-section owning one cell per plane.
-// Planes of x pass through a 4-plane LDS ring with a 1-cell halo (each loaded
-// once per item, PF planes of loads in flight); f and the neighbour code of
-// the thread's own cell stay in registers.  Each cell's residual is summed
-// with its x and y partners by lane exchanges (the two rows of a wave are the
-// two y children), and planes 2K and 2K+1 complete coarse plane K:
-// f_c = -(1/8) sum of the 8 children's residuals on active coarse cells, 0 on
-// inactive ones.  Only coarse cells above active finest tiles are written.
+// Residual of the finest level as a march: one block per smoother work item
+// (a TX x TY column of cells over a z range of tile pairs), thread (u, v) of
+// the tile cross-section owning one cell per plane.  Planes of x pass through
+// a 4-plane LDS ring with a 1-cell halo (each loaded once per item); f and
+// the code of the thread's own cell stay in registers.  Loads are masked by
+// the item's activity masks (granules without active cells read as zero).
+// Modes:
+//  RM_RESTRICT  R1 restriction: each cell's residual is summed with its x and y
+//               partners by lane exchanges (the two rows of a wave are the two
+//               y children), and planes 2K and 2K+1 complete coarse plane K:
+//               f_c = -(1/8) sum of the 8 children's residuals on active coarse
+//               cells, 0 on inactive ones.  Only coarse cells above active
+//               finest tiles are written.
+//  RM_NORM      sum of r^2 over the item's active cells into part[item] (x may
+//               be null: x = 0, r = -f).
+//  RM_NORM32    as RM_NORM, and -r is written in float to r32 on active cells.
+enum { RM_RESTRICT = 0, RM_NORM = 1, RM_NORM32 = 2 };
 namespace rm {
 constexpr int PX = TX + 2, PY = TY + 2, PN = PX * PY;  // x plane, 1-cell halo
 constexpr int XR = (PN + NT - 1) / NT;
@@ -129,99 +137,125 @@ constexpr int PF = 4;
 constexpr int XS = 4;
 }  // namespace rm
 
-template <typename T, int SEGZ>
-__global__ __launch_bounds__(NT) void k_restrict_march(const T *__restrict__ x, const T *__restrict__ f,
+template <typename T, int SEGZ, int MODE>
+__global__ __launch_bounds__(NT) void k_residual_march(const T *__restrict__ x, const T *__restrict__ f,
                                                        const uint8_t *__restrict__ code, int nx, int ny, int nz,
-                                                       T ih2, const Seg *__restrict__ segs, int nsegs,
+                                                       T ih2, const Seg *__restrict__ segs,
+                                                       const unsigned long long *__restrict__ pm, int nsegs,
                                                        const T *__restrict__ cd, int cnx, int cny,
-                                                       T *__restrict__ fc) {
+                                                       T *__restrict__ fc, double *__restrict__ part,
+                                                       float *__restrict__ r32) {
     using namespace rm;
     __shared__ T xs[XS][PN];
+    __shared__ unsigned long long ms[SEGZ + 4];
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= nsegs) return;
     const Seg sg = segs[item];
     const int tid = threadIdx.x;
+    if (tid < SEGZ + 4) ms[tid] = pm[(size_t)item * (SEGZ + 4) + tid];
     const int gx0 = sg.x0 - 1, gy0 = sg.y0 - 1;
     const int z0 = max(sg.z0, 0), z1 = min(sg.z1, nz);
     const size_t plane = (size_t)nx * ny;
-    // plane elements of this thread (x with halo) and its own cell
+    const int pbytes = (int)(plane * sizeof(T));
+    constexpr int TSH = sizeof(T) == 8 ? 3 : 2;  // byte offset -> element offset
+    // plane elements of this thread (x with halo) and its own cell: byte
+    // offsets (OFF_NONE outside the box) and mask bits (one byte each)
     int xoff[XR];
-    unsigned okx = 0;
+    unsigned bits = 0;
 #pragma unroll
     for (int q = 0; q < XR; q++) {
         const int e = min(tid + q * NT, PN - 1);
         const int gx = gx0 + e % PX, gy = gy0 + e / PX;
-        okx |= (unsigned)((tid + q * NT < PN) && gx >= 0 && gx < nx && gy >= 0 && gy < ny) << q;
-        xoff[q] = min(max(gy, 0), ny - 1) * nx + min(max(gx, 0), nx - 1);
+        const bool in = (tid + q * NT < PN) && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        xoff[q] = in ? (gy * nx + gx) * (int)sizeof(T) : OFF_NONE;
+        bits |= (unsigned)item_mask_bit(e % PX + 1, e / PX + 1) << (8 * q);
     }
+    static_assert(XR < 4, "mask bit indices are packed into one word");
     const int u = tid % TX, v = tid / TX;
     const int ci = sg.x0 + u, cj = sg.y0 + v;
     const bool own = ci < nx && cj < ny;
-    const int coff = min(cj, ny - 1) * nx + min(ci, nx - 1);
+    const int coff = own ? (cj * nx + ci) * (int)sizeof(T) : OFF_NONE;
+    bits |= (unsigned)item_mask_bit(u + 2, v + 2) << (8 * XR);
     const int q0 = (v + 1) * PX + (u + 1);  // own cell in the x plane
+    __syncthreads();  // masks
+    auto mbit = [&](unsigned long long m, int j) { return (bool)((m >> ((bits >> (8 * j)) & 63u)) & 1ull); };
 
     struct Regs {
         T x[XR];
         T f;
         uint8_t c;
-        bool kin;
     };
-    auto fetch = [&](Regs &r, int k) {
-        r.kin = k >= 0 && k < nz;
+    // plane k = z0 - 2 + pi
+    auto fetch = [&](Regs &r, int k, int pi) {
+        const unsigned long long m = (k >= 0 && k < nz) ? ms[pi] : 0ull;
         const size_t base = (size_t)min(max(k, 0), nz - 1) * plane;
+        const __amdgpu_buffer_rsrc_t rx = rsrc(x ? x + base : f + base, x ? pbytes : 0);
 #pragma unroll
-        for (int q = 0; q < XR; q++) r.x[q] = x[base + xoff[q]];
-        r.f = f[base + coff];
-        r.c = code[base + coff];
+        for (int q = 0; q < XR; q++) r.x[q] = bload<T>(rx, mbit(m, q) ? xoff[q] : OFF_NONE);
+        const int oo = mbit(m, XR) ? coff : OFF_NONE;
+        r.f = bload<T>(rsrc(f + base, pbytes), oo);
+        r.c = bload<uint8_t>(rsrc(code + base, (int)plane), oo == OFF_NONE ? OFF_NONE : oo >> TSH);
     };
-    auto commit = [&](const Regs &r, int k) {
-        T *d = xs[(k + XS) % XS];
+    auto commit = [&](const Regs &r, int j) {  // plane z0 + j, j >= -1
+        T *d = xs[(j + XS) % XS];
 #pragma unroll
         for (int q = 0; q < XR; q++)
-            if (tid + q * NT < PN) d[tid + q * NT] = (r.kin && ((okx >> q) & 1u)) ? r.x[q] : T(0);
+            if (tid + q * NT < PN) d[tid + q * NT] = r.x[q];
     };
 
-    // steps commit planes z0-1 .. z1; step of plane p computes the residual
-    // of plane p-1 (f and code of plane p-1 held from the previous step)
+    // steps commit planes z0-1 .. z0+SEGZ; the step of plane p computes the
+    // residual of plane p-1 (f and code of plane p-1 held from the previous step)
     constexpr int NSTEP = SEGZ + 2;
     Regs r[PF];
 #pragma unroll
-    for (int q = 0; q < PF; q++) fetch(r[q], z0 - 1 + q);
+    for (int q = 0; q < PF; q++) fetch(r[q], z0 - 1 + q, q + 1);
     T hold_f = T(0), acc = T(0);
+    double sq = 0.0;
     uint8_t hold_c = CODE_OFF;
 #pragma unroll
     for (int st = 0; st < NSTEP; st++) {
-        const int p = z0 - 1 + st;
+        const int j = st - 2;  // plane z0 + j gets its residual in this step
         const T fprev = hold_f;
         const uint8_t cprev = hold_c;
         hold_f = r[st % PF].f;
-        hold_c = (r[st % PF].kin && own) ? r[st % PF].c : CODE_OFF;
-        commit(r[st % PF], p);
-        if (st + PF < NSTEP) fetch(r[st % PF], p + PF);
+        hold_c = r[st % PF].c;
+        commit(r[st % PF], j + 1);
+        if (st + PF < NSTEP) fetch(r[st % PF], z0 + j + 1 + PF, st + 1 + PF);
         __syncthreads();
-        const int k = p - 1;
-        if (k >= z0 && k < z1) {  // uniform; k = z0 .. z1-1 at steps 2 .. z1-z0+1
-            const T *xc = xs[(k + XS) % XS];
-            const T *xd = xs[(k - 1 + XS) % XS];
-            const T *xu = xs[(k + 1 + XS) % XS];
+        const int k = z0 + j;
+        if (j >= 0 && k < z1) {  // uniform
+            const T *xc = xs[(j + XS) % XS];
+            const T *xd = xs[(j - 1 + XS) % XS];
+            const T *xu = xs[(j + 1 + XS) % XS];
             T rr = T(0);
             if (cprev != CODE_OFF) {
                 const T d = T((int)cprev);
                 const T sum = ((xc[q0 - 1] + xc[q0 + 1]) + (xc[q0 - PX] + xc[q0 + PX])) + (xd[q0] + xu[q0]);
                 rr = (sum - d * xc[q0]) * ih2 - fprev;
             }
-            T s2 = rr + __shfl_xor(rr, 1);
-            s2 += __shfl_xor(s2, 32);
-            if ((k & 1) == 0) {
-                acc = s2;
-            } else {
-                acc += s2;
-                if ((u & 1) == 0 && (v & 1) == 0 && own) {
-                    const size_t P = ((size_t)(k >> 1) * cny + (cj >> 1)) * cnx + (ci >> 1);
-                    fc[P] = cd[P] != T(0) ? -acc / T(8) : T(0);
+            if constexpr (MODE == RM_RESTRICT) {
+                T s2 = rr + __shfl_xor(rr, 1);
+                s2 += __shfl_xor(s2, 32);
+                if ((k & 1) == 0) {
+                    acc = s2;
+                } else {
+                    acc += s2;
+                    if ((u & 1) == 0 && (v & 1) == 0 && own) {
+                        const size_t P = ((size_t)(k >> 1) * cny + (cj >> 1)) * cnx + (ci >> 1);
+                        fc[P] = cd[P] != T(0) ? -acc / T(8) : T(0);
+                    }
                 }
+            } else {
+                sq += (double)rr * (double)rr;
+                if constexpr (MODE == RM_NORM32)
+                    bstore<float>((float)(-rr), rsrc(r32 + (size_t)k * plane, (int)(plane * sizeof(float))),
+                                  cprev != CODE_OFF ? coff >> (TSH - 2) : OFF_NONE);
             }
         }
+    }
+    if constexpr (MODE != RM_RESTRICT) {
+        const double t = block_sum(sq);
+        if (tid == 0) part[item] = t;
     }
 }
 
@@ -230,11 +264,13 @@ __global__ __launch_bounds__(NT) void k_restrict_march(const T *__restrict__ x, 
 // footprint with a 1-cell halo, planes z0/2 - 1 .. z1/2) are staged in LDS
 // once; thread (u, v) owns one fine column, issues the loads of its whole
 // column first, then adds the interpolated correction on active cells (same
-// weights and summation order as prolong_col).
+// weights and summation order as prolong_col).  Fine loads and stores are
+// masked by the item's activity masks.
 template <typename T, int SEGZ>
 __global__ __launch_bounds__(NT) void k_prolong_march(const uint8_t *__restrict__ code, const T *__restrict__ xc,
                                                       int cnx, int cny, int cnz, T *__restrict__ x, int nx, int ny,
-                                                      int nz, const Seg *__restrict__ segs, int nsegs) {
+                                                      int nz, const Seg *__restrict__ segs,
+                                                      const unsigned long long *__restrict__ pm, int nsegs) {
     constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CP = CX * CY;
     constexpr int NCZ = SEGZ / 2 + 2;
     __shared__ T cs[NCZ][CP];
@@ -242,6 +278,7 @@ __global__ __launch_bounds__(NT) void k_prolong_march(const uint8_t *__restrict_
     if (item >= nsegs) return;
     const Seg sg = segs[item];
     const int tid = threadIdx.x;
+    const unsigned long long *im = pm + (size_t)item * (SEGZ + 4);
     const int z0 = max(sg.z0, 0), z1 = min(sg.z1, nz);  // even (tile-aligned, even dims)
     const int I0 = sg.x0 / 2 - 1, J0 = sg.y0 / 2 - 1, K0 = z0 / 2 - 1;
     const size_t cpl = (size_t)cnx * cny, pl = (size_t)nx * ny;
@@ -256,14 +293,20 @@ __global__ __launch_bounds__(NT) void k_prolong_march(const uint8_t *__restrict_
     const int u = tid % TX, v = tid / TX;
     const int i = sg.x0 + u, j = sg.y0 + v;
     const bool own = i < nx && j < ny;
-    const size_t c0 = (size_t)min(j, ny - 1) * nx + min(i, nx - 1);
+    const int c0 = own ? j * nx + i : 0;
+    const int mb = item_mask_bit(u + 2, v + 2);
+    const int pbytes = (int)(pl * sizeof(T));
     T xv[SEGZ];
     uint8_t cv[SEGZ];
+    int oq[SEGZ];  // own cell's element offset per plane, OFF_NONE when masked
 #pragma unroll
     for (int q = 0; q < SEGZ; q++) {
-        const size_t b = (size_t)min(z0 + q, nz - 1) * pl;
-        xv[q] = x[b + c0];
-        cv[q] = code[b + c0];
+        const int k = z0 + q;
+        const bool ld = own && k < z1 && ((im[q + 2] >> mb) & 1ull);
+        oq[q] = ld ? c0 : OFF_NONE;
+        const size_t b = (size_t)min(k, nz - 1) * pl;
+        xv[q] = bload<T>(rsrc(x + b, pbytes), ld ? c0 * (int)sizeof(T) : OFF_NONE);
+        cv[q] = bload<uint8_t>(rsrc(code + b, (int)pl), oq[q]);
     }
     __syncthreads();
     const int a0 = u / 2 + 1, b0 = v / 2 + 1;  // parent in the staged footprint
@@ -283,7 +326,7 @@ __global__ __launch_bounds__(NT) void k_prolong_march(const uint8_t *__restrict_
 #pragma unroll
                 for (int a = 0; a < 2; a++)
                     s += w4[a] * w4[b] * w4[cz] * cs[cz ? nk : pk][(b0 + b * sy) * CX + (a0 + a * sx)];
-        x[(size_t)k * pl + c0] = xv[q] + s;
+        bstore<T>(xv[q] + s, rsrc(x + (size_t)k * pl, pbytes), oq[q] * (int)sizeof(T));
     }
 }
 
@@ -345,30 +388,27 @@ void launch_copy_masked(const Level &L, int level, const OrderData &od, const do
 void launch_resnorm(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *part,
                     double *out, int slot, hipStream_t s) {
     const double ih2 = 1.0 / (L.h * L.h);
-    const unsigned g = gridc(od.ntiles);
-    if (od.ntiles) {
-        if (level == 0) {
-            if (x)
-                k_resnorm<true, true, false><<<g, NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz, ih2,
-                                                              L.code, nullptr, x, f, part, nullptr);
-            else
-                k_resnorm<true, false, false><<<g, NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
-                                                               ih2, L.code, nullptr, x, f, part, nullptr);
-        } else {
-            k_resnorm<false, true, false><<<g, NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz, ih2,
-                                                           nullptr, od.d, x, f, part, nullptr);
-        }
+    if (level == 0) {
+        if (od.nsegs)
+            k_residual_march<double, SEG_TILES_FINE * TZ, RM_NORM><<<grid8(od.nsegs), NT, 0, s>>>(
+                x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part,
+                nullptr);
+        k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot);
+        return;
     }
+    if (od.ntiles)
+        k_resnorm<false, true, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny,
+                                                                      L.nz, ih2, nullptr, od.d, x, f, part, nullptr);
     k_finalize<<<1, 1024, 0, s>>>(part, od.ntiles * NQ, out, slot);
 }
 
 void launch_resnorm32(const Level &L, const OrderData &od, const double *x, const double *f, float *r32, double *part,
                       double *out, int slot, hipStream_t s) {
     const double ih2 = 1.0 / (L.h * L.h);
-    if (od.ntiles)
-        k_resnorm<true, true, true><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny,
-                                                                    L.nz, ih2, L.code, nullptr, x, f, part, r32);
-    k_finalize<<<1, 1024, 0, s>>>(part, od.ntiles * NQ, out, slot);
+    if (od.nsegs)
+        k_residual_march<double, SEG_TILES_FINE * TZ, RM_NORM32><<<grid8(od.nsegs), NT, 0, s>>>(
+            x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32);
+    k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot);
 }
 
 void launch_residual(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *r,
@@ -391,8 +431,9 @@ void launch_restrict(const Level &L, const Level &C, int level, int order, const
     if (level == 0) {
         const OrderData &fo = L.od[2];
         if (fo.nsegs)
-            k_restrict_march<double, SEG_TILES_FINE * TZ><<<grid8(fo.nsegs), NT, 0, s>>>(
-                x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.nsegs, co.d, C.nx, C.ny, fc);
+            k_residual_march<double, SEG_TILES_FINE * TZ, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
+                x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d, C.nx, C.ny, fc, nullptr,
+                nullptr);
     } else
         k_restrict<double, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny,
                                                                   C.nz, co.d, L.nx, L.ny, L.nz, ih2, nullptr,
@@ -407,8 +448,9 @@ void launch_restrict32(const Level &L, const Level &C, int level, int order, con
     if (level == 0) {
         const OrderData &fo = L.od[2];
         if (fo.nsegs)
-            k_restrict_march<float, SEG_TILES_FINE * TZ><<<grid8(fo.nsegs), NT, 0, s>>>(
-                x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.nsegs, co.d32, C.nx, C.ny, fc);
+            k_residual_march<float, SEG_TILES_FINE * TZ, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
+                x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d32, C.nx, C.ny, fc, nullptr,
+                nullptr);
     } else
         k_restrict<float, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny, C.nz,
                                                                  co.d32, L.nx, L.ny, L.nz, ih2, nullptr,
@@ -421,8 +463,8 @@ void launch_prolong(const Level &L, const Level &C, int level, int order, const 
     if (!od.ntiles) return;
     if (level == 0) {
         if (od.nsegs)
-            k_prolong_march<double, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(L.code, xc, C.nx, C.ny, C.nz, x,
-                                                                                   L.nx, L.ny, L.nz, od.segs, od.nsegs);
+            k_prolong_march<double, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
+                L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs);
     } else
         k_prolong<double, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
                                                                  nullptr, od.d, xc, C.nx, C.ny, C.nz, x);
@@ -434,8 +476,8 @@ void launch_prolong32(const Level &L, const Level &C, int level, int order, cons
     if (!od.ntiles) return;
     if (level == 0) {
         if (od.nsegs)
-            k_prolong_march<float, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(L.code, xc, C.nx, C.ny, C.nz, x,
-                                                                                   L.nx, L.ny, L.nz, od.segs, od.nsegs);
+            k_prolong_march<float, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
+                L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs);
     } else
         k_prolong<float, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
                                                                 nullptr, od.d32, xc, C.nx, C.ny, C.nz, x);
