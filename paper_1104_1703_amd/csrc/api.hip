@@ -335,11 +335,12 @@ void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *pari
         launch_resnorm(L0, 0, od0, L0.x[cur.c[0]], L0.f, H->part, H->norm_dev, 0, H->stream);
     } else {
         mg_level(H, 0, order, true, cur, true);
-        launch_axpy32(L0, od0, L0.x32[cur.c[0]], L0.x[parity], H->stream);
-        launch_resnorm32(L0, od0, L0.x[parity], L0.f, L0.f32, H->part, H->norm_dev, 0, H->stream);
+        // x + e goes to the other FP64 buffer (unused by the FP32 inner cycle)
+        launch_axpy_resnorm32(L0, od0, L0.x[parity], L0.x32[cur.c[0]], L0.x[parity ^ 1], L0.f, L0.f32, H->part,
+                              H->norm_dev, 0, H->stream);
     }
     HIPCHK(hipMemcpyAsync(H->norm_host, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
-    *parity_out = mixed ? parity : cur.c[0];
+    *parity_out = mixed ? parity ^ 1 : cur.c[0];
 }
 
 int cycle_parity_after(const mg_hierarchy *H, int order, int parity) {
@@ -356,7 +357,7 @@ void run_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_o
     for (auto &g : H->graphs)
         if (g.order == order && g.parity == parity && g.mixed == mixed) {
             HIPCHK(hipGraphLaunch(g.exec, H->stream));
-            *parity_out = mixed ? parity : cycle_parity_after(H, order, parity);
+            *parity_out = mixed ? parity ^ 1 : cycle_parity_after(H, order, parity);
             return;
         }
     hipGraph_t graph = nullptr;

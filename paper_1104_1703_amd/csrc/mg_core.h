@@ -167,9 +167,13 @@ void launch_prolong32(const Level &L, const Level &C, int level, int order, cons
 void launch_zero_tiles(const Level &L, const OrderData &od, double *x, hipStream_t s);
 void launch_zero_tiles32(const Level &L, const OrderData &od, float *x, hipStream_t s);
 // Mixed precision: outer FP64 residual norm of the finest level that also
-// writes r32 = f - L x in float (the inner right-hand side), and x += e.
+// writes r32 = f - L x in float (the inner right-hand side).
 void launch_resnorm32(const Level &L, const OrderData &od, const double *x, const double *f, float *r32, double *part,
                       double *out, int slot, hipStream_t s);
-void launch_axpy32(const Level &L, const OrderData &od, const float *e, double *x, hipStream_t s);
+// Mixed precision, end of an outer iteration: xo = x + e on active cells (xo
+// must differ from x), then the FP64 residual norm of xo and r32 = f - L xo
+// in float.
+void launch_axpy_resnorm32(const Level &L, const OrderData &od, const double *x, const float *e, double *xo,
+                           const double *f, float *r32, double *part, double *out, int slot, hipStream_t s);
 
 }  // namespace mg

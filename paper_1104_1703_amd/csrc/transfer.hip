@@ -129,7 +129,11 @@ __global__ __launch_bounds__(NT) void k_restrict(const int *__restrict__ ctiles,
 //  RM_NORM      sum of r^2 over the item's active cells into part[item] (x may
 //               be null: x = 0, r = -f).
 //  RM_NORM32    as RM_NORM, and -r is written in float to r32 on active cells.
-enum { RM_RESTRICT = 0, RM_NORM = 1, RM_NORM32 = 2 };
+//  RM_AXPY32    the correction is added first: the residual and norm are those
+//               of x + e (e a float correction), x + e is written to xo on
+//               active cells (xo != x: neighbouring items read x as halo) and
+//               -r in float to r32.
+enum { RM_RESTRICT = 0, RM_NORM = 1, RM_NORM32 = 2, RM_AXPY32 = 3 };
 namespace rm {
 constexpr int PX = TX + 2, PY = TY + 2, PN = PX * PY;  // x plane, 1-cell halo
 constexpr int XR = (PN + NT - 1) / NT;
@@ -144,7 +148,8 @@ __global__ __launch_bounds__(NT) void k_residual_march(const T *__restrict__ x, 
                                                        const unsigned long long *__restrict__ pm, int nsegs,
                                                        const T *__restrict__ cd, int cnx, int cny,
                                                        T *__restrict__ fc, double *__restrict__ part,
-                                                       float *__restrict__ r32) {
+                                                       float *__restrict__ r32, const float *__restrict__ ecor,
+                                                       T *__restrict__ xo) {
     using namespace rm;
     __shared__ T xs[XS][PN];
     __shared__ unsigned long long ms[SEGZ + 4];
@@ -182,6 +187,7 @@ __global__ __launch_bounds__(NT) void k_residual_march(const T *__restrict__ x, 
 
     struct Regs {
         T x[XR];
+        float e[MODE == RM_AXPY32 ? XR : 1];
         T f;
         uint8_t c;
     };
@@ -192,6 +198,12 @@ __global__ __launch_bounds__(NT) void k_residual_march(const T *__restrict__ x, 
         const __amdgpu_buffer_rsrc_t rx = rsrc(x ? x + base : f + base, x ? pbytes : 0);
 #pragma unroll
         for (int q = 0; q < XR; q++) r.x[q] = bload<T>(rx, mbit(m, q) ? xoff[q] : OFF_NONE);
+        if constexpr (MODE == RM_AXPY32) {
+            const __amdgpu_buffer_rsrc_t re = rsrc(ecor + base, (int)(plane * sizeof(float)));
+#pragma unroll
+            for (int q = 0; q < XR; q++)
+                r.e[q] = bload<float>(re, mbit(m, q) && xoff[q] != OFF_NONE ? xoff[q] >> (TSH - 2) : OFF_NONE);
+        }
         const int oo = mbit(m, XR) ? coff : OFF_NONE;
         r.f = bload<T>(rsrc(f + base, pbytes), oo);
         r.c = bload<uint8_t>(rsrc(code + base, (int)plane), oo == OFF_NONE ? OFF_NONE : oo >> TSH);
@@ -199,8 +211,11 @@ __global__ __launch_bounds__(NT) void k_residual_march(const T *__restrict__ x, 
     auto commit = [&](const Regs &r, int j) {  // plane z0 + j, j >= -1
         T *d = xs[(j + XS) % XS];
 #pragma unroll
-        for (int q = 0; q < XR; q++)
-            if (tid + q * NT < PN) d[tid + q * NT] = r.x[q];
+        for (int q = 0; q < XR; q++) {
+            if (tid + q * NT >= PN) continue;
+            if constexpr (MODE == RM_AXPY32) d[tid + q * NT] = r.x[q] + (T)r.e[q];
+            else d[tid + q * NT] = r.x[q];
+        }
     };
 
     // steps commit planes z0-1 .. z0+SEGZ; the step of plane p computes the
@@ -247,9 +262,12 @@ __global__ __launch_bounds__(NT) void k_residual_march(const T *__restrict__ x, 
                 }
             } else {
                 sq += (double)rr * (double)rr;
-                if constexpr (MODE == RM_NORM32)
+                const bool act = cprev != CODE_OFF;
+                if constexpr (MODE == RM_NORM32 || MODE == RM_AXPY32)
                     bstore<float>((float)(-rr), rsrc(r32 + (size_t)k * plane, (int)(plane * sizeof(float))),
-                                  cprev != CODE_OFF ? coff >> (TSH - 2) : OFF_NONE);
+                                  act ? coff >> (TSH - 2) : OFF_NONE);
+                if constexpr (MODE == RM_AXPY32)
+                    bstore<T>(xc[q0], rsrc(xo + (size_t)k * plane, pbytes), act ? coff : OFF_NONE);
             }
         }
     }
@@ -349,17 +367,6 @@ __global__ __launch_bounds__(NT) void k_zero_tiles(const int *__restrict__ tiles
     if (t.ok) x[(size_t)t.k * nx * ny + (size_t)t.j * nx + t.i] = T(0);
 }
 
-__global__ __launch_bounds__(NT) void k_axpy32(const int *__restrict__ tiles, int ntiles, int ntx, int nty, int nx,
-                                               int ny, int nz, const uint8_t *__restrict__ code,
-                                               const float *__restrict__ e, double *__restrict__ x) {
-    int tile, kk, w;
-    if (!block_tile(tiles, ntiles, TZ, tile, kk, w)) return;
-    const TileCoord t = tile_cell(tile, kk, ntx, nty, nx, ny, nz);
-    if (!t.ok) return;
-    const size_t p = (size_t)t.k * nx * ny + (size_t)t.j * nx + t.i;
-    if (code[p] != CODE_OFF) x[p] += (double)e[p];
-}
-
 }  // namespace
 
 void launch_fold(const Level &L, const OrderData &od, const double *rho, const double *B, const double *phi,
@@ -392,7 +399,7 @@ void launch_resnorm(const Level &L, int level, const OrderData &od, const double
         if (od.nsegs)
             k_residual_march<double, SEG_TILES_FINE * TZ, RM_NORM><<<grid8(od.nsegs), NT, 0, s>>>(
                 x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part,
-                nullptr);
+                nullptr, nullptr, nullptr);
         k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot);
         return;
     }
@@ -407,7 +414,18 @@ void launch_resnorm32(const Level &L, const OrderData &od, const double *x, cons
     const double ih2 = 1.0 / (L.h * L.h);
     if (od.nsegs)
         k_residual_march<double, SEG_TILES_FINE * TZ, RM_NORM32><<<grid8(od.nsegs), NT, 0, s>>>(
-            x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32);
+            x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32,
+            nullptr, nullptr);
+    k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot);
+}
+
+void launch_axpy_resnorm32(const Level &L, const OrderData &od, const double *x, const float *e, double *xo,
+                           const double *f, float *r32, double *part, double *out, int slot, hipStream_t s) {
+    const double ih2 = 1.0 / (L.h * L.h);
+    if (od.nsegs)
+        k_residual_march<double, SEG_TILES_FINE * TZ, RM_AXPY32><<<grid8(od.nsegs), NT, 0, s>>>(
+            x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32, e,
+            xo);
     k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot);
 }
 
@@ -433,7 +451,7 @@ void launch_restrict(const Level &L, const Level &C, int level, int order, const
         if (fo.nsegs)
             k_residual_march<double, SEG_TILES_FINE * TZ, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
                 x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d, C.nx, C.ny, fc, nullptr,
-                nullptr);
+                nullptr, nullptr, nullptr);
     } else
         k_restrict<double, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny,
                                                                   C.nz, co.d, L.nx, L.ny, L.nz, ih2, nullptr,
@@ -450,7 +468,7 @@ void launch_restrict32(const Level &L, const Level &C, int level, int order, con
         if (fo.nsegs)
             k_residual_march<float, SEG_TILES_FINE * TZ, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
                 x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d32, C.nx, C.ny, fc, nullptr,
-                nullptr);
+                nullptr, nullptr, nullptr);
     } else
         k_restrict<float, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny, C.nz,
                                                                  co.d32, L.nx, L.ny, L.nz, ih2, nullptr,
@@ -491,11 +509,6 @@ void launch_zero_tiles(const Level &L, const OrderData &od, double *x, hipStream
 void launch_zero_tiles32(const Level &L, const OrderData &od, float *x, hipStream_t s) {
     if (!od.ntiles) return;
     k_zero_tiles<float><<<gridt(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz, x);
-}
-
-void launch_axpy32(const Level &L, const OrderData &od, const float *e, double *x, hipStream_t s) {
-    if (!od.ntiles) return;
-    k_axpy32<<<gridt(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz, L.code, e, x);
 }
 
 }  // namespace mg
