@@ -294,9 +294,18 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
     if (f32) launch_restrict32(L, C, l, order, L.x32[cur.c[l]], L.f32, C.f32, H->stream);
     else launch_restrict(L, C, l, order, L.x[cur.c[l]], L.f, C.f, H->stream);
     for (int c = 0; c < o.n_cycles; c++) mg_level(H, l + 1, order, c == 0, cur, f32);
-    if (f32) launch_prolong32(L, C, l, order, C.x32[cur.c[l + 1]], L.x32[cur.c[l]], H->stream);
-    else launch_prolong(L, C, l, order, C.x[cur.c[l + 1]], L.x[cur.c[l]], H->stream);
-    smooth(H, l, order, o.n_post, false, cur, f32);
+    if (o.n_post == 0) {
+        if (f32) launch_prolong32(L, C, l, order, C.x32[cur.c[l + 1]], L.x32[cur.c[l]], H->stream);
+        else launch_prolong(L, C, l, order, C.x[cur.c[l + 1]], L.x[cur.c[l]], H->stream);
+        return;
+    }
+    // the first post-smoothing pass applies the prolongation as it loads x
+    const OrderData &od = odata(H, l, order);
+    const int a = cur.c[l], b = a ^ 1;
+    if (f32) launch_rbgs_prolong32(L, l, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream);
+    else launch_rbgs_prolong(L, l, od, C, C.x[cur.c[l + 1]], L.x[a], L.x[b], L.f, H->stream);
+    cur.c[l] = b;
+    smooth(H, l, order, o.n_post - 1, false, cur, f32);
 }
 
 // Coarse iterates must be 0 outside the active tiles of the order in use.

@@ -134,6 +134,13 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
                  const double *f, hipStream_t s);
 void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
                    hipStream_t s);
+// A pass that first adds the P2 prolongation of the coarse iterate xc (level
+// level + 1, dims of C) to xin on active cells, as launch_prolong would, then
+// relaxes; xin is left unchanged.
+void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const Level &C, const double *xc,
+                         const double *xin, double *xout, const double *f, hipStream_t s);
+void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const Level &C, const float *xc,
+                           const float *xin, float *xout, const float *f, hipStream_t s);
 
 // -------- small levels in one workgroup (coarse.hip) --------
 size_t small_lds_bytes(const mg_hierarchy *H, int order, int ls, bool f32);

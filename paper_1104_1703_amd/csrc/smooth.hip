@@ -31,17 +31,18 @@ namespace {
 
 using namespace rb;
 
-template <typename T, bool FINE, int SEGZ>
+template <typename T, bool FINE, int SEGZ, bool PRO = false>
 __global__ __launch_bounds__(NT, 5) void k_rbgs(const T *__restrict__ xin, T *__restrict__ xout,
                                               const T *__restrict__ f, const uint8_t *__restrict__ code,
                                               const T *__restrict__ dco, int nx, int ny, int nz, T h2,
                                               const Seg *__restrict__ segs, const unsigned long long *__restrict__ pm,
-                                              int nsegs) {
-    __shared__ RbgsLds<T, FINE> lds;
+                                              int nsegs, const T *__restrict__ xc = nullptr, int cnx = 0,
+                                              int cny = 0, int cnz = 0) {
+    __shared__ RbgsLds<T, FINE, PRO> lds;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= nsegs) return;
-    rbgs_item<T, FINE, SEGZ>(lds, xin, xout, f, code, dco, nx, ny, nz, h2, segs[item],
-                             pm + (size_t)item * (SEGZ + 4));
+    rbgs_item<T, FINE, SEGZ, PRO>(lds, xin, xout, f, code, dco, nx, ny, nz, h2, segs[item],
+                                  pm + (size_t)item * (SEGZ + 4), xc, cnx, cny, cnz);
 }
 
 inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
@@ -49,15 +50,16 @@ inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
 }  // namespace
 
 // Coarse levels: the kernel instance for the level's item depth.
-template <typename T>
+template <typename T, bool PRO = false>
 void launch_coarse(int depth, const T *xin, T *xout, const T *f, const T *d, const Level &L, const OrderData &od,
-                   T h2, hipStream_t s) {
+                   T h2, hipStream_t s, const T *xc = nullptr, const Level *C = nullptr) {
+    const int cnx = C ? C->nx : 0, cny = C ? C->ny : 0, cnz = C ? C->nz : 0;
     if (depth == 8)
-        k_rbgs<T, false, 8><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs,
-                                                          od.pmask, od.nsegs);
+        k_rbgs<T, false, 8, PRO><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2,
+                                                               od.segs, od.pmask, od.nsegs, xc, cnx, cny, cnz);
     else
-        k_rbgs<T, false, 4><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs,
-                                                          od.pmask, od.nsegs);
+        k_rbgs<T, false, 4, PRO><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2,
+                                                               od.segs, od.pmask, od.nsegs, xc, cnx, cny, cnz);
 }
 static_assert((SEGZ_COARSE1 == 4 || SEGZ_COARSE1 == 8) && (SEGZ_COARSE == 4 || SEGZ_COARSE == 8),
               "coarse item depths have kernel instances for 4 and 8 planes");
@@ -71,6 +73,28 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
             xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs);
     else
         launch_coarse<double>(item_depth(level), xin, xout, f, od.d, L, od, h2, s);
+}
+
+void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const Level &C, const double *xc,
+                         const double *xin, double *xout, const double *f, hipStream_t s) {
+    if (od.nsegs == 0) return;
+    const double h2 = L.h * L.h;
+    if (level == 0)
+        k_rbgs<double, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
+            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, xc, C.nx, C.ny, C.nz);
+    else
+        launch_coarse<double, true>(item_depth(level), xin, xout, f, od.d, L, od, h2, s, xc, &C);
+}
+
+void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const Level &C, const float *xc,
+                           const float *xin, float *xout, const float *f, hipStream_t s) {
+    if (od.nsegs == 0) return;
+    const float h2 = (float)(L.h * L.h);
+    if (level == 0)
+        k_rbgs<float, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
+            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, xc, C.nx, C.ny, C.nz);
+    else
+        launch_coarse<float, true>(item_depth(level), xin, xout, f, od.d32, L, od, h2, s, xc, &C);
 }
 
 void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,

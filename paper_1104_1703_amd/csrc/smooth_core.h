@@ -23,6 +23,7 @@ constexpr int QR = (QN + NT - 1) / NT;  // f elements per thread per plane
 // bytes of float planes; measured on the 256^3 workload, three are best for
 // doubles and more would only keep lines in L2 longer.
 constexpr int PF64 = 3, PF32 = 4;
+constexpr int PFC = 3;  // coarse levels
 
 // Work items are dealt to the 8 XCDs round-robin by block id; give each XCD a
 // contiguous range of work items so that halo re-reads hit its own L2.
@@ -31,11 +32,15 @@ __device__ __forceinline__ int xcd_item(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
-template <typename T, bool FINE>
+// PRO: the pass starts with the P2 prolongation and correction x += P2(xc)
+// applied to every plane as it enters LDS (the first post-smoothing pass); the
+// diagonal or code is then kept on the whole x plane (the 2-cell halo must be
+// known inactive to stay zero).
+template <typename T, bool FINE, bool PRO>
 struct PlaneRegs {
     T x[XR];
     T f[QR];
-    typename std::conditional<FINE, uint8_t, T>::type d[QR];  // raw code byte or diagonal
+    typename std::conditional<FINE, uint8_t, T>::type d[PRO ? XR : QR];  // raw code byte or diagonal
 };
 
 // LDS of one work item: a 5-plane ring of x (2-cell halo), and 4-plane rings
@@ -44,28 +49,37 @@ struct PlaneRegs {
 // touches lets a step commit its new plane while the previous step's black
 // half-sweep may still read the oldest one, so a step needs two barriers.
 // `m` holds the item's activity masks, one word per plane (see item_mask_bit).
-constexpr int XS = 5, FS = 4;
+// With PRO, `c` is a 4-plane ring of the coarse footprint of the x plane
+// (CX x CY coarse cells at (x0/2 - 2, y0/2 - 2)).
+constexpr int XS = 5, FS = 4, CS = 4;
+constexpr int CX = BX / 2 + 4, CY = BY / 2 + 4, CPN = CX * CY;
+static_assert(CPN <= NT, "one coarse element per thread");
 constexpr int MAXPL = SEG_TILES_FINE * TZ + 4;  // planes touched by the longest work item
-template <typename T, bool FINE>
+template <typename T, bool FINE, bool PRO = false>
 struct RbgsLds {
     using DT = typename std::conditional<FINE, uint8_t, T>::type;
+    static constexpr int DN = PRO ? PN : QN;
     T x[XS][PN];
     T f[FS][QN];
-    DT d[FS][QN];
+    DT d[FS][DN];
     unsigned long long m[MAXPL];
+    T c[PRO ? CS : 1][PRO ? CPN : 1];
 };
 
 // One full red-black pass over one work item (see the file comment of
 // smooth.hip).  Called by all 256 threads of a block.  `pm`: the item's
 // SEGZ + 4 activity masks, or nullptr to load every in-box cell.  A plane of
-// the level must hold fewer than 2^31 bytes.
-template <typename T, bool FINE, int SEGZ>
-__device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restrict__ xin, T *__restrict__ xout,
-                                          const T *__restrict__ f, const uint8_t *__restrict__ code,
-                                          const T *__restrict__ dco, int nx, int ny, int nz, T h2, const Seg sg,
-                                          const unsigned long long *__restrict__ pm) {
+// the level must hold fewer than 2^31 bytes.  PRO: xc is the next coarser
+// level's iterate (cnx x cny x cnz); the item's x0, y0 and z0 are even.
+template <typename T, bool FINE, int SEGZ, bool PRO = false>
+__device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__restrict__ xin,
+                                          T *__restrict__ xout, const T *__restrict__ f,
+                                          const uint8_t *__restrict__ code, const T *__restrict__ dco, int nx,
+                                          int ny, int nz, T h2, const Seg sg, const unsigned long long *__restrict__ pm,
+                                          const T *__restrict__ xc = nullptr, int cnx = 0, int cny = 0, int cnz = 0) {
     static_assert(SEGZ + 4 <= MAXPL, "work item longer than the mask array");
-    using DT = typename RbgsLds<T, FINE>::DT;
+    using DT = typename RbgsLds<T, FINE, PRO>::DT;
+    using Regs = PlaneRegs<T, FINE, PRO>;
     auto &sx = L.x;
     auto &sf = L.f;
     auto &sd = L.d;
@@ -102,7 +116,33 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
     static_assert(XR + QR <= 4, "mask bit indices are packed into one word");
     const int pbytes = (int)(plane * sizeof(T));
     constexpr int TSH = sizeof(T) == 8 ? 3 : 2;  // byte offset -> element offset
-    __syncthreads();  // masks
+
+    // PRO: coarse footprint element of this thread and the coarse plane loads
+    // (coarse plane index ck = K - (z0/2 - 2) >= 0)
+    const int cI0 = sg.x0 / 2 - 2, cJ0 = sg.y0 / 2 - 2, cK0 = z0 / 2 - 2;
+    int coff = OFF_NONE;
+    if constexpr (PRO) {
+        const int ci = cI0 + tid % CX, cj = cJ0 + tid / CX;
+        if (tid < CPN && ci >= 0 && ci < cnx && cj >= 0 && cj < cny) coff = (cj * cnx + ci) * (int)sizeof(T);
+    }
+    const size_t cpl = (size_t)cnx * cny;
+    auto cload = [&](int ck) -> T {
+        const int K = cK0 + ck;
+        if (!PRO || K < 0 || K >= cnz) return T(0);
+        return bload<T>(rsrc(xc + (size_t)K * cpl, (int)(cpl * sizeof(T))), coff);
+    };
+    T cr[2] = {T(0), T(0)};
+    if constexpr (PRO) {
+        const T c0 = cload(0), c1 = cload(1), c2 = cload(2);
+        if (tid < CPN) {
+            L.c[0][tid] = c0;
+            L.c[1][tid] = c1;
+            L.c[2][tid] = c2;
+        }
+        cr[0] = cload(3);
+        cr[1] = cload(4);
+    }
+    __syncthreads();  // masks (and the first coarse planes)
 
     auto mbit = [&](unsigned long long m, int j) { return (bool)((m >> ((bits >> (8 * j)) & 63u)) & 1ull); };
     // f and the diagonal are read on planes z0-1 .. z1 only
@@ -110,43 +150,79 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
     auto fload = [&](unsigned long long m, int k, int q) { return fplane(k) && qoff[q] >= 0 && mbit(m, XR + q); };
 
     // global -> registers for plane k = z0 - 2 + pi (x on planes z0-2 .. z1+1)
-    auto fetch = [&](PlaneRegs<T, FINE> &r, int k, int pi) {
+    auto fetch = [&](Regs &r, int k, int pi) {
         const bool kin = k >= 0 && k < nz && k <= z1 + 1;
         const unsigned long long m = kin ? L.m[pi] : 0ull;
         const size_t base = (size_t)min(max(k, 0), nz - 1) * plane;
         const __amdgpu_buffer_rsrc_t rx = rsrc(xin ? xin + base : f + base, xin ? pbytes : 0);
         const __amdgpu_buffer_rsrc_t rf = rsrc(f + base, pbytes);
 #pragma unroll
-        for (int q = 0; q < XR; q++) r.x[q] = bload<T>(rx, mbit(m, q) ? xoff[q] : OFF_NONE);
+        for (int q = 0; q < XR; q++) {
+            const int o = mbit(m, q) ? xoff[q] : OFF_NONE;
+            r.x[q] = bload<T>(rx, o);
+            if constexpr (PRO) {  // the diagonal on the whole x plane
+                if constexpr (FINE) r.d[q] = bload<uint8_t>(rsrc(code + base, (int)plane), o == OFF_NONE ? o : o >> TSH);
+                else r.d[q] = bload<T>(rsrc(dco + base, pbytes), o);
+            }
+        }
 #pragma unroll
         for (int q = 0; q < QR; q++) {
             const bool p = fload(m, k, q);
             r.f[q] = bload<T>(rf, p ? qoff[q] : OFF_NONE);
-            if constexpr (FINE) r.d[q] = bload<uint8_t>(rsrc(code + base, (int)plane), p ? qoff[q] >> TSH : OFF_NONE);
-            else r.d[q] = bload<T>(rsrc(dco + base, pbytes), p ? qoff[q] : OFF_NONE);
+            if constexpr (!PRO) {
+                if constexpr (FINE) r.d[q] = bload<uint8_t>(rsrc(code + base, (int)plane), p ? qoff[q] >> TSH : OFF_NONE);
+                else r.d[q] = bload<T>(rsrc(dco + base, pbytes), p ? qoff[q] : OFF_NONE);
+            }
         }
     };
     // Ring slots are indexed by a plane's position j = k - z0 in the item
     // (j >= -2), a compile-time value in the unrolled march.
     auto xslot = [](int j) { return (j + 2 * XS) % XS; };
     auto fslot = [](int j) { return (j + 2 * FS) % FS; };
+    // diagonal of x-plane cell (u, v) in its ring plane
+    auto didx = [](int u, int v) { return PRO ? v * PX + u : (v - 1) * QX + (u - 1); };
     // registers -> LDS ring slot of plane z0 + j (skipped loads read zero,
-    // which is also the code of an inactive cell)
-    auto commit = [&](const PlaneRegs<T, FINE> &r, int j) {
+    // which is also the code of an inactive cell); st = j + 2 is the step
+    auto commit = [&](const Regs &r, int j) {
         T *dx = sx[xslot(j)];
         T *df = sf[fslot(j)];
         DT *dd = sd[fslot(j)];
 #pragma unroll
         for (int q = 0; q < XR; q++) {
             const int e = tid + q * NT;
-            if (e < PN) dx[e] = r.x[q];
+            if (e >= PN) continue;
+            T xv = r.x[q];
+            if constexpr (PRO) {
+                dd[e] = r.d[q];
+                if (r.d[q] != DT(0)) {
+                    // P2: parents (I + a sx, J + b sy, K + c sz) with weights 3/4, 1/4
+                    // per axis, summed in the order of the prolongation kernels
+                    const int u = e % PX, v = e / PX, st = j + 2;
+                    const int a0 = 1 + (u >> 1), b0 = 1 + (v >> 1);
+                    const int sxx = (u & 1) ? 1 : -1, syy = (v & 1) ? 1 : -1;
+                    const int ck0 = 1 + (st >> 1), ck1 = ck0 + ((st & 1) ? 1 : -1);
+                    const T w4[2] = {T(0.75), T(0.25)};
+                    T s = T(0);
+#pragma unroll
+                    for (int cz = 0; cz < 2; cz++) {
+                        const T *cp = L.c[(cz ? ck1 : ck0) % CS];
+#pragma unroll
+                        for (int b = 0; b < 2; b++)
+#pragma unroll
+                            for (int a = 0; a < 2; a++)
+                                s += w4[a] * w4[b] * w4[cz] * cp[(b0 + b * syy) * CX + (a0 + a * sxx)];
+                    }
+                    xv = xv + s;
+                }
+            }
+            dx[e] = xv;
         }
 #pragma unroll
         for (int q = 0; q < QR; q++) {
             const int e = tid + q * NT;
             if (e < QN) {
                 df[e] = r.f[q];
-                dd[e] = r.d[q];
+                if constexpr (!PRO) dd[e] = r.d[q];
             }
         }
     };
@@ -168,8 +244,8 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
             const int u = lo + ((col + gy0 + v + k + gx0 + lo) & 1) + 2 * (e % half);
             const int qq = (v - 1) * QX + (u - 1);
             T d;
-            if constexpr (FINE) d = T((int)dq[qq]);
-            else d = dq[qq];
+            if constexpr (FINE) d = T((int)dq[didx(u, v)]);
+            else d = dq[didx(u, v)];
             if (d == T(0)) continue;
             const int q = v * PX + u;
             const T s = (c[q - 1] + c[q + 1]) + (c[q - PX] + c[q + PX]) + (dn[q] + up[q]);
@@ -186,7 +262,7 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
         for (int e = tid; e < BX * BY; e += NT) {
             const int u = 2 + e % BX, v = 2 + e / BX;
             const int gx = gx0 + u, gy = gy0 + v;
-            const bool act = dq[(v - 1) * QX + (u - 1)] != DT(0);
+            const bool act = dq[didx(u, v)] != DT(0);
             bstore<T>(c[v * PX + u], ro, act ? (gy * nx + gx) * (int)sizeof(T) : OFF_NONE);
         }
     };
@@ -197,16 +273,26 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE> &L, const T *__restri
     // planes of loads stay in flight and every wait count is exact.  Step k+2
     // commits plane k+2, relaxes red of plane k+1 and stores plane k-1 (black
     // since the previous step), then relaxes black of plane k; the last step
-    // only stores.
+    // only stores.  PRO: the commit of step st reads coarse planes
+    // ck = st/2 .. st/2 + 2; an odd step stores coarse plane st/2 + 3 for the
+    // next steps (its ring slot was last read two steps before).
     constexpr int NSTEP = SEGZ + 4;
-    constexpr int PF = sizeof(T) == 8 ? PF64 : PF32;
-    PlaneRegs<T, FINE> r[PF];
+    constexpr int PF = !FINE ? (PFC < NSTEP ? PFC : NSTEP) : sizeof(T) == 8 ? PF64 : PF32;
+    constexpr int CKMAX = ((NSTEP - 1) >> 1) + 2;  // last coarse plane read
+    Regs r[PF];
 #pragma unroll
     for (int q = 0; q < PF; q++) fetch(r[q], z0 - 2 + q, q);
 #pragma unroll
     for (int st = 0; st <= NSTEP; st++) {
         const int j = st - 4;  // plane z0 + j is black-relaxed in this step
         if (st < NSTEP) {
+            if constexpr (PRO) {
+                if ((st & 1) && (st >> 1) + 3 <= CKMAX) {
+                    const int P = (st >> 1) + 3;
+                    if (tid < CPN) L.c[P % CS][tid] = cr[(st >> 1) & 1];
+                    if (P + 2 <= CKMAX) cr[(st >> 1) & 1] = cload(P + 2);
+                }
+            }
             commit(r[st % PF], j + 2);
             if (st + PF < NSTEP) fetch(r[st % PF], z0 + j + 2 + PF, st + PF);
         }
