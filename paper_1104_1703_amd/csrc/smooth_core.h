@@ -51,7 +51,15 @@ struct PlaneRegs {
 // `m` holds the item's activity masks, one word per plane (see item_mask_bit).
 // With PRO, `c` is a 4-plane ring of the coarse footprint of the x plane
 // (CX x CY coarse cells at (x0/2 - 2, y0/2 - 2)).
-constexpr int XS = 5, FS = 4, CS = 4;
+constexpr int CS = 4;
+// Ring depths.  Coarse FP64 levels use one plane less in each ring and a
+// third barrier per step (after the black half-sweep), which keeps a block
+// under 32 KB of LDS: five blocks per CU, so a level-1 pass fits in one round.
+template <typename T, bool FINE>
+struct Rings {
+    static constexpr bool SLIM = !FINE && sizeof(T) == 8;
+    static constexpr int XS = SLIM ? 4 : 5, FS = SLIM ? 3 : 4;
+};
 constexpr int CX = BX / 2 + 4, CY = BY / 2 + 4, CPN = CX * CY;
 static_assert(CPN <= NT, "one coarse element per thread");
 constexpr int MAXPL = SEG_TILES_FINE * TZ + 4;  // planes touched by the longest work item
@@ -59,6 +67,7 @@ template <typename T, bool FINE, bool PRO = false>
 struct RbgsLds {
     using DT = typename std::conditional<FINE, uint8_t, T>::type;
     static constexpr int DN = PRO ? PN : QN;
+    static constexpr int XS = Rings<T, FINE>::XS, FS = Rings<T, FINE>::FS;
     T x[XS][PN];
     T f[FS][QN];
     DT d[FS][DN];
@@ -80,6 +89,8 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__r
     static_assert(SEGZ + 4 <= MAXPL, "work item longer than the mask array");
     using DT = typename RbgsLds<T, FINE, PRO>::DT;
     using Regs = PlaneRegs<T, FINE, PRO>;
+    constexpr bool SLIM = Rings<T, FINE>::SLIM;
+    constexpr int XS = Rings<T, FINE>::XS, FS = Rings<T, FINE>::FS;
     auto &sx = L.x;
     auto &sf = L.f;
     auto &sd = L.d;
@@ -254,7 +265,9 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__r
     };
 
     // LDS -> xout for the tile cells of plane z0 + j; inactive cells are not
-    // written (they hold zero in every iterate buffer).
+    // written (they hold zero in every iterate buffer).  The slim rings no
+    // longer hold the plane's diagonal here: every in-box cell is written
+    // (inactive ones with their zero).
     auto store = [&](int j) {
         const T *c = sx[xslot(j)];
         const DT *dq = sd[fslot(j)];
@@ -262,7 +275,9 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__r
         for (int e = tid; e < BX * BY; e += NT) {
             const int u = 2 + e % BX, v = 2 + e / BX;
             const int gx = gx0 + u, gy = gy0 + v;
-            const bool act = dq[didx(u, v)] != DT(0);
+            bool act;
+            if constexpr (SLIM) act = gx < nx && gy < ny;
+            else act = dq[didx(u, v)] != DT(0);
             bstore<T>(c[v * PX + u], ro, act ? (gy * nx + gx) * (int)sizeof(T) : OFF_NONE);
         }
     };
@@ -308,6 +323,9 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__r
             __syncthreads();
             relax(j, 1, 2);
         }
+        // slim rings: the next commit overwrites a plane this step still read
+        if constexpr (SLIM)
+            if (st >= 3 && st < NSTEP) __syncthreads();
     }
 }
 
