@@ -42,25 +42,30 @@ __device__ __forceinline__ f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f3
 // ------------------------------------------------------ conv fwd, LDS tiles
 // out = [ReLU](conv3x3x3(concat(up2?(ina), inb)) + bias) as an implicit GEMM
 // (M = voxels, N = output channels, K = 27 taps x input channels), organised
-// around LDS: a block owns an
-// 8 x 8 x 4 tile of output voxels of one sample and, for each chunk of CK
-// input channels, stages the 10 x 10 x 6 halo of its input in LDS (zeros
-// outside the box, nearest up-sampling and the skip concatenation resolved
-// while staging).  The tap loop then reads every A fragment from LDS at a
-// uniform tap offset, with no bounds tests.  Wave w computes z-plane w of
-// the tile; its fragment mt covers rows y = 2 mt, 2 mt + 1, lane row r the
-// voxel x = r mod 8, y = 2 mt + r div 8.
-constexpr int TX = 8, TY = 8, TZ = 4;
+// around LDS: a block owns a 16 x 4 x 4 tile of output voxels of one sample
+// and, for each chunk of CK input channels, stages the 18 x 6 x 6 halo of its
+// input in LDS (zeros outside the box, nearest up-sampling and the skip
+// concatenation resolved while staging).  The tap loop then reads every A
+// fragment from LDS at a uniform tap offset, with no bounds tests.  Wave w
+// computes z-plane w of the tile; its fragment mt is row y = mt, lane row r
+// the voxel x = r.  A voxel's LDS row is CK + 8 channels long (an odd number
+// of 16-byte bank groups), so the 16 x-consecutive rows of a fragment fall in
+// 16 distinct bank groups.  A chunk holding only 16 input channels (CK = 16,
+// or with HALF the last chunk when C_in = 32 q + 16) takes two taps per K step
+// of 32 (lane groups 0, 1: tap 2p; 2, 3: tap 2p + 1) instead of padding K
+// with zeros.
+constexpr int TX = 16, TY = 4, TZ = 4;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HV = HX * HY * HZ;
 
-template <int CK, int NTC>
+template <int CK, int NTC, bool HALF = false>
 __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina, int ca, int upa,
-                                                    const bf16 *__restrict__ inb, int cb, const bf16 *__restrict__ wt,
-                                                    const float *__restrict__ bias, bf16 *__restrict__ out, int cout,
-                                                    int relu, int D, int H, int W, int ntx, int nty, int ntz,
-                                                    int nblk) {
-    constexpr int CKP = CK + 8;  // padded LDS row: spreads a fragment's 16 voxels over the banks
+                                                   const bf16 *__restrict__ inb, int cb, const bf16 *__restrict__ wt,
+                                                   const float *__restrict__ bias, bf16 *__restrict__ out, int cout,
+                                                   int relu, int D, int H, int W, int ntx, int nty, int ntz,
+                                                   int nblk) {
+    constexpr int CKP = CK + 8;
     constexpr int MT = 4;
+    static_assert(MT == TY && NTH / 64 == TZ && TX == 16, "a wave owns the 16 x 4 voxels of one tile plane");
     __shared__ __attribute__((aligned(16))) bf16 tile[HV * CKP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, grp = lane >> 4;
@@ -79,7 +84,7 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
     const int Dc = D >> 1, Hc = H >> 1, Wc = W >> 1;
     int hb[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; mt++) hb[mt] = ((wave + 1) * HY + 2 * mt + (row >> 3) + 1) * HX + (row & 7) + 1;
+    for (int mt = 0; mt < MT; mt++) hb[mt] = ((wave + 1) * HY + mt + 1) * HX + row + 1;
     f32x4 acc[MT][NTC];
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
@@ -107,9 +112,8 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
             *(bf16x8 *)(tile + hv * CKP + c8) = v;
         }
         __syncthreads();
-        if constexpr (CK == 32) {
+        if (CK == 32 && (!HALF || cin - c0 >= 32)) {
             const int cw = c0 + grp * 8;  // this lane's 8 K entries: channels cw .. cw + 7 of one tap
-            const bool cok = cw < cin;
 #pragma unroll 1
             for (int tzy = 0; tzy < 9; ++tzy) {  // (dz, dy) rows of taps; the 3 dx taps unrolled
                 const int rowoff = ((tzy / 3 - 1) * HY + tzy % 3 - 1) * HX;
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
 #pragma unroll
                     for (int nt = 0; nt < NTC; nt++) {
                         const int co = co_base + nt * 16 + row;
-                        bfr[nt] = cok ? *(const bf16x8 *)(wt + ((size_t)tap * cout + co) * cin + cw) : zero8();
+                        bfr[nt] = *(const bf16x8 *)(wt + ((size_t)tap * cout + co) * cin + cw);
                     }
 #pragma unroll
                     for (int mt = 0; mt < MT; mt++) {
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
                     }
                 }
             }
-        } else {
+        } else if constexpr (CK == 16 || HALF) {
             // 16 channels per tap: one K step of 32 covers taps 2p (lane groups 0, 1) and 2p + 1 (2, 3)
             const int half = grp >> 1, cl = (grp & 1) * 8, cw = c0 + cl;
             const bool cok = cw < cin;
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
             }
         }
     }
-    // lane l holds D[4 (l div 16) + r][l mod 16]: voxel m = 4 grp + r of fragment mt, channel row
+    // lane l holds D[4 (l div 16) + r][l mod 16]: voxel x = 4 grp + r of row y = mt, channel row
     const int z = z0 + wave;
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
@@ -165,8 +169,7 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
             const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int m = grp * 4 + r;
-                const int x = x0 + (m & 7), y = y0 + 2 * mt + (m >> 3);
+                const int x = x0 + grp * 4 + r, y = y0 + mt;
                 if (x < W && y < H && z < D) {
                     float val = acc[mt][nt][r] + bv;
                     if (relu) val = fmaxf(val, 0.f);
@@ -683,6 +686,13 @@ void launch_tile(const bf16 *ina, int ca, int upa, const bf16 *inb, int cb, cons
     const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY, ntz = (D + TZ - 1) / TZ;
     const int nblk = n * ntx * nty * ntz;
     dim3 grid((unsigned)nblk, (unsigned)(cout / (16 * NTC)));
+    if constexpr (CK == 32) {
+        if ((ca + cb) % 32 == 16) {
+            k_conv_tile<CK, NTC, true><<<grid, NTH, 0, s>>>(ina, ca, upa, inb, cb, w, bias, out, cout, relu, D, H, W,
+                                                            ntx, nty, ntz, nblk);
+            return;
+        }
+    }
     k_conv_tile<CK, NTC><<<grid, NTH, 0, s>>>(ina, ca, upa, inb, cb, w, bias, out, cout, relu, D, H, W, ntx, nty, ntz,
                                               nblk);
 }
