@@ -68,7 +68,8 @@ typedef struct {
     int32_t bc_order;         /* mg_bc_order (default MG_BC_AUTO) */
     double eta;               /* switch threshold on ||r_n+1||/||r_n|| (Sec. 4: 0.5) */
     int32_t first_order_hold; /* solves kept in first order after a switch (Sec. 4: 10) */
-    int32_t use_graph;        /* 1 = replay each cycle as a captured hipGraph (default 1) */
+    int32_t use_graph;        /* 1 = replay each cycle as a captured hipGraph; 0 (default) =
+                                 launch its kernels directly (measured faster for one solve) */
     mg_allocator allocator;
 } mg_options;
 

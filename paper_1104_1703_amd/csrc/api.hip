@@ -604,7 +604,7 @@ void mg_default_options(mg_options *o) {
     o->bc_order = MG_BC_AUTO;
     o->eta = 0.5;
     o->first_order_hold = 10;
-    o->use_graph = 1;
+    o->use_graph = 0;
 }
 
 const char *mg_status_string(mg_status s) {

@@ -190,13 +190,31 @@ def test_solve_auto_switch_islands(mg):
 
 
 @pytest.mark.parametrize("opts", [dict(bc_order="first"), dict(n_cycles=2), dict(n_pre=1, n_post=2),
-                                  dict(use_graph=0), dict(n_pre=3, n_post=1, n_coarse_sweeps=7)])
+                                  dict(use_graph=1), dict(n_pre=3, n_post=1, n_coarse_sweeps=7)])
 def test_solve_options_match_oracle(mg, opts):
     p, H, got, info, ref, rinfo = _solve_pair(mg, "holes64", **opts)
     assert info["status"] == rinfo["status"]
     assert info["cycles"] == rinfo["cycles"]
     assert relerr(got, ref, p.mask == 1) <= TOL
     H.close()
+
+
+def test_graph_replays_match_direct_launches(mg):
+    """Each cycle replayed from a captured graph gives bit for bit what the
+    directly launched kernels give, on every replay (38 replays per solve,
+    host work between them) and across solves on one hierarchy."""
+    p = gen.holes_problem(64, 2)
+    rho = dev(p.rho)
+    Hd = mg.Hierarchy(dev(p.mask), p.h, use_graph=0)
+    Hg = mg.Hierarchy(dev(p.mask), p.h, use_graph=1)
+    for _ in range(3):  # the first solve switches order; the next start in first order (hold)
+        ref, rinfo = Hd.solve(rho, None, None, tol=1e-10)
+        got, info = Hg.solve(rho, None, None, tol=1e-10)
+        assert info["cycles"] == rinfo["cycles"] and info["order_used"] == rinfo["order_used"]
+        assert info["history"] == rinfo["history"]
+        assert np.array_equal(host(got), host(ref))
+    Hd.close()
+    Hg.close()
 
 
 def test_solve_from_guess_and_residual_norm(mg):
