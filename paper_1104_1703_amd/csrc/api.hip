@@ -237,10 +237,16 @@ void create(mg_hierarchy *H, const int8_t *mask, int nx, int ny, int nz, double 
     H->part_cap = std::max(1, lev[0].od[2].ntiles * TZ);
     H->part = alloc_n<double>(H, (size_t)H->part_cap);
     H->norm_dev = alloc_n<double>(H, 8);
+    H->halt_dev = alloc_n<int>(H, 1);
+    HIPCHK(hipMemsetAsync(H->halt_dev, 0, sizeof(int), s));
+    H->stop_dev = alloc_n<StopTest>(H, 1);
+    HIPCHK(hipMemsetAsync(H->stop_dev, 0, sizeof(StopTest), s));
+    for (int l = 0; l < MAXL; l++) lev[l].halt = H->halt_dev;
     HIPCHK(hipMemsetAsync(H->norm_dev, 0, 8 * sizeof(double), s));
     HIPCHK(hipHostMalloc((void **)&H->norm_host, 8 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreate(&H->ev0));
     HIPCHK(hipEventCreate(&H->ev1));
+    for (int q = 0; q < 2; q++) HIPCHK(hipEventCreateWithFlags(&H->evq[q], hipEventDisableTiming));
     HIPCHK(hipStreamSynchronize(s));
     H->coarse_order_state = 0;
 }
@@ -332,8 +338,11 @@ void zero_level_x(mg_hierarchy *H, int l) {
 // One solve-loop cycle as a kernel sequence: FP64 MG(0) then the residual
 // norm of the new iterate, or (mixed) the FP32 inner MG(0) on L e = f - L x
 // from e = 0, x += e, and the FP64 residual norm that also writes the next
-// inner right-hand side.  Ends with an 8-byte copy of the norm to the host.
-void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out) {
+// inner right-hand side.  decide: the norm's final sum also runs the stop
+// test on the device and sets the halt flag that makes every kernel of a
+// following cycle return at once.
+void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out, bool decide) {
+    const StopTest *stop = decide ? H->stop_dev : nullptr;
     Cur cur;
     for (int l = 0; l < MAXL; l++) cur.c[l] = 0;
     Level &L0 = H->lev[0];
@@ -341,14 +350,13 @@ void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *pari
     if (!mixed) {
         cur.c[0] = parity;
         mg_level(H, 0, order, false, cur, false);
-        launch_resnorm(L0, 0, od0, L0.x[cur.c[0]], L0.f, H->part, H->norm_dev, 0, H->stream);
+        launch_resnorm(L0, 0, od0, L0.x[cur.c[0]], L0.f, H->part, H->norm_dev, 0, H->stream, stop);
     } else {
         mg_level(H, 0, order, true, cur, true);
         // x + e goes to the other FP64 buffer (unused by the FP32 inner cycle)
         launch_axpy_resnorm32(L0, od0, L0.x[parity], L0.x32[cur.c[0]], L0.x[parity ^ 1], L0.f, L0.f32, H->part,
-                              H->norm_dev, 0, H->stream);
+                              H->norm_dev, 0, H->stream, stop);
     }
-    HIPCHK(hipMemcpyAsync(H->norm_host, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
     *parity_out = mixed ? parity ^ 1 : cur.c[0];
 }
 
@@ -358,13 +366,13 @@ int cycle_parity_after(const mg_hierarchy *H, int order, int parity) {
     return parity ^ (passes & 1);
 }
 
-void run_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out) {
+void run_cycle_kernels(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out, bool decide) {
     if (!H->opt.use_graph) {
-        enqueue_cycle(H, order, parity, mixed, parity_out);
+        enqueue_cycle(H, order, parity, mixed, parity_out, decide);
         return;
     }
     for (auto &g : H->graphs)
-        if (g.order == order && g.parity == parity && g.mixed == mixed) {
+        if (g.order == order && g.parity == parity && g.mixed == mixed && g.decide == decide) {
             HIPCHK(hipGraphLaunch(g.exec, H->stream));
             *parity_out = mixed ? parity ^ 1 : cycle_parity_after(H, order, parity);
             return;
@@ -372,7 +380,7 @@ void run_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_o
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(H->stream, hipStreamCaptureModeThreadLocal));
     try {
-        enqueue_cycle(H, order, parity, mixed, parity_out);
+        enqueue_cycle(H, order, parity, mixed, parity_out, decide);
     } catch (...) {
         hipGraph_t tmp;
         (void)hipStreamEndCapture(H->stream, &tmp);
@@ -384,10 +392,18 @@ void run_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_o
     g.order = order;
     g.parity = parity;
     g.mixed = mixed;
+    g.decide = decide;
     HIPCHK(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
     (void)hipGraphDestroy(graph);
     H->graphs.push_back(g);
     HIPCHK(hipGraphLaunch(g.exec, H->stream));
+}
+
+// One cycle (replayed from its captured graph when use_graph), then an
+// 8-byte copy of its norm to norm_host[host_slot].
+void run_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out, bool decide, int host_slot) {
+    run_cycle_kernels(H, order, parity, mixed, parity_out, decide);
+    HIPCHK(hipMemcpyAsync(H->norm_host + host_slot, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
 }
 
 double read_norm(mg_hierarchy *H) {
@@ -422,6 +438,7 @@ void solve_begin(mg_hierarchy *H, const double *rho, double *phi, const double *
     hipStream_t s = H->stream;
     ensure_coarse_clean(H, S.order);
     HIPCHK(hipEventRecord(H->ev0, s));
+    launch_set_halt(H->halt_dev, 0, s);
     launch_fold(L0, od0, rho, B, phi, L0.f, L0.x[0], s);
     launch_resnorm(L0, 0, od0, nullptr, L0.f, H->part, H->norm_dev, 1, s);
     if (S.mixed) launch_resnorm32(L0, od0, L0.x[0], L0.f, L0.f32, H->part, H->norm_dev, 0, s);
@@ -454,7 +471,8 @@ void solve_start(mg_hierarchy *H, SolveState &S) {
 
 void solve_cycle_enqueue(mg_hierarchy *H, SolveState &S) {
     int np = S.parity;
-    run_cycle(H, S.order, S.parity, S.mixed, &np);
+    run_cycle(H, S.order, S.parity, S.mixed, &np, false, 0);
+    S.host_slot = 0;
     S.parity = np;
 }
 
@@ -463,7 +481,7 @@ void solve_cycle_finish(mg_hierarchy *H, SolveState &S) {
     const mg_options &o = H->opt;
     mg_solve_info *info = S.info;
     const int n = ++S.n;
-    const double rn = sqrt(H->norm_host[0]);
+    const double rn = sqrt(H->norm_host[S.host_slot]);
     info->cycles = n;
     info->r_final = rn;
     if (n < 257) info->history[n] = rn;
@@ -495,18 +513,62 @@ void solve_end(mg_hierarchy *H, SolveState &S) {
     S.info->status = S.st;
 }
 
+// The device copy of the stop test's inputs for the cycles to come.
+void set_device_stop(mg_hierarchy *H, const SolveState &S) {
+    const bool check = H->opt.bc_order == MG_BC_AUTO && S.order == 2;
+    launch_set_stop(H->stop_dev, S.tol * S.rref, S.rprev, H->opt.eta, check ? 1 : 0, H->stream);
+}
+
+// One solve with the next cycle always in flight: cycle n+1 is enqueued
+// before the host reads cycle n's norm.  Cycle n's norm also runs the stop
+// test on the device (the same FP64 comparisons as solve_cycle_finish); if it
+// stops or switches order, every kernel of cycle n+1 returns at once and the
+// host discards that cycle.  The host's decisions stay authoritative; the GPU
+// no longer idles while the host decides.
 mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol, mg_solve_info *info) {
     mg_solve_info tmp;
     if (!info) info = &tmp;
+    hipStream_t s = H->stream;
     SolveState S;
     solve_begin(H, rho, phi, B, tol, info, S);
-    HIPCHK(hipStreamSynchronize(H->stream));
+    HIPCHK(hipStreamSynchronize(s));
     solve_start(H, S);
+    if (S.active) set_device_stop(H, S);
+    struct Flight {
+        int parity_out, slot, ev;
+    } fl[2];
+    int nf = 0, enq = 0, par = S.parity;
+    auto launch = [&]() {
+        const int k = enq & 1;
+        int np = par;
+        run_cycle(H, S.order, par, S.mixed, &np, true, 4 + k);
+        HIPCHK(hipEventRecord(H->evq[k], s));
+        fl[nf++] = Flight{np, 4 + k, k};
+        par = np;
+        enq++;
+    };
     while (S.active) {
-        solve_cycle_enqueue(H, S);
-        HIPCHK(hipStreamSynchronize(H->stream));
+        if (nf == 0) launch();
+        if (nf == 1 && S.n + 2 <= H->opt.max_cycles) launch();  // speculative
+        HIPCHK(hipEventSynchronize(H->evq[fl[0].ev]));
+        const int order_before = S.order;
+        S.host_slot = fl[0].slot;
         solve_cycle_finish(H, S);
+        S.parity = fl[0].parity_out;
+        fl[0] = fl[1];
+        nf--;
+        if (!S.active || S.order != order_before) {
+            // the cycle in flight found the halt flag set and did nothing
+            if (nf) HIPCHK(hipEventSynchronize(H->evq[fl[0].ev]));
+            nf = 0;
+            par = S.parity;
+            if (S.active) {
+                launch_set_halt(H->halt_dev, 0, s);
+                set_device_stop(H, S);
+            }
+        }
     }
+    launch_set_halt(H->halt_dev, 0, s);  // other entry points run with the flag clear
     solve_end(H, S);
     HIPCHK(hipEventSynchronize(H->ev1));
     float ms = 0.f;
@@ -635,6 +697,8 @@ void mg_destroy_hierarchy(mg_hierarchy *H) {
     if (H->own_stream && H->stream) (void)hipStreamDestroy(H->stream);
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
+    for (int q = 0; q < 2; q++)
+        if (H->evq[q]) (void)hipEventDestroy(H->evq[q]);
     delete H;
 }
 

@@ -22,6 +22,7 @@ constexpr int NTC = 1024;  // 16 waves: four per SIMD to hide LDS and FP64 laten
 template <typename T>
 __global__ __launch_bounds__(NTC) void k_coarse(SmallLevels<T> S) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (S.halt && *S.halt) return;
     small_tail<T, NTC>(reinterpret_cast<T *>(smem_raw), S, S.f0, S.x0, S.load_x != 0);
 }
 
@@ -50,6 +51,7 @@ void launch_impl(const mg_hierarchy *H, int order, int ls, bool zero_start, cons
     S.f0 = f0;
     S.x0 = x0;
     S.load_x = zero_start ? 0 : 1;
+    S.halt = H->lev[0].halt;
     S.n_pre = H->opt.n_pre;
     S.n_post = H->opt.n_post;
     S.n_cycles = H->opt.n_cycles;

@@ -23,6 +23,7 @@ struct SmallLevels {
     const T *f0;           // right-hand side of level ls (global)
     T *x0;                 // iterate of level ls (global, in/out)
     int load_x;            // 1: start from x0, 0: start from zero
+    const int *halt;       // the solve loop's halt flag (nullable): the call does nothing when set
     int n_pre, n_post, n_cycles, n_coarse;
 };
 

@@ -28,6 +28,14 @@ constexpr int item_depth(int level) {
 }
 constexpr int item_planes(int level) { return item_depth(level) + 4; }
 
+// Stop test of the solve loop evaluated on the device by the norm's final
+// sum (the same FP64 comparisons as the host's): halt when sqrt(sum) <= thresh,
+// when it is not finite, or (check_switch) when sqrt(sum) / rprev > eta.
+struct StopTest {
+    double thresh, rprev, eta;
+    int check_switch, pad;
+};
+
 // Per boundary order data of one level (index 1 = first order, 2 = second).
 struct OrderData {
     double *d = nullptr;   // operator diagonal (coarse levels), 0 off the active set
@@ -47,6 +55,7 @@ struct Level {
     int32_t *cnt = nullptr;   // active finest descendants per cell
     uint8_t *code = nullptr;  // level 0: diagonal of the cell equation (6..12), CODE_OFF (0) if inactive
     OrderData od[3];
+    const int *halt = nullptr;          // the hierarchy's halt flag: cycle kernels exit when set
     double *x[2] = {nullptr, nullptr};  // ping-pong iterate
     double *f = nullptr;                // right-hand side
     float *x32[2] = {nullptr, nullptr};
@@ -56,7 +65,7 @@ struct Level {
 struct Graph {
     hipGraphExec_t exec = nullptr;
     int order = 0, parity = 0;
-    bool mixed = false;
+    bool mixed = false, decide = false;
 };
 
 }  // namespace mg
@@ -76,11 +85,14 @@ struct mg_hierarchy {
     int part_cap = 0;
     double *norm_dev = nullptr;     // finalised sums (device, 4 doubles)
     double *norm_host = nullptr;    // pinned mirror
+    int *halt_dev = nullptr;        // set by the device stop test; read by every cycle kernel
+    mg::StopTest *stop_dev = nullptr;
     double *scratch = nullptr;      // finest-level float64 scratch (fold/residual of the fine level)
     double *scratch2 = nullptr;
     std::vector<void *> allocs;
     std::vector<mg::Graph> graphs;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evq[2] = {nullptr, nullptr};  // ends of the (at most two) cycles in flight
 };
 
 namespace mg {
@@ -99,6 +111,7 @@ struct SolveState {
     double rprev = 0.0, rref = 0.0;
     mg_status st = MG_NOT_CONVERGED;
     bool active = false;  // another cycle is due
+    int host_slot = 0;    // norm_host entry holding the last finished cycle's norm
 };
 // begin: enqueue fold and the two reference norms; start: read them (the
 // caller has synchronised the hierarchy's stream); cycle_enqueue: one cycle
@@ -158,9 +171,13 @@ void launch_store(const Level &L, const OrderData &od, const double *x, double *
 void launch_copy_masked(const Level &L, int level, const OrderData &od, const double *src, double *dst,
                         hipStream_t s);
 // Sum of squares of (L x - f) (or of f alone when x == nullptr) into part[],
-// then a fixed-order total into out[slot].
+// then a fixed-order total into out[slot]; with `stop` the total also runs
+// the stop test and sets the level's halt flag.
 void launch_resnorm(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *part,
-                    double *out, int slot, hipStream_t s);
+                    double *out, int slot, hipStream_t s, const StopTest *stop = nullptr);
+// Device flags of the solve loop (small kernels, safe inside captured graphs).
+void launch_set_halt(int *halt, int v, hipStream_t s);
+void launch_set_stop(StopTest *st, double thresh, double rprev, double eta, int check_switch, hipStream_t s);
 void launch_residual(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *r,
                      hipStream_t s);
 void launch_restrict(const Level &L, const Level &C, int level, int order, const double *x, const double *f,
@@ -181,6 +198,7 @@ void launch_resnorm32(const Level &L, const OrderData &od, const double *x, cons
 // must differ from x), then the FP64 residual norm of xo and r32 = f - L xo
 // in float.
 void launch_axpy_resnorm32(const Level &L, const OrderData &od, const double *x, const float *e, double *xo,
-                           const double *f, float *r32, double *part, double *out, int slot, hipStream_t s);
+                           const double *f, float *r32, double *part, double *out, int slot, hipStream_t s,
+                           const StopTest *stop = nullptr);
 
 }  // namespace mg

@@ -36,11 +36,12 @@ __global__ __launch_bounds__(NT, 5) void k_rbgs(const T *__restrict__ xin, T *__
                                               const T *__restrict__ f, const uint8_t *__restrict__ code,
                                               const T *__restrict__ dco, int nx, int ny, int nz, T h2,
                                               const Seg *__restrict__ segs, const unsigned long long *__restrict__ pm,
-                                              int nsegs, const T *__restrict__ xc = nullptr, int cnx = 0,
-                                              int cny = 0, int cnz = 0) {
+                                              int nsegs, const int *__restrict__ halt,
+                                              const T *__restrict__ xc = nullptr, int cnx = 0, int cny = 0,
+                                              int cnz = 0) {
     __shared__ RbgsLds<T, FINE, PRO> lds;
     const int item = xcd_item(blockIdx.x, gridDim.x);
-    if (item >= nsegs) return;
+    if (item >= nsegs || (halt && *halt)) return;
     rbgs_item<T, FINE, SEGZ, PRO>(lds, xin, xout, f, code, dco, nx, ny, nz, h2, segs[item],
                                   pm + (size_t)item * (SEGZ + 4), xc, cnx, cny, cnz);
 }
@@ -56,10 +57,10 @@ void launch_coarse(int depth, const T *xin, T *xout, const T *f, const T *d, con
     const int cnx = C ? C->nx : 0, cny = C ? C->ny : 0, cnz = C ? C->nz : 0;
     if (depth == 8)
         k_rbgs<T, false, 8, PRO><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2,
-                                                               od.segs, od.pmask, od.nsegs, xc, cnx, cny, cnz);
+                                                               od.segs, od.pmask, od.nsegs, L.halt, xc, cnx, cny, cnz);
     else
         k_rbgs<T, false, 4, PRO><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2,
-                                                               od.segs, od.pmask, od.nsegs, xc, cnx, cny, cnz);
+                                                               od.segs, od.pmask, od.nsegs, L.halt, xc, cnx, cny, cnz);
 }
 static_assert((SEGZ_COARSE1 == 4 || SEGZ_COARSE1 == 8) && (SEGZ_COARSE == 4 || SEGZ_COARSE == 8),
               "coarse item depths have kernel instances for 4 and 8 planes");
@@ -70,7 +71,7 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
     const double h2 = L.h * L.h;
     if (level == 0)
         k_rbgs<double, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
-            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs);
+            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
     else
         launch_coarse<double>(item_depth(level), xin, xout, f, od.d, L, od, h2, s);
 }
@@ -81,7 +82,8 @@ void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const L
     const double h2 = L.h * L.h;
     if (level == 0)
         k_rbgs<double, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
-            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, xc, C.nx, C.ny, C.nz);
+            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx, C.ny,
+            C.nz);
     else
         launch_coarse<double, true>(item_depth(level), xin, xout, f, od.d, L, od, h2, s, xc, &C);
 }
@@ -92,7 +94,8 @@ void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const
     const float h2 = (float)(L.h * L.h);
     if (level == 0)
         k_rbgs<float, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
-            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, xc, C.nx, C.ny, C.nz);
+            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx, C.ny,
+            C.nz);
     else
         launch_coarse<float, true>(item_depth(level), xin, xout, f, od.d32, L, od, h2, s, xc, &C);
 }
@@ -103,7 +106,7 @@ void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *
     const float h2 = (float)(L.h * L.h);
     if (level == 0)
         k_rbgs<float, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
-            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs);
+            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
     else
         launch_coarse<float>(item_depth(level), xin, xout, f, od.d32, L, od, h2, s);
 }

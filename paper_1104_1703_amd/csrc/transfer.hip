@@ -13,11 +13,13 @@ inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
 inline unsigned gridt(int ntiles) { return grid8(ntiles * TZ); }  // one block per (tile, plane)
 inline unsigned gridc(int ntiles) { return grid8(ntiles * NQ); }  // one block per (tile, quarter)
 
-// Block work index w -> (tile, sub-block); false for grid padding.
-__device__ __forceinline__ bool block_tile(const int *tiles, int ntiles, int per, int &tile, int &sub, int &w) {
+// Block work index w -> (tile, sub-block); false for grid padding and when
+// the solve loop's halt flag is set.
+__device__ __forceinline__ bool block_tile(const int *tiles, int ntiles, int per, int &tile, int &sub, int &w,
+                                           const int *halt = nullptr) {
     w = xcd_item(blockIdx.x, gridDim.x);
     const int item = w / per;
-    if (item >= ntiles) return false;
+    if (item >= ntiles || (halt && *halt)) return false;
     tile = tiles[item];
     sub = w % per;
     return true;
@@ -71,8 +73,9 @@ __global__ __launch_bounds__(NT) void k_resnorm(const int *__restrict__ tiles, i
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ part, int n, double *__restrict__ out,
-                                                   int slot) {
+                                                   int slot, StopTest *__restrict__ stop, int *__restrict__ halt) {
     __shared__ double sm[1024];
+    if (halt && *halt) return;
     double v = 0.0;
     for (int q = threadIdx.x; q < n; q += 1024) v += part[q];
     sm[threadIdx.x] = v;
@@ -81,7 +84,25 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
         if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[slot] = sm[0];
+    if (threadIdx.x == 0) {
+        out[slot] = sm[0];
+        if (stop) {
+            const double r = sqrt(sm[0]);
+            const bool h = !(r > stop->thresh) || !isfinite(r) || (stop->check_switch && r / stop->rprev > stop->eta);
+            stop->rprev = r;
+            *halt = h ? 1 : 0;
+        }
+    }
+}
+
+__global__ void k_set_halt(int *__restrict__ halt, int v) { *halt = v; }
+
+__global__ void k_set_stop(StopTest *__restrict__ st, double thresh, double rprev, double eta, int check_switch) {
+    st->thresh = thresh;
+    st->rprev = rprev;
+    st->eta = eta;
+    st->check_switch = check_switch;
+    st->pad = 0;
 }
 
 template <bool FINE>
@@ -106,9 +127,10 @@ __global__ __launch_bounds__(NT) void k_restrict(const int *__restrict__ ctiles,
                                                  int cnx, int cny, int cnz, const T *__restrict__ cd, int nx, int ny,
                                                  int nz, T ih2, const uint8_t *__restrict__ code,
                                                  const T *__restrict__ dco, const T *__restrict__ x,
-                                                 const T *__restrict__ f, T *__restrict__ fc) {
+                                                 const T *__restrict__ f, T *__restrict__ fc,
+                                                 const int *__restrict__ halt) {
     int tile, kk, w;
-    if (!block_tile(ctiles, ntiles, TZ, tile, kk, w)) return;
+    if (!block_tile(ctiles, ntiles, TZ, tile, kk, w, halt)) return;
     restrict_cell<T, FINE>(tile_cell(tile, kk, cntx, cnty, cnx, cny, cnz), cnx, cny, cd, nx, ny, nz, ih2, code, dco,
                            x, f, fc);
 }
@@ -149,12 +171,12 @@ __global__ __launch_bounds__(NT) void k_residual_march(const T *__restrict__ x, 
                                                        const T *__restrict__ cd, int cnx, int cny,
                                                        T *__restrict__ fc, double *__restrict__ part,
                                                        float *__restrict__ r32, const float *__restrict__ ecor,
-                                                       T *__restrict__ xo) {
+                                                       T *__restrict__ xo, const int *__restrict__ halt) {
     using namespace rm;
     __shared__ T xs[XS][PN];
     __shared__ unsigned long long ms[SEGZ + 4];
     const int item = xcd_item(blockIdx.x, gridDim.x);
-    if (item >= nsegs) return;
+    if (item >= nsegs || (halt && *halt)) return;
     const Seg sg = segs[item];
     const int tid = threadIdx.x;
     if (tid < SEGZ + 4) ms[tid] = pm[(size_t)item * (SEGZ + 4) + tid];
@@ -288,12 +310,13 @@ template <typename T, int SEGZ>
 __global__ __launch_bounds__(NT) void k_prolong_march(const uint8_t *__restrict__ code, const T *__restrict__ xc,
                                                       int cnx, int cny, int cnz, T *__restrict__ x, int nx, int ny,
                                                       int nz, const Seg *__restrict__ segs,
-                                                      const unsigned long long *__restrict__ pm, int nsegs) {
+                                                      const unsigned long long *__restrict__ pm, int nsegs,
+                                                      const int *__restrict__ halt) {
     constexpr int CX = TX / 2 + 2, CY = TY / 2 + 2, CP = CX * CY;
     constexpr int NCZ = SEGZ / 2 + 2;
     __shared__ T cs[NCZ][CP];
     const int item = xcd_item(blockIdx.x, gridDim.x);
-    if (item >= nsegs) return;
+    if (item >= nsegs || (halt && *halt)) return;
     const Seg sg = segs[item];
     const int tid = threadIdx.x;
     const unsigned long long *im = pm + (size_t)item * (SEGZ + 4);
@@ -352,17 +375,17 @@ template <typename T, bool FINE>
 __global__ __launch_bounds__(NT) void k_prolong(const int *__restrict__ tiles, int ntiles, int ntx, int nty, int nx,
                                                 int ny, int nz, const uint8_t *__restrict__ code,
                                                 const T *__restrict__ dco, const T *__restrict__ xc, int cnx, int cny,
-                                                int cnz, T *__restrict__ x) {
+                                                int cnz, T *__restrict__ x, const int *__restrict__ halt) {
     int tile, q, w;
-    if (!block_tile(tiles, ntiles, NQ, tile, q, w)) return;
+    if (!block_tile(tiles, ntiles, NQ, tile, q, w, halt)) return;
     prolong_col<T, FINE>(tile_col(tile, q, ntx, nty, nx, ny), nx, ny, nz, code, dco, xc, cnx, cny, cnz, x);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_zero_tiles(const int *__restrict__ tiles, int ntiles, int ntx, int nty, int nx,
-                                                   int ny, int nz, T *__restrict__ x) {
+                                                   int ny, int nz, T *__restrict__ x, const int *__restrict__ halt) {
     int tile, kk, w;
-    if (!block_tile(tiles, ntiles, TZ, tile, kk, w)) return;
+    if (!block_tile(tiles, ntiles, TZ, tile, kk, w, halt)) return;
     const TileCoord t = tile_cell(tile, kk, ntx, nty, nx, ny, nz);
     if (t.ok) x[(size_t)t.k * nx * ny + (size_t)t.j * nx + t.i] = T(0);
 }
@@ -392,21 +415,31 @@ void launch_copy_masked(const Level &L, int level, const OrderData &od, const do
                                                              nullptr, od.d, src, dst);
 }
 
+// The halt flag is written only by a k_finalize that runs the stop test; the
+// other kernels of a cycle read it (a const view of the same flag).
+inline int *halt_rw(const Level &L) { return const_cast<int *>(L.halt); }
+
 void launch_resnorm(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *part,
-                    double *out, int slot, hipStream_t s) {
+                    double *out, int slot, hipStream_t s, const StopTest *stop) {
     const double ih2 = 1.0 / (L.h * L.h);
     if (level == 0) {
         if (od.nsegs)
             k_residual_march<double, SEG_TILES_FINE * TZ, RM_NORM><<<grid8(od.nsegs), NT, 0, s>>>(
                 x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part,
-                nullptr, nullptr, nullptr);
-        k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot);
+                nullptr, nullptr, nullptr, L.halt);
+        k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
         return;
     }
     if (od.ntiles)
         k_resnorm<false, true, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny,
                                                                       L.nz, ih2, nullptr, od.d, x, f, part, nullptr);
-    k_finalize<<<1, 1024, 0, s>>>(part, od.ntiles * NQ, out, slot);
+    k_finalize<<<1, 1024, 0, s>>>(part, od.ntiles * NQ, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
+}
+
+void launch_set_halt(int *halt, int v, hipStream_t s) { k_set_halt<<<1, 1, 0, s>>>(halt, v); }
+
+void launch_set_stop(StopTest *st, double thresh, double rprev, double eta, int check_switch, hipStream_t s) {
+    k_set_stop<<<1, 1, 0, s>>>(st, thresh, rprev, eta, check_switch);
 }
 
 void launch_resnorm32(const Level &L, const OrderData &od, const double *x, const double *f, float *r32, double *part,
@@ -415,18 +448,19 @@ void launch_resnorm32(const Level &L, const OrderData &od, const double *x, cons
     if (od.nsegs)
         k_residual_march<double, SEG_TILES_FINE * TZ, RM_NORM32><<<grid8(od.nsegs), NT, 0, s>>>(
             x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32,
-            nullptr, nullptr);
-    k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot);
+            nullptr, nullptr, L.halt);
+    k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, nullptr, halt_rw(L));
 }
 
 void launch_axpy_resnorm32(const Level &L, const OrderData &od, const double *x, const float *e, double *xo,
-                           const double *f, float *r32, double *part, double *out, int slot, hipStream_t s) {
+                           const double *f, float *r32, double *part, double *out, int slot, hipStream_t s,
+                           const StopTest *stop) {
     const double ih2 = 1.0 / (L.h * L.h);
     if (od.nsegs)
         k_residual_march<double, SEG_TILES_FINE * TZ, RM_AXPY32><<<grid8(od.nsegs), NT, 0, s>>>(
             x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32, e,
-            xo);
-    k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot);
+            xo, L.halt);
+    k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
 }
 
 void launch_residual(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *r,
@@ -451,11 +485,11 @@ void launch_restrict(const Level &L, const Level &C, int level, int order, const
         if (fo.nsegs)
             k_residual_march<double, SEG_TILES_FINE * TZ, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
                 x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d, C.nx, C.ny, fc, nullptr,
-                nullptr, nullptr, nullptr);
+                nullptr, nullptr, nullptr, L.halt);
     } else
         k_restrict<double, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny,
                                                                   C.nz, co.d, L.nx, L.ny, L.nz, ih2, nullptr,
-                                                                  L.od[order].d, x, f, fc);
+                                                                  L.od[order].d, x, f, fc, L.halt);
 }
 
 void launch_restrict32(const Level &L, const Level &C, int level, int order, const float *x, const float *f,
@@ -468,11 +502,11 @@ void launch_restrict32(const Level &L, const Level &C, int level, int order, con
         if (fo.nsegs)
             k_residual_march<float, SEG_TILES_FINE * TZ, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
                 x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d32, C.nx, C.ny, fc, nullptr,
-                nullptr, nullptr, nullptr);
+                nullptr, nullptr, nullptr, L.halt);
     } else
         k_restrict<float, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny, C.nz,
                                                                  co.d32, L.nx, L.ny, L.nz, ih2, nullptr,
-                                                                 L.od[order].d32, x, f, fc);
+                                                                 L.od[order].d32, x, f, fc, L.halt);
 }
 
 void launch_prolong(const Level &L, const Level &C, int level, int order, const double *xc, double *x,
@@ -482,10 +516,10 @@ void launch_prolong(const Level &L, const Level &C, int level, int order, const 
     if (level == 0) {
         if (od.nsegs)
             k_prolong_march<double, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
-                L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs);
+                L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs, L.halt);
     } else
         k_prolong<double, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
-                                                                 nullptr, od.d, xc, C.nx, C.ny, C.nz, x);
+                                                                 nullptr, od.d, xc, C.nx, C.ny, C.nz, x, L.halt);
 }
 
 void launch_prolong32(const Level &L, const Level &C, int level, int order, const float *xc, float *x,
@@ -495,20 +529,22 @@ void launch_prolong32(const Level &L, const Level &C, int level, int order, cons
     if (level == 0) {
         if (od.nsegs)
             k_prolong_march<float, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
-                L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs);
+                L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs, L.halt);
     } else
         k_prolong<float, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
-                                                                nullptr, od.d32, xc, C.nx, C.ny, C.nz, x);
+                                                                nullptr, od.d32, xc, C.nx, C.ny, C.nz, x, L.halt);
 }
 
 void launch_zero_tiles(const Level &L, const OrderData &od, double *x, hipStream_t s) {
     if (!od.ntiles) return;
-    k_zero_tiles<double><<<gridt(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz, x);
+    k_zero_tiles<double><<<gridt(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz, x,
+                                                         L.halt);
 }
 
 void launch_zero_tiles32(const Level &L, const OrderData &od, float *x, hipStream_t s) {
     if (!od.ntiles) return;
-    k_zero_tiles<float><<<gridt(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz, x);
+    k_zero_tiles<float><<<gridt(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz, x,
+                                                        L.halt);
 }
 
 }  // namespace mg

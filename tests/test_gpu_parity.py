@@ -217,6 +217,24 @@ def test_graph_replays_match_direct_launches(mg):
     Hg.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_entry_points_after_a_solve(mg, precision):
+    """A solve keeps one cycle in flight and lets the device stop it; the
+    flag that does so must be clear afterwards: the residual norm of the
+    returned solution equals the solve's final norm, and a second solve from
+    that solution stops at once."""
+    p = gen.holes_problem(64, 2)
+    H = mg.Hierarchy(dev(p.mask), p.h, precision=precision)
+    phi, info = H.solve(dev(p.rho), None, None, tol=1e-9)
+    assert info["status"] == 0
+    rn = H.residual_norm(dev(p.rho), phi, None)
+    assert abs(rn - info["r_final"]) <= 1e-12 * info["r_final"]
+    phi2, info2 = H.solve(dev(p.rho), phi.clone(), None, tol=1e-9)
+    assert info2["status"] == 0 and info2["cycles"] == 0
+    assert np.array_equal(host(phi2)[p.mask == 1], host(phi)[p.mask == 1])
+    H.close()
+
+
 def test_solve_from_guess_and_residual_norm(mg):
     p = gen.random_small_problem((32, 32, 32), 8, active_frac=0.8, blur=1.0)
     H = mg.Hierarchy(dev(p.mask), p.h)
