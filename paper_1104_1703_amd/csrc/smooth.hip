@@ -58,12 +58,16 @@ void launch_coarse(int depth, const T *xin, T *xout, const T *f, const T *d, con
     if (depth == 8)
         k_rbgs<T, false, 8, PRO><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2,
                                                                od.segs, od.pmask, od.nsegs, L.halt, xc, cnx, cny, cnz);
+    else if (depth == 2)
+        k_rbgs<T, false, 2, PRO><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2,
+                                                               od.segs, od.pmask, od.nsegs, L.halt, xc, cnx, cny, cnz);
     else
         k_rbgs<T, false, 4, PRO><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2,
                                                                od.segs, od.pmask, od.nsegs, L.halt, xc, cnx, cny, cnz);
 }
-static_assert((SEGZ_COARSE1 == 4 || SEGZ_COARSE1 == 8) && (SEGZ_COARSE == 4 || SEGZ_COARSE == 8),
-              "coarse item depths have kernel instances for 4 and 8 planes");
+static_assert((SEGZ_COARSE1 == 2 || SEGZ_COARSE1 == 4 || SEGZ_COARSE1 == 8) &&
+                  (SEGZ_COARSE == 2 || SEGZ_COARSE == 4 || SEGZ_COARSE == 8),
+              "coarse item depths have kernel instances for 2, 4 and 8 planes");
 
 void launch_rbgs(const Level &L, int level, const OrderData &od, const double *xin, double *xout, const double *f,
                  hipStream_t s) {

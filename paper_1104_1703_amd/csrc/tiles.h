@@ -12,7 +12,7 @@ constexpr int TY = 8;
 constexpr int TZ = 8;
 constexpr int SEG_TILES_FINE = 2;    // z-tiles per smoother work item on the finest level
 constexpr int SEGZ_COARSE1 = 4;      // planes per smoother work item on level 1
-constexpr int SEGZ_COARSE = 4;       // planes per smoother work item on coarser levels (more items)
+constexpr int SEGZ_COARSE = 2;       // planes per smoother work item on coarser levels (latency-bound: short marches)
 // Finest-level cell code: the diagonal of the cell's equation, 12 - (number
 // of active face neighbours) = 6..12 for an active cell, CODE_OFF if inactive.
 constexpr uint8_t CODE_OFF = 0;
