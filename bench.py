@@ -187,6 +187,9 @@ def batch_measurement(args):
     B = mg.Batch(masks, [p.h for p in probs])
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
+    B_phases = B.phases(2)
+    if B_phases == 0:
+        raise RuntimeError("the batch has no phase programs for the default options")
     walls, infos = [], None
     for rep in range(4):
         for x in phis:
@@ -203,8 +206,8 @@ def batch_measurement(args):
     cycles = [i["cycles"] for i in infos]
     return {"workload": f"{len(probs)} masked patches (seed 3), {sum(p.mask.size for p in probs)} cells, "
                         f"{active} active, Dirichlet data, tol 1e-10",
-            "engine": "lockstep: one graph-captured cycle per unconverged patch per round on 4 streams, "
-                      "one synchronisation per round",
+            "engine": f"phase programs: one launch per cycle phase over all patches' work items "
+                      f"({B_phases} launches per cycle), one norm copy and synchronisation per cycle",
             "ms": round(ms, 3), "active_cells_per_s": round(active / (ms * 1e-3), 1),
             "cycles_min": min(cycles), "cycles_max": max(cycles), "cycles_total": int(sum(cycles)),
             "all_converged": all(i["status"] == 0 for i in infos),

@@ -198,10 +198,17 @@ void *mg_stream(const mg_hierarchy *H);
 
 /* ---------------- batched solver ---------------- */
 /* Many independent masked grids (AMR-level patches of uneven size and depth)
- * solved together: each patch has its own hierarchy and operators exactly as
- * in mg_solve (Sec. 2-4).  The persistent one-launch-per-cycle engine is
- * switched off in this build (see the library sources); each patch then runs
- * its own graph-captured cycles on the batch stream. */
+ * solved together: each patch has its own hierarchy, operators, order switch
+ * (Sec. 4) and stop test exactly as in mg_solve (Sec. 2-4), and gets bit for
+ * bit the result mg_solve gives it.  One multigrid cycle of all unconverged
+ * patches runs as one program of launches on the batch stream, each launch
+ * one phase of the cycle (a red-black pass on level l, a restriction, the
+ * small levels, the norm) over the work items of every patch that reaches
+ * it; the host reads all patch norms once per cycle.  Options the programs
+ * do not cover (odd finest-level pass counts per cycle, n_post == 0, a
+ * zero-pass relaxation from zero) run each patch's own captured cycle in
+ * lockstep instead.  use_graph = 1 replays each program from a captured
+ * graph.  Calls on one batch must not overlap. */
 typedef struct mg_batch mg_batch; /* opaque */
 
 /*
@@ -230,12 +237,17 @@ mg_status mg_solve_batch(mg_batch *B, const double *const *rho_dev, double *cons
 /* Release the batch and every patch hierarchy (NULL is a no-op). */
 void mg_destroy_batch(mg_batch *B);
 
-/* Number of patches; blocks of the persistent launch and phases of one
- * cycle program of boundary order `order` (1 or 2), both 0 while the
- * persistent engine is off. */
+/* Number of patches; work items of the largest launch of the cycle programs,
+ * and launches of the cycle program of boundary order `order` (1 or 2), both
+ * 0 when the batch runs on the per-patch lockstep engine only. */
 int32_t mg_batch_size(const mg_batch *B);
 int32_t mg_batch_grid(const mg_batch *B);
 int32_t mg_batch_phases(const mg_batch *B, int32_t order);
+
+/* Select the engine of later solves: phased != 0 the phase programs (the
+ * default where they exist; MG_ERR_ARG if they do not), 0 the per-patch
+ * lockstep cycles.  Both give the same results. */
+mg_status mg_batch_set_engine(mg_batch *B, int32_t phased);
 
 /* ---------------- learned first guess (U-Net) ----------------
  * The iteration of Sec. 2 converges from any first guess, and the paper's

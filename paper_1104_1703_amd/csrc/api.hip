@@ -415,8 +415,9 @@ double read_norm(mg_hierarchy *H) {
 // advance together with one host synchronisation per cycle (batch.hip):
 // begin (fold, two reference norms) | start (after a sync) | cycle enqueue |
 // cycle finish (after a sync) | end (store).
-void solve_begin(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol, mg_solve_info *info,
-                 SolveState &S) {
+// Host part of begin: the solve state, the boundary order of this solve and
+// the coarse buffers cleaned for it.
+void solve_init(mg_hierarchy *H, double *phi, double tol, mg_solve_info *info, SolveState &S) {
     const mg_options &o = H->opt;
     memset(info, 0, sizeof(*info));
     info->switched_at_cycle = -1;
@@ -433,10 +434,15 @@ void solve_begin(mg_hierarchy *H, const double *rho, double *phi, const double *
         S.order = 2;
     }
     S.mixed = o.precision == MG_MIXED;
+    ensure_coarse_clean(H, S.order);
+}
+
+void solve_begin(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol, mg_solve_info *info,
+                 SolveState &S) {
+    solve_init(H, phi, tol, info, S);
     Level &L0 = H->lev[0];
     const OrderData &od0 = odata(H, 0, S.order);
     hipStream_t s = H->stream;
-    ensure_coarse_clean(H, S.order);
     HIPCHK(hipEventRecord(H->ev0, s));
     launch_set_halt(H->halt_dev, 0, s);
     launch_fold(L0, od0, rho, B, phi, L0.f, L0.x[0], s);
@@ -615,6 +621,13 @@ mg_status phase_begin(mg_hierarchy *H, const double *rho, double *phi, const dou
                       mg_solve_info *info, SolveState &S) {
     return guarded([&]() {
         solve_begin(H, rho, phi, B, tol, info, S);
+        return MG_OK;
+    });
+}
+
+mg_status phase_init(mg_hierarchy *H, double *phi, double tol, mg_solve_info *info, SolveState &S) {
+    return guarded([&]() {
+        solve_init(H, phi, tol, info, S);
         return MG_OK;
     });
 }

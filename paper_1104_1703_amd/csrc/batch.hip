@@ -1,237 +1,210 @@
 // Batched solver: many independent masked grids (AMR-level patches of uneven
-// size and depth) advanced together, one persistent launch per multigrid
-// cycle for the whole batch.
+// size and depth) solved together.
 //
-// Each patch has its own hierarchy (same construction and operators as a
-// single solve).  The cycle of Sec. 2 for every patch is flattened on the host
-// into a fixed program of phases; a phase is a list of work items of one kind
-// (a red-black pass over a 32 x 8 x 8 tile of one patch level, a restriction
-// or prolongation over a tile, the small-level call MG(ls) of one patch in one
-// workgroup, norm partials over a tile, ...).  One cooperative launch runs the
-// phases in order, the blocks taking items of a phase round-robin, with a grid
-// barrier between phases.  Patches whose multigrid calls reach a given level
-// share that level's phases, so patches of different depths interleave.  The
-// barrier spins for a bounded time and reports an error instead of hanging.
+// Every patch has its own hierarchy, operators, boundary-order switch and
+// stop test, exactly as a single solve (Sec. 2-4).  One multigrid cycle of
+// all unconverged patches runs as a short program of launches, each launch
+// one phase of the cycle for every patch that reaches it: a red-black pass
+// over the smoother items of level l, the residual with R1 restriction, the
+// small levels (one 1024-thread workgroup per patch), the residual-norm
+// partials and their per-patch fixed-order sums.  A block takes one work
+// item, which names a patch level (a descriptor in device memory) and an
+// item of that level's own lists, and runs the single-grid kernels' device
+// code on it.  So each patch gets bit for bit what a single solve gives it,
+// while one cycle of hundreds of patches costs as many launches as one cycle
+// of one grid.  A state word per patch gates every item: the program of each
+// boundary order serves the patches now in that order; converged patches
+// skip.  The host reads all per-patch norms once per cycle and takes each
+// patch's decisions with the single-grid solve loop's own code.
+//
+// The programs keep the finest iterate in buffer 0 between cycles.  Options
+// they do not cover (an odd number of finest-level passes per cycle, no
+// post-smoothing, a zero-pass relaxation from a zero start) run each patch's
+// own captured cycles in lockstep instead: one round enqueues one cycle per
+// unconverged patch and synchronises once.
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <new>
 
 #include "coarse_core.h"
-#include "smooth_core.h"
-#include "transfer_core.h"
+#include "march_core.h"
 
 namespace mg {
 namespace {
 
-// The persistent cooperative kernel below is switched off: its first GPU runs
-// ended in HSA_STATUS_ERROR_MEMORY_APERTURE_VIOLATION (a generic-address
-// access out of every aperture) and the faulting access has not been found.
-// With it off, mg_solve_batch advances all patches in lockstep: each round
-// enqueues one graph-captured cycle (the single-grid path, same kernels and
-// results) of every unconverged patch, spread over a few streams, and then
-// synchronises once for all of them.
-constexpr bool kPersistentEnabled = false;
-constexpr int kPatchStreams = 4;  // hardware queues of one process
-constexpr int BNT = 256;
-constexpr int BSEGZ = TZ;  // batch smoother items are one tile deep
-constexpr unsigned long long BARRIER_SPIN_LIMIT = 1ull << 24;
+constexpr int FINE_Z = SEG_TILES_FINE * TZ;  // planes of a finest-level smoother item
+constexpr int NTS = 1024;                     // threads of the small-level workgroup (as coarse.hip)
+constexpr int WBITS = 24;                     // BRef::w: item index in the low bits, selector above
+constexpr int IDX_MASK = (1 << WBITS) - 1;
 
-enum : int {
-    PH_SMOOTH0 = 0,   // red-black pass, finest level
-    PH_SMOOTH = 1,    // red-black pass, coarse level
-    PH_RESTRICT0 = 2, // residual + R1 from the finest level
-    PH_RESTRICT = 3,  // residual + R1 from a coarse level
-    PH_PROLONG0 = 4,  // P2 + correction onto the finest level
-    PH_PROLONG = 5,   // P2 + correction onto a coarse level
-    PH_SMALL = 6,     // MG(ls) of one patch in one workgroup
-    PH_NORM = 7,      // residual-norm partials over a finest tile (flags: 1 = with x)
-    PH_NORMSUM = 8,   // per-patch fixed-order sum of its partials into norm2[slot]
-    PH_FOLD = 9,      // Dirichlet fold and guess load over a finest tile
-    PH_STORE = 10,    // copy the finest iterate back to the caller's phi
-};
-
-// Level descriptor of one patch (device copy).
-struct PLev {
+// One level of one patch as the phases see it; one table per boundary order,
+// entry patch * MAXL + level.
+struct BLev {
     int nx, ny, nz, ntx, nty;
+    int cnx, cny, cnz, cntx, cnty;  // next coarser level (0 if none)
     double h2, ih2;
     double *x[2];
     double *f;
-    const uint8_t *code;    // finest level only
-    const double *d[3];     // coarse diagonals, index = order
+    const uint8_t *code;                 // level 0 (else null)
+    const double *d;                     // coarse levels: diagonal of this order (else null)
+    const Seg *segs;                     // smoother items of this level and order
+    const unsigned long long *pm;        // their activity masks
+    const int *tiles;                    // active tiles
+    double *cx[2];                       // next coarser level: iterate,
+    double *cf;                          //   right-hand side,
+    const double *cd;                    //   diagonal of this order,
+    const int *ctiles;                   //   active tiles of this order
 };
 
-struct BItem {
-    int patch;
-    int level;
-    int tile;               // tile id, or first partial index (NORMSUM)
-    int sel;                // bit 0: input iterate buffer; bit 1: start from zero;
-                            // bit 2: coarse buffer (PROLONG); NORMSUM: partial count
-    Seg seg;                // smoother work item
+// Work item: descriptor index and (item index | selector << WBITS).  Selector
+// bits: 1 = iterate buffer read, 2 = start from zero (no read), 4 = coarse
+// iterate buffer of a prolongation pass.
+struct BRef {
+    int lev, w;
 };
 
-struct Phase {
-    int type, first, count, flags;
+enum : int {
+    K_SM0,    // red-black pass, finest level
+    K_SM0P,   //   ... applying P2 from level 1 on load
+    K_SM1,    // red-black pass, level 1
+    K_SM1P,
+    K_SM2,    // red-black pass, levels 2 and coarser
+    K_SM2P,
+    K_RES0,   // residual march of the finest level with R1 onto level 1
+    K_RESC,   // residual and R1 from a coarse level, one coarse (tile, plane) per item
+    K_SMALL,  // MG(ls) of one patch in one workgroup
+    K_NORM,   // residual-norm partials of the finest level
+    K_FIN,    // per-patch fixed-order sum of the partials
+    K_FOLD,   // Dirichlet fold and guess load of the finest level
+    K_STORE,  // finest iterate back to phi
 };
 
-struct BatchArgs {
-    const Phase *ph;
-    int nph;
-    int npatch;
-    const BItem *items;
-    const PLev *lev;                       // [npatch * MAXL]
-    const small::SmallLevels<double> *sl;  // [npatch]: small levels of this program's order
-    double *const *small_scratch;          // [npatch]: global scratch when the small levels exceed LDS
-    double *part;                          // norm partials, one per NORM item
-    double *norm2;                         // [npatch * 2]
-    const int *state;                      // [npatch]: 0 = skip, else the boundary order in use
-    int order;                             // order this program serves
-    const double *const *rho;              // [npatch] inputs of the solve
-    const double *const *dir;
-    double *const *phi;
-    unsigned *bar;                         // [2]: arrival count, generation
-    int *err;
-    int n_pre, n_post, n_cycles, n_coarse;
-};
-
-union BatchLds {
-    rb::RbgsLds<double, true> fine;
-    rb::RbgsLds<double, false> coarse;
-    double small_levels[sizeof(rb::RbgsLds<double, false>) / sizeof(double)];
-};
-
-// Grid-wide barrier for a co-resident (cooperative) launch.  Device-scope
-// fences make each phase's writes visible to every XCD before the next phase.
-// The wait is bounded: on timeout it raises err and lets the block go on, so
-// every wave always reaches the end of the kernel.
-__device__ void grid_barrier(unsigned *bar, int *err) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = atomicAdd(&bar[0], 1u) + 1u;
-        if (arrived == gridDim.x) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned long long spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > BARRIER_SPIN_LIMIT) {
-                    atomicExch(err, 1);
-                    break;
-                }
-            }
-        }
-        __threadfence();
-    }
-    __syncthreads();
+// Block -> work item; false for grid padding and for patches this program
+// does not serve.
+__device__ __forceinline__ bool take(const BRef *__restrict__ refs, int count, const int *__restrict__ state,
+                                     int order, BRef &r) {
+    const int w = rb::xcd_item(blockIdx.x, gridDim.x);
+    if (w >= count) return false;
+    r = refs[w];
+    return state[r.lev / MAXL] == order;
 }
 
-__global__ __launch_bounds__(BNT) void k_batch(BatchArgs A) {
-    __shared__ BatchLds lds;
-    for (int ph = 0; ph < A.nph; ph++) {
-        const Phase P = A.ph[ph];
-        for (int it = blockIdx.x; it < P.count; it += gridDim.x) {
-            const BItem w = A.items[P.first + it];
-            if (w.patch < 0 || w.patch >= A.npatch || w.level < 0 || w.level >= MAXL - 1) continue;
-            if (A.state[w.patch] != A.order) continue;  // converged or served by the other order's program
-            const PLev &L = A.lev[w.patch * MAXL + w.level];
-            switch (P.type) {
-                case PH_SMOOTH0:
-                case PH_SMOOTH: {
-                    const int a = w.sel & 1;
-                    const double *xin = (w.sel & 2) ? nullptr : L.x[a];
-                    if (P.type == PH_SMOOTH0)
-                        rb::rbgs_item<double, true, BSEGZ>(lds.fine, xin, L.x[a ^ 1], L.f, L.code, nullptr, L.nx,
-                                                           L.ny, L.nz, L.h2, w.seg, nullptr);
-                    else
-                        rb::rbgs_item<double, false, BSEGZ>(lds.coarse, xin, L.x[a ^ 1], L.f, nullptr,
-                                                            L.d[A.order], L.nx, L.ny, L.nz, L.h2, w.seg, nullptr);
-                    __syncthreads();
-                    break;
-                }
-                case PH_RESTRICT0:
-                case PH_RESTRICT: {
-                    const PLev &C = A.lev[w.patch * MAXL + w.level + 1];
-                    const double *x = L.x[w.sel & 1];
-                    for (int kk = 0; kk < TZ; kk++) {
-                        const tr::TileCoord t = tr::tile_cell(w.tile, kk, C.ntx, C.nty, C.nx, C.ny, C.nz);
-                        if (P.type == PH_RESTRICT0)
-                            tr::restrict_cell<double, true>(t, C.nx, C.ny, C.d[A.order], L.nx, L.ny, L.nz, L.ih2,
-                                                            L.code, nullptr, x, L.f, C.f);
-                        else
-                            tr::restrict_cell<double, false>(t, C.nx, C.ny, C.d[A.order], L.nx, L.ny, L.nz, L.ih2,
-                                                             nullptr, L.d[A.order], x, L.f, C.f);
-                    }
-                    break;
-                }
-                case PH_PROLONG0:
-                case PH_PROLONG: {
-                    const PLev &C = A.lev[w.patch * MAXL + w.level + 1];
-                    double *x = L.x[w.sel & 1];
-                    const double *xc = C.x[(w.sel >> 2) & 1];
-                    for (int q = 0; q < tr::NQ; q++) {
-                        const tr::Col c = tr::tile_col(w.tile, q, L.ntx, L.nty, L.nx, L.ny);
-                        if (P.type == PH_PROLONG0)
-                            tr::prolong_col<double, true>(c, L.nx, L.ny, L.nz, L.code, nullptr, xc, C.nx, C.ny, C.nz,
-                                                          x);
-                        else
-                            tr::prolong_col<double, false>(c, L.nx, L.ny, L.nz, nullptr, L.d[A.order], xc, C.nx,
-                                                           C.ny, C.nz, x);
-                    }
-                    break;
-                }
-                case PH_SMALL: {
-                    double *scratch = A.small_scratch[w.patch];
-                    double *sm = scratch ? scratch : lds.small_levels;
-                    small::small_tail<double>(sm, A.sl[w.patch], L.f, L.x[w.sel & 1], (w.sel & 2) == 0);
-                    break;
-                }
-                case PH_NORM: {
-                    double acc = 0.0;
-                    for (int q = 0; q < tr::NQ; q++) {
-                        const tr::Col c = tr::tile_col(w.tile, q, L.ntx, L.nty, L.nx, L.ny);
-                        if (P.flags & 1)
-                            acc += tr::resnorm_col<true, true, false>(c, L.nx, L.ny, L.nz, L.ih2, L.code, nullptr,
-                                                                      L.x[w.sel & 1], L.f, nullptr);
-                        else
-                            acc += tr::resnorm_col<true, false, false>(c, L.nx, L.ny, L.nz, L.ih2, L.code, nullptr,
-                                                                       nullptr, L.f, nullptr);
-                    }
-                    const double s = tr::block_sum(acc);
-                    if (threadIdx.x == 0) A.part[P.first + it] = s;
-                    break;
-                }
-                case PH_NORMSUM: {
-                    // partials of this patch: part[w.tile .. w.tile + w.sel), summed in order
-                    if (threadIdx.x == 0) {
-                        double s = 0.0;
-                        for (int q = 0; q < w.sel; q++) s += A.part[w.tile + q];
-                        A.norm2[w.patch * 2 + (P.flags & 1)] = s;
-                    }
-                    break;
-                }
-                case PH_FOLD: {
-                    for (int kk = 0; kk < TZ; kk++)
-                        tr::fold_cell(tr::tile_cell(w.tile, kk, L.ntx, L.nty, L.nx, L.ny, L.nz), L.nx, L.ny, L.ih2,
-                                      L.code, A.rho[w.patch], A.dir[w.patch], A.phi[w.patch], L.f, L.x[0]);
-                    break;
-                }
-                case PH_STORE: {
-                    for (int kk = 0; kk < TZ; kk++)
-                        tr::store_cell(tr::tile_cell(w.tile, kk, L.ntx, L.nty, L.nx, L.ny, L.nz), L.nx, L.ny, L.code,
-                                       L.x[w.sel & 1], A.phi[w.patch]);
-                    break;
-                }
-                default:
-                    break;
-            }
-        }
-        if (ph + 1 < A.nph) grid_barrier(A.bar, A.err);
+template <bool FINE, int SEGZ, bool PRO>
+__global__ __launch_bounds__(rb::NT, 5) void kb_smooth(const BRef *__restrict__ refs, int count,
+                                                       const BLev *__restrict__ lev, const int *__restrict__ state,
+                                                       int order) {
+    __shared__ rb::RbgsLds<double, FINE, PRO> lds;
+    BRef r;
+    if (!take(refs, count, state, order, r)) return;
+    const BLev &L = lev[r.lev];
+    const int idx = r.w & IDX_MASK, sel = r.w >> WBITS, a = sel & 1;
+    rb::rbgs_item<double, FINE, SEGZ, PRO>(lds, (sel & 2) ? nullptr : L.x[a], L.x[a ^ 1], L.f, L.code, L.d, L.nx,
+                                           L.ny, L.nz, L.h2, L.segs[idx], L.pm + (size_t)idx * (SEGZ + 4),
+                                           PRO ? L.cx[(sel >> 2) & 1] : nullptr, L.cnx, L.cny, L.cnz);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(tr::NT) void kb_residual(const BRef *__restrict__ refs, int count,
+                                                      const BLev *__restrict__ lev, const int *__restrict__ state,
+                                                      int order, double *__restrict__ part) {
+    __shared__ tr::ResLds<double> lds;
+    BRef r;
+    if (!take(refs, count, state, order, r)) return;
+    const BLev &L = lev[r.lev];
+    const int idx = r.w & IDX_MASK, sel = r.w >> WBITS;
+    constexpr bool RS = MODE == tr::RM_RESTRICT;
+    const double sq = tr::residual_item<double, FINE_Z, MODE>(
+        lds, (sel & 2) ? nullptr : L.x[sel & 1], L.f, L.code, L.nx, L.ny, L.nz, L.ih2, L.segs[idx],
+        L.pm + (size_t)idx * (FINE_Z + 4), RS ? L.cd : nullptr, RS ? L.cnx : 0, RS ? L.cny : 0,
+        RS ? L.cf : nullptr, nullptr, nullptr, nullptr);
+    if constexpr (!RS) {
+        const double t = tr::block_sum(sq);
+        if (threadIdx.x == 0) part[rb::xcd_item(blockIdx.x, gridDim.x)] = t;
     }
 }
+
+__global__ __launch_bounds__(tr::NT) void kb_restrict(const BRef *__restrict__ refs, int count,
+                                                      const BLev *__restrict__ lev, const int *__restrict__ state,
+                                                      int order) {
+    BRef r;
+    if (!take(refs, count, state, order, r)) return;
+    const BLev &L = lev[r.lev];
+    const int idx = r.w & IDX_MASK, sel = r.w >> WBITS;
+    const tr::TileCoord t = tr::tile_cell(L.ctiles[idx / TZ], idx % TZ, L.cntx, L.cnty, L.cnx, L.cny, L.cnz);
+    tr::restrict_cell<double, false>(t, L.cnx, L.cny, L.cd, L.nx, L.ny, L.nz, L.ih2, nullptr, L.d, L.x[sel & 1], L.f,
+                                     L.cf);
+}
+
+__global__ __launch_bounds__(NTS) void kb_small(const BRef *__restrict__ refs, int count,
+                                                const BLev *__restrict__ lev, const int *__restrict__ state,
+                                                int order, const small::SmallLevels<double> *__restrict__ sl) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    if ((int)blockIdx.x >= count) return;
+    const BRef r = refs[blockIdx.x];
+    const int p = r.lev / MAXL;
+    if (state[p] != order) return;
+    const BLev &L = lev[r.lev];
+    const int sel = r.w >> WBITS;
+    small::small_tail<double, NTS>(reinterpret_cast<double *>(smem_raw), sl[p], L.f, L.x[sel & 1], (sel & 2) == 0);
+}
+
+// Per patch p: the sum of part[first[p] .. first[p] + cnt[p]) in the same
+// order as the single-grid norm's final sum, into out[2 p + slot].
+__global__ __launch_bounds__(1024) void kb_finalize(const int *__restrict__ first, const int *__restrict__ cnt,
+                                                    int npatch, const double *__restrict__ part,
+                                                    double *__restrict__ out, int slot, const int *__restrict__ state,
+                                                    int order) {
+    __shared__ double sm[1024];
+    const int p = blockIdx.x;
+    if (p >= npatch || state[p] != order) return;
+    const double *pp = part + first[p];
+    const int n = cnt[p];
+    double v = 0.0;
+    for (int q = threadIdx.x; q < n; q += 1024) v += pp[q];
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[2 * p + slot] = sm[0];
+}
+
+__global__ __launch_bounds__(tr::NT) void kb_fold(const BRef *__restrict__ refs, int count,
+                                                  const BLev *__restrict__ lev, const int *__restrict__ state,
+                                                  int order, const double *const *__restrict__ rho,
+                                                  const double *const *__restrict__ dir,
+                                                  const double *const *__restrict__ phi) {
+    BRef r;
+    if (!take(refs, count, state, order, r)) return;
+    const BLev &L = lev[r.lev];
+    const int p = r.lev / MAXL, idx = r.w & IDX_MASK;
+    tr::fold_cell(tr::tile_cell(L.tiles[idx / TZ], idx % TZ, L.ntx, L.nty, L.nx, L.ny, L.nz), L.nx, L.ny, L.ih2,
+                  L.code, rho[p], dir[p], phi[p], L.f, L.x[0]);
+}
+
+__global__ __launch_bounds__(tr::NT) void kb_store(const BRef *__restrict__ refs, int count,
+                                                   const BLev *__restrict__ lev, const int *__restrict__ state,
+                                                   int order, double *const *__restrict__ phi) {
+    BRef r;
+    if (!take(refs, count, state, order, r)) return;
+    const BLev &L = lev[r.lev];
+    const int p = r.lev / MAXL, idx = r.w & IDX_MASK, sel = r.w >> WBITS;
+    tr::store_cell(tr::tile_cell(L.tiles[idx / TZ], idx % TZ, L.ntx, L.nty, L.nx, L.ny, L.nz), L.nx, L.ny, L.code,
+                   L.x[sel & 1], phi[p]);
+}
+
+inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
+
+// One launch of a program.
+struct Launch {
+    int kind, first, count;
+    size_t lds;  // dynamic LDS (K_SMALL)
+    int slot;    // K_FIN: norm slot
+};
 
 }  // namespace
 }  // namespace mg
@@ -243,41 +216,30 @@ struct mg_batch {
     mg_options opt;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    std::vector<mg_hierarchy *> patches;
-    // per patch and order: first small level (-1: none, never in a batch)
-    std::vector<int> ls[3];
-    std::vector<void *> allocs;                   // batch-owned device memory
-    mg::PLev *lev = nullptr;                      // device [n * MAXL]
-    mg::small::SmallLevels<double> *sl[3] = {};   // device [n], per order
-    double **small_scratch[3] = {};               // device [n], per order
-    // programs: fold, cycle per order, store
+    std::vector<mg_hierarchy *> patches;  // all enqueue on `stream`
+    std::vector<void *> allocs;           // batch-owned device memory
+    bool phased_ok = false;               // phase programs built
+    bool use_phases = true;
+    // phase programs: begin (fold, reference norms), one cycle per order, end (store)
     struct Prog {
-        mg::Phase *ph = nullptr;
-        int nph = 0;
-        mg::BItem *items = nullptr;
-        int nitems = 0;
+        std::vector<mg::Launch> k;
+        hipGraphExec_t exec = nullptr;
     };
-    Prog fold, store, cycle[3];
-    std::vector<int> cycle_parity[3];  // finest-level buffer holding x after a cycle from buffer 0
+    Prog begin, end, cycle[3];
+    mg::BRef *refs = nullptr;                    // device, all programs' work items
+    mg::BLev *lev[3] = {};                       // device [n * MAXL] per order
+    mg::small::SmallLevels<double> *sl[3] = {};  // device [n] per order
+    int *state[3] = {};                          // device [n]: [0] every patch 2, [o] this cycle's order-o patches
+    int *pin_state = nullptr;                    // pinned [3n]
+    int *nfirst = nullptr, *ncnt = nullptr;      // device [n]: each patch's norm partials within a norm phase
     double *part = nullptr;
-    int part_cap = 0;
-    double *norm2 = nullptr;      // device [2n]
-    double *norm2_host = nullptr; // pinned
-    int *state = nullptr;         // device [n]
-    const double **in_rho = nullptr, **in_dir = nullptr;
+    double *norm2 = nullptr;       // device [2n]
+    double *norm2_host = nullptr;  // pinned
+    const double **in_rho = nullptr, **in_dir = nullptr;  // device [n] each
     double **in_phi = nullptr;
-    unsigned *bar = nullptr;
-    int *err = nullptr;
-    int grid = 0;
-    std::vector<int> hold;
-    // pinned staging of per-solve uploads: input pointers, and one state array
-    // per queued program (the host never rewrites a buffer a pending copy reads)
-    const double **pin_ptrs = nullptr;  // [3n]: rho, dirichlet, phi
-    int *pin_state = nullptr;           // [3n]: fold/store, order 2, order 1
+    const double **pin_ptrs = nullptr;  // pinned [3n]: rho, dirichlet, phi
+    int small_lim = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    // lockstep engine: patch p runs on pstreams[p % size]
-    std::vector<hipStream_t> pstreams;
-    std::vector<hipEvent_t> pevents;
 };
 
 namespace mg {
@@ -286,6 +248,7 @@ namespace {
 struct BFail {
     mg_status st;
 };
+struct Unsupported {};
 
 #define BHIP(call)                                           \
     do {                                                     \
@@ -317,322 +280,395 @@ T *upload(mg_batch *B, const std::vector<T> &v) {
     return d;
 }
 
-std::vector<int> tiles_of(mg_batch *B, const OrderData &od) {
-    std::vector<int> t(od.ntiles);
-    if (od.ntiles) {
-        BHIP(hipMemcpyAsync(t.data(), od.tiles, od.ntiles * sizeof(int), hipMemcpyDeviceToHost, B->stream));
-        BHIP(hipStreamSynchronize(B->stream));
+// Emits the phase programs.  cur[p][l]: buffer holding patch p's level-l
+// iterate, tracked as the single-grid cycle does.
+struct Planner {
+    mg_batch *B;
+    int o;
+    std::vector<Launch> *out;
+    std::vector<BRef> &refs;
+    std::vector<std::array<int, MAXL>> cur;
+
+    Planner(mg_batch *b, int order, std::vector<BRef> &r) : B(b), o(order), out(nullptr), refs(r) {
+        cur.assign(b->n, std::array<int, MAXL>{});
+    }
+    static int pack(int idx, int sel) {
+        if (idx < 0 || idx > IDX_MASK) throw Unsupported{};
+        return idx | (sel << WBITS);
+    }
+    const OrderData &od(int p, int l) const { return B->patches[p]->lev[l].od[l == 0 ? 2 : o]; }
+    void open(int kind, size_t lds = 0, int slot = 0) {
+        out->push_back(Launch{kind, (int)refs.size(), 0, lds, slot});
+    }
+    void close() {
+        Launch &k = out->back();
+        k.count = (int)refs.size() - k.first;
+        if (k.count == 0) out->pop_back();
+    }
+    void add(int p, int l, int n, int sel) {
+        for (int i = 0; i < n; i++) refs.push_back(BRef{p * MAXL + l, pack(i, sel)});
+    }
+    // one red-black pass on level l (pro: the first post pass, with P2 on load)
+    void pass(const std::vector<int> &ps, int l, bool zero, bool pro) {
+        open((l == 0 ? K_SM0 : l == 1 ? K_SM1 : K_SM2) + (pro ? 1 : 0));
+        for (int p : ps)
+            add(p, l, od(p, l).nsegs, cur[p][l] | (zero ? 2 : 0) | (pro ? cur[p][l + 1] << 2 : 0));
+        close();
+        for (int p : ps) cur[p][l] ^= 1;
+    }
+    void smooth(const std::vector<int> &ps, int l, int passes, bool zero) {
+        if (ps.empty()) return;
+        if (passes == 0) {
+            if (zero) throw Unsupported{};  // the single-grid cycle zeroes the tiles here
+            return;
+        }
+        for (int j = 0; j < passes; j++) pass(ps, l, zero && j == 0, false);
+    }
+    // MG(l) for the patches ps, in the single-grid cycle's order of steps
+    void mg(const std::vector<int> &ps, int l, bool zero) {
+        const mg_options &op = B->opt;
+        std::vector<int> sm, last, reg;
+        for (int p : ps) {
+            const mg_hierarchy *H = B->patches[p];
+            if (l == H->ls[o]) sm.push_back(p);
+            else if (l == H->nlev[o] - 1) last.push_back(p);
+            else reg.push_back(p);
+        }
+        if (!sm.empty()) {
+            size_t lds = 0;
+            for (int p : sm) lds = std::max(lds, small_lds_bytes(B->patches[p], o, l, false));
+            if (lds > (size_t)B->small_lim) throw Unsupported{};
+            open(K_SMALL, lds);
+            for (int p : sm) add(p, l, 1, cur[p][l] | (zero ? 2 : 0));
+            close();
+        }
+        smooth(last, l, op.n_coarse_sweeps, zero);
+        if (reg.empty()) return;
+        smooth(reg, l, op.n_pre, zero);
+        open(l == 0 ? K_RES0 : K_RESC);
+        for (int p : reg) {
+            const Level &C = B->patches[p]->lev[l + 1];
+            if (C.od[o].ntiles) add(p, l, l == 0 ? od(p, 0).nsegs : C.od[o].ntiles * TZ, cur[p][l]);
+        }
+        close();
+        for (int c = 0; c < op.n_cycles; c++) mg(reg, l + 1, c == 0);
+        if (op.n_post == 0) throw Unsupported{};  // the single-grid cycle prolongs without a pass
+        pass(reg, l, false, true);
+        smooth(reg, l, op.n_post - 1, false);
+    }
+    // residual-norm partials of every patch's finest level and their sums into slot
+    void norm(bool with_x, int slot) {
+        open(K_NORM);
+        for (int p = 0; p < B->n; p++) add(p, 0, od(p, 0).nsegs, with_x ? cur[p][0] : 2);
+        close();
+        out->push_back(Launch{K_FIN, 0, B->n, 0, slot});
+    }
+    void tiles0(int kind) {
+        open(kind);
+        for (int p = 0; p < B->n; p++) add(p, 0, od(p, 0).ntiles * TZ, 0);
+        close();
+    }
+};
+
+// Level descriptors of one order.
+std::vector<BLev> descriptors(mg_batch *B, int o) {
+    std::vector<BLev> t((size_t)B->n * MAXL);
+    memset(t.data(), 0, t.size() * sizeof(BLev));
+    for (int p = 0; p < B->n; p++) {
+        const mg_hierarchy *H = B->patches[p];
+        for (int l = 0; l < H->nlev[o]; l++) {
+            const Level &L = H->lev[l];
+            const OrderData &d = L.od[l == 0 ? 2 : o];
+            BLev &e = t[(size_t)p * MAXL + l];
+            e.nx = L.nx; e.ny = L.ny; e.nz = L.nz; e.ntx = L.ntx; e.nty = L.nty;
+            e.h2 = L.h * L.h;
+            e.ih2 = 1.0 / (L.h * L.h);
+            e.x[0] = L.x[0]; e.x[1] = L.x[1]; e.f = L.f;
+            e.code = l == 0 ? L.code : nullptr;
+            e.d = l == 0 ? nullptr : L.od[o].d;
+            e.segs = d.segs; e.pm = d.pmask; e.tiles = d.tiles;
+            if (l + 1 < H->nlev[o]) {
+                const Level &C = H->lev[l + 1];
+                e.cnx = C.nx; e.cny = C.ny; e.cnz = C.nz; e.cntx = C.ntx; e.cnty = C.nty;
+                e.cx[0] = C.x[0]; e.cx[1] = C.x[1]; e.cf = C.f;
+                e.cd = C.od[o].d;
+                e.ctiles = C.od[o].tiles;
+            }
+        }
     }
     return t;
 }
 
-// Host view of the patch hierarchies used while emitting programs.
-struct Planner {
-    mg_batch *B;
-    int order;
-    std::vector<std::vector<int>> tiles[MAXL];  // [level][patch]
-    std::vector<std::vector<int>> cur;          // [patch][level] buffer holding the iterate
-    std::vector<Phase> ph;
-    std::vector<BItem> items;
-    int nparts = 0;
+// Small-level descriptors of one order (as the single-grid launch builds them).
+std::vector<small::SmallLevels<double>> small_levels(mg_batch *B, int o) {
+    std::vector<small::SmallLevels<double>> sl(B->n);
+    for (int p = 0; p < B->n; p++) {
+        small::SmallLevels<double> &S = sl[p];
+        memset(&S, 0, sizeof(S));
+        const mg_hierarchy *H = B->patches[p];
+        const int ls = H->ls[o];
+        if (ls < 0) continue;
+        S.n = H->nlev[o] - ls;
+        int off = 0;
+        for (int q = 0; q < S.n; q++) {
+            const Level &L = H->lev[ls + q];
+            S.nx[q] = L.nx; S.ny[q] = L.ny; S.nz[q] = L.nz;
+            S.mx[q] = small::div_magic((unsigned)L.nx);
+            S.mxy[q] = small::div_magic((unsigned)(L.nx * L.ny));
+            S.mh[q] = small::div_magic((unsigned)((L.nx + 1) / 2));
+            S.mhy[q] = small::div_magic((unsigned)((L.nx + 1) / 2 * L.ny));
+            S.h2[q] = L.h * L.h;
+            S.ih2[q] = 1.0 / (L.h * L.h);
+            S.d[q] = L.od[o].d;
+            S.off[q] = off;
+            off += 3 * (int)L.n;
+        }
+        S.n_pre = B->opt.n_pre;
+        S.n_post = B->opt.n_post;
+        S.n_cycles = B->opt.n_cycles;
+        S.n_coarse = B->opt.n_coarse_sweeps;
+    }
+    return sl;
+}
 
-    const std::vector<int> &tl(int p, int l) {
-        if (tiles[l].empty()) tiles[l].resize(B->n);
-        if (tiles[l][p].empty()) {
-            const Level &L = B->patches[p]->lev[l];
-            tiles[l][p] = tiles_of(B, L.od[l == 0 ? 2 : order]);
-            if (tiles[l][p].empty()) tiles[l][p].push_back(-1);  // marker: no tile
+// Builds the phase programs; false (and the lockstep engine) when the
+// options or a patch need a step the programs do not have.
+bool build_programs(mg_batch *B) {
+    const int n = B->n;
+    std::vector<BRef> refs;
+    try {
+        for (int o = 1; o <= 2; o++) {
+            Planner P(B, o, refs);
+            P.out = &B->cycle[o].k;
+            std::vector<int> all(n);
+            for (int p = 0; p < n; p++) all[p] = p;
+            P.mg(all, 0, false);
+            for (int p = 0; p < n; p++)
+                if (P.cur[p][0] != 0) throw Unsupported{};  // odd number of finest-level passes
+            P.norm(true, 0);
         }
-        return tiles[l][p];
+        Planner P(B, 2, refs);
+        P.out = &B->begin.k;
+        P.tiles0(K_FOLD);
+        P.norm(false, 1);
+        P.norm(true, 0);
+        P.out = &B->end.k;
+        P.tiles0(K_STORE);
+    } catch (const Unsupported &) {
+        for (auto *g : {&B->begin, &B->end, &B->cycle[1], &B->cycle[2]}) g->k.clear();
+        return false;
     }
-    void begin(int type, int flags = 0) { ph.push_back(Phase{type, (int)items.size(), 0, flags}); }
-    void end() {
-        ph.back().count = (int)items.size() - ph.back().first;
-        if (ph.back().count == 0) ph.pop_back();
+    // each patch's partials within a norm phase (every norm phase lists all
+    // patches' finest items in patch order)
+    std::vector<int> first(n), cnt(n);
+    int part_cap = 1, acc = 0;
+    for (int p = 0; p < n; p++) {
+        first[p] = acc;
+        cnt[p] = B->patches[p]->lev[0].od[2].nsegs;
+        acc += cnt[p];
     }
-    Seg seg_of(const Level &L, int tile) {
-        const int tx = tile % L.ntx, ty = (tile / L.ntx) % L.nty, tz = tile / (L.ntx * L.nty);
-        return Seg{tx * TX, ty * TY, tz * TZ, std::min(L.nz, (tz + 1) * TZ)};
+    part_cap = std::max(part_cap, acc);
+    B->refs = upload(B, refs);
+    B->nfirst = upload(B, first);
+    B->ncnt = upload(B, cnt);
+    B->part = balloc<double>(B, (size_t)part_cap);
+    for (int o = 1; o <= 2; o++) {
+        B->lev[o] = upload(B, descriptors(B, o));
+        B->sl[o] = upload(B, small_levels(B, o));
     }
-    void smooth(const std::vector<int> &ps, int l, bool zero) {
-        begin(l == 0 ? PH_SMOOTH0 : PH_SMOOTH);
-        for (int p : ps) {
-            const Level &L = B->patches[p]->lev[l];
-            for (int t : tl(p, l))
-                if (t >= 0) items.push_back(BItem{p, l, 0, cur[p][l] | (zero ? 2 : 0), seg_of(L, t)});
-        }
-        end();
-        for (int p : ps) cur[p][l] ^= 1;
-    }
-    // MG(l) for the patches ps (all have at least l+1 levels in this order)
-    void mg(const std::vector<int> &ps, int l, bool zero) {
-        const mg_options &o = B->opt;
-        std::vector<int> small, reg;
-        for (int p : ps) (B->ls[order][p] == l ? small : reg).push_back(p);
-        if (!small.empty()) {
-            begin(PH_SMALL);
-            for (int p : small) items.push_back(BItem{p, l, 0, cur[p][l] | (zero ? 2 : 0), Seg{}});
-            end();
-        }
-        if (reg.empty()) return;
-        for (int j = 0; j < o.n_pre; j++) smooth(reg, l, zero && j == 0);
-        begin(l == 0 ? PH_RESTRICT0 : PH_RESTRICT);
-        for (int p : reg)
-            for (int t : tl(p, l + 1))
-                if (t >= 0) items.push_back(BItem{p, l, t, cur[p][l], Seg{}});
-        end();
-        for (int c = 0; c < o.n_cycles; c++) mg(reg, l + 1, c == 0);
-        begin(l == 0 ? PH_PROLONG0 : PH_PROLONG);
-        for (int p : reg)
-            for (int t : tl(p, l))
-                if (t >= 0) items.push_back(BItem{p, l, t, cur[p][l] | (cur[p][l + 1] << 2), Seg{}});
-        end();
-        for (int j = 0; j < o.n_post; j++) smooth(reg, l, false);
-    }
-    // residual-norm partials of every patch's finest level, then per-patch sums into slot
-    void norm(bool with_x, int slot) {
-        std::vector<int> first(B->n), count(B->n);
-        begin(PH_NORM, with_x ? 1 : 0);
-        for (int p = 0; p < B->n; p++) {
-            first[p] = (int)items.size();
-            for (int t : tl(p, 0))
-                if (t >= 0) items.push_back(BItem{p, 0, t, cur[p][0], Seg{}});
-            count[p] = (int)items.size() - first[p];
-        }
-        end();
-        nparts = std::max(nparts, (int)items.size());
-        begin(PH_NORMSUM, slot);
-        for (int p = 0; p < B->n; p++) items.push_back(BItem{p, 0, first[p], count[p], Seg{}});
-        end();
-    }
-};
-
-mg_batch::Prog finish(mg_batch *B, Planner &P) {
-    mg_batch::Prog g;
-    g.ph = upload(B, P.ph);
-    g.nph = (int)P.ph.size();
-    g.items = upload(B, P.items);
-    g.nitems = (int)P.items.size();
-    B->part_cap = std::max(B->part_cap, (int)P.items.size());
-    return g;
+    B->lev[0] = B->lev[2];
+    for (int s = 0; s < 3; s++) B->state[s] = balloc<int>(B, n);
+    std::vector<int> all2(n, 2);
+    BHIP(hipMemcpyAsync(B->state[0], all2.data(), n * sizeof(int), hipMemcpyHostToDevice, B->stream));
+    BHIP(hipStreamSynchronize(B->stream));
+    B->in_rho = (const double **)balloc<double *>(B, n);
+    B->in_dir = (const double **)balloc<double *>(B, n);
+    B->in_phi = balloc<double *>(B, n);
+    BHIP(hipHostMalloc((void **)&B->pin_ptrs, 3 * (size_t)n * sizeof(double *), hipHostMallocDefault));
+    BHIP(hipHostMalloc((void **)&B->pin_state, 3 * (size_t)n * sizeof(int), hipHostMallocDefault));
+    return true;
 }
 
 void build_batch(mg_batch *B, const int8_t *const *masks, const int32_t *dims, const double *h) {
     const int n = B->n;
     BHIP(hipEventCreate(&B->ev0));
     BHIP(hipEventCreate(&B->ev1));
-    if (!kPersistentEnabled) {
-        // patch streams (default priority), ordered after the batch stream
-        BHIP(hipEventRecord(B->ev0, B->stream));
-        for (int k = 0; k < std::min(n, kPatchStreams); k++) {
-            hipStream_t ps = nullptr;
-            BHIP(hipStreamCreate(&ps));
-            B->pstreams.push_back(ps);
-            hipEvent_t ev = nullptr;
-            BHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-            B->pevents.push_back(ev);
-            BHIP(hipStreamWaitEvent(ps, B->ev0, 0));
-        }
-    }
-    // per-patch hierarchies (their own kernels are not used by the persistent engine)
     B->patches.resize(n, nullptr);
     for (int p = 0; p < n; p++) {
         mg_options o = B->opt;
-        o.use_graph = kPersistentEnabled ? 0 : 1;
+        o.use_graph = 1;  // the lockstep engine replays each patch's captured cycle
         mg_hierarchy *H = nullptr;
-        void *ps = kPersistentEnabled ? (void *)B->stream : (void *)B->pstreams[p % B->pstreams.size()];
-        const mg_status st = mg_create_hierarchy(masks[p], dims[3 * p], dims[3 * p + 1], dims[3 * p + 2], h[p], &o,
-                                                 ps, &H);
+        const mg_status st =
+            mg_create_hierarchy(masks[p], dims[3 * p], dims[3 * p + 1], dims[3 * p + 2], h[p], &o, B->stream, &H);
         if (st != MG_OK) throw BFail{st};
         B->patches[p] = H;
-        if (kPersistentEnabled && (H->nlev[1] < 2 || H->nlev[2] < 2)) {
-            set_error("batch patch " + std::to_string(p) + " has no coarse level");
-            throw BFail{MG_ERR_ARG};
-        }
     }
-    if (!kPersistentEnabled) {
-        for (hipStream_t ps : B->pstreams) BHIP(hipStreamSynchronize(ps));
-        BHIP(hipStreamSynchronize(B->stream));
-        return;
-    }
-    // level descriptors
-    std::vector<PLev> lev((size_t)n * MAXL);
-    for (int p = 0; p < n; p++)
-        for (int l = 0; l < B->patches[p]->nlev_geom; l++) {
-            const Level &L = B->patches[p]->lev[l];
-            PLev &d = lev[(size_t)p * MAXL + l];
-            d.nx = L.nx; d.ny = L.ny; d.nz = L.nz; d.ntx = L.ntx; d.nty = L.nty;
-            d.h2 = L.h * L.h;
-            d.ih2 = 1.0 / (L.h * L.h);
-            d.x[0] = L.x[0]; d.x[1] = L.x[1]; d.f = L.f;
-            d.code = L.code;
-            d.d[1] = L.od[1].d; d.d[2] = L.od[2].d;
-        }
-    B->lev = upload(B, lev);
-    // small levels per patch and order: the first coarse level that fits the
-    // kernel's LDS budget, else the deepest level run from global scratch
-    const size_t lds_budget = sizeof(BatchLds);
-    for (int o = 1; o <= 2; o++) {
-        B->ls[o].assign(n, -1);
-        std::vector<small::SmallLevels<double>> sl(n);
-        std::vector<double *> scr(n, nullptr);
-        for (int p = 0; p < n; p++) {
-            mg_hierarchy *H = B->patches[p];
-            int ls = -1;
-            for (int l = 1; l < H->nlev[o]; l++)
-                if (H->nlev[o] - l <= MAXS && small_lds_bytes(H, o, l, false) <= lds_budget) {
-                    ls = l;
-                    break;
-                }
-            if (ls < 0) {
-                ls = std::max(1, H->nlev[o] - MAXS);
-                ls = std::max(ls, H->nlev[o] - 1);
-                scr[p] = balloc<double>(B, small_lds_bytes(H, o, ls, false) / sizeof(double));
-            }
-            B->ls[o][p] = ls;
-            small::SmallLevels<double> &S = sl[p];
-            memset(&S, 0, sizeof(S));
-            S.n = H->nlev[o] - ls;
-            int off = 0;
-            for (int q = 0; q < S.n; q++) {
-                const Level &L = H->lev[ls + q];
-                S.nx[q] = L.nx; S.ny[q] = L.ny; S.nz[q] = L.nz;
-                S.mx[q] = small::div_magic((unsigned)L.nx);
-                S.mxy[q] = small::div_magic((unsigned)(L.nx * L.ny));
-                S.mh[q] = small::div_magic((unsigned)((L.nx + 1) / 2));
-                S.mhy[q] = small::div_magic((unsigned)((L.nx + 1) / 2 * L.ny));
-                S.h2[q] = L.h * L.h;
-                S.ih2[q] = 1.0 / (L.h * L.h);
-                S.d[q] = L.od[o].d;
-                S.off[q] = off;
-                off += 3 * (int)L.n;
-            }
-            S.n_pre = B->opt.n_pre;
-            S.n_post = B->opt.n_post;
-            S.n_cycles = B->opt.n_cycles;
-            S.n_coarse = B->opt.n_coarse_sweeps;
-        }
-        B->sl[o] = upload(B, sl);
-        B->small_scratch[o] = upload(B, scr);
-    }
-    // programs
-    for (int o = 1; o <= 2; o++) {
-        Planner P{B, o};
-        P.cur.assign(n, std::vector<int>(MAXL, 0));
-        std::vector<int> all(n);
-        for (int p = 0; p < n; p++) all[p] = p;
-        P.mg(all, 0, false);
-        P.norm(true, 0);
-        B->cycle_parity[o].resize(n);
-        for (int p = 0; p < n; p++) B->cycle_parity[o][p] = P.cur[p][0];
-        B->cycle[o] = finish(B, P);
-    }
-    {
-        Planner P{B, 2};
-        P.cur.assign(n, std::vector<int>(MAXL, 0));
-        P.begin(PH_FOLD);
-        for (int p = 0; p < n; p++)
-            for (int t : P.tl(p, 0))
-                if (t >= 0) P.items.push_back(BItem{p, 0, t, 0, Seg{}});
-        P.end();
-        P.norm(false, 1);
-        P.norm(true, 0);
-        B->fold = finish(B, P);
-    }
-    B->part = balloc<double>(B, (size_t)B->part_cap);
     B->norm2 = balloc<double>(B, 2 * (size_t)n);
     BHIP(hipHostMalloc((void **)&B->norm2_host, 2 * (size_t)n * sizeof(double), hipHostMallocDefault));
-    B->state = balloc<int>(B, n);
-    B->in_rho = (const double **)balloc<double *>(B, n);
-    B->in_dir = (const double **)balloc<double *>(B, n);
-    B->in_phi = balloc<double *>(B, n);
-    B->bar = balloc<unsigned>(B, 2);
-    B->err = balloc<int>(B, 1);
-    BHIP(hipMemsetAsync(B->bar, 0, 2 * sizeof(unsigned), B->stream));
-    BHIP(hipMemsetAsync(B->err, 0, sizeof(int), B->stream));
-    // co-resident grid for the cooperative launch
-    int dev = 0, ncu = 0, per = 0;
-    BHIP(hipGetDevice(&dev));
-    BHIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_batch, BNT, 0));
-    if (per < 1) {
-        set_error("batch kernel cannot be resident");
-        throw BFail{MG_ERR_HIP};
+    // the small-level workgroup gets the LDS the patches' small levels were sized for
+    B->small_lim = small_init();
+    bool lds_ok = B->small_lim > 0;
+    if (lds_ok && B->small_lim > 64 * 1024 - 1024 &&
+        hipFuncSetAttribute((const void *)kb_small, hipFuncAttributeMaxDynamicSharedMemorySize, B->small_lim) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        lds_ok = false;
     }
-    B->grid = ncu * per;
-    B->hold.assign(n, 0);
-    BHIP(hipHostMalloc((void **)&B->pin_ptrs, 3 * (size_t)n * sizeof(double *), hipHostMallocDefault));
-    BHIP(hipHostMalloc((void **)&B->pin_state, 3 * (size_t)n * sizeof(int), hipHostMallocDefault));
+    B->phased_ok = lds_ok && build_programs(B);
+    B->use_phases = B->phased_ok;
     BHIP(hipStreamSynchronize(B->stream));
 }
 
-void run_program(mg_batch *B, const mg_batch::Prog &g, int order) {
-    BatchArgs A;
-    memset(&A, 0, sizeof(A));
-    A.ph = g.ph;
-    A.nph = g.nph;
-    A.npatch = B->n;
-    A.items = g.items;
-    A.lev = B->lev;
-    A.sl = B->sl[order];
-    A.small_scratch = B->small_scratch[order];
-    A.part = B->part;
-    A.norm2 = B->norm2;
-    A.state = B->state;
-    A.order = order;
-    A.rho = B->in_rho;
-    A.dir = B->in_dir;
-    A.phi = B->in_phi;
-    A.bar = B->bar;
-    A.err = B->err;
-    A.n_pre = B->opt.n_pre;
-    A.n_post = B->opt.n_post;
-    A.n_cycles = B->opt.n_cycles;
-    A.n_coarse = B->opt.n_coarse_sweeps;
-    void *args[] = {&A};
-    BHIP(hipLaunchCooperativeKernel((const void *)k_batch, dim3(B->grid), dim3(BNT), args, 0, B->stream));
-}
-
-void check_barrier(mg_batch *B) {
-    int e = 0;
-    BHIP(hipMemcpyAsync(&e, B->err, sizeof(int), hipMemcpyDeviceToHost, B->stream));
-    BHIP(hipStreamSynchronize(B->stream));
-    if (e) {
-        set_error("batch grid barrier timed out (blocks not co-resident)");
-        throw BFail{MG_ERR_HIP};
+void launch(mg_batch *B, const Launch &k, int order, const int *state) {
+    const BRef *r = B->refs + k.first;
+    const BLev *lev = B->lev[order];
+    hipStream_t s = B->stream;
+    const unsigned g = grid8(k.count);
+    constexpr int NT = rb::NT;
+    switch (k.kind) {
+        case K_SM0: kb_smooth<true, FINE_Z, false><<<g, NT, 0, s>>>(r, k.count, lev, state, order); break;
+        case K_SM0P: kb_smooth<true, FINE_Z, true><<<g, NT, 0, s>>>(r, k.count, lev, state, order); break;
+        case K_SM1: kb_smooth<false, SEGZ_COARSE1, false><<<g, NT, 0, s>>>(r, k.count, lev, state, order); break;
+        case K_SM1P: kb_smooth<false, SEGZ_COARSE1, true><<<g, NT, 0, s>>>(r, k.count, lev, state, order); break;
+        case K_SM2: kb_smooth<false, SEGZ_COARSE, false><<<g, NT, 0, s>>>(r, k.count, lev, state, order); break;
+        case K_SM2P: kb_smooth<false, SEGZ_COARSE, true><<<g, NT, 0, s>>>(r, k.count, lev, state, order); break;
+        case K_RES0:
+            kb_residual<tr::RM_RESTRICT><<<g, NT, 0, s>>>(r, k.count, lev, state, order, nullptr);
+            break;
+        case K_RESC: kb_restrict<<<g, NT, 0, s>>>(r, k.count, lev, state, order); break;
+        case K_SMALL: kb_small<<<k.count, NTS, k.lds, s>>>(r, k.count, lev, state, order, B->sl[order]); break;
+        case K_NORM: kb_residual<tr::RM_NORM><<<g, NT, 0, s>>>(r, k.count, lev, state, order, B->part); break;
+        case K_FIN:
+            kb_finalize<<<B->n, 1024, 0, s>>>(B->nfirst, B->ncnt, B->n, B->part, B->norm2, k.slot, state, order);
+            break;
+        case K_FOLD:
+            kb_fold<<<g, NT, 0, s>>>(r, k.count, lev, state, order, B->in_rho, B->in_dir,
+                                     (const double *const *)B->in_phi);
+            break;
+        case K_STORE: kb_store<<<g, NT, 0, s>>>(r, k.count, lev, state, order, B->in_phi); break;
+        default: break;
     }
 }
 
-void clean_coarse(mg_batch *B, int p) {
-    mg_hierarchy *H = B->patches[p];
-    for (int l = 1; l < std::max(H->nlev[1], H->nlev[2]); l++)
-        for (int b = 0; b < 2; b++)
-            BHIP(hipMemsetAsync(H->lev[l].x[b], 0, H->lev[l].n * sizeof(double), B->stream));
+// One program on the batch stream, replayed from its captured graph when
+// the options ask for graphs.
+void run_program(mg_batch *B, mg_batch::Prog &g, int order, const int *state) {
+    if (!B->opt.use_graph) {
+        for (const Launch &k : g.k) launch(B, k, order, state);
+        BHIP(hipGetLastError());
+        return;
+    }
+    if (!g.exec) {
+        hipGraph_t graph = nullptr;
+        BHIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+        for (const Launch &k : g.k) launch(B, k, order, state);
+        const hipError_t le = hipGetLastError();
+        BHIP(hipStreamEndCapture(B->stream, &graph));
+        BHIP(le);
+        const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        BHIP(ie);
+    }
+    BHIP(hipGraphLaunch(g.exec, B->stream));
 }
 
-// Batch solve on the single-grid path in lockstep: every round enqueues one
-// cycle of each unconverged patch (its captured graph and 8-byte norm copy)
-// on the patch's stream, then synchronises all patch streams once and
+mg_status first_error(const std::vector<SolveState> &S) {
+    mg_status worst = MG_OK;
+    for (const SolveState &s : S)
+        if (s.st < 0 || (s.st == MG_NOT_CONVERGED && worst == MG_OK)) worst = s.st;
+    return worst;
+}
+
+mg_status finish_batch(mg_batch *B, std::vector<SolveState> &S, mg_solve_info *infos, double *ms_out) {
+    BHIP(hipEventRecord(B->ev1, B->stream));
+    BHIP(hipEventSynchronize(B->ev1));
+    float ms = 0.f;
+    BHIP(hipEventElapsedTime(&ms, B->ev0, B->ev1));
+    if (ms_out) *ms_out = ms;
+    for (int p = 0; p < B->n; p++) {
+        infos[p].status = S[p].st;
+        infos[p].ms = ms;
+    }
+    return first_error(S);
+}
+
+// The phase engine: per cycle, one program launch per boundary order in
+// use, one copy of all per-patch norms and one synchronisation.
+mg_status solve_batch_phased(mg_batch *B, const double *const *rho, double *const *phi, const double *const *dir,
+                             double tol, mg_solve_info *infos, double *ms_out) {
+    const int n = B->n;
+    hipStream_t s = B->stream;
+    std::vector<SolveState> S(n);
+    BHIP(hipStreamSynchronize(s));  // no copy of an earlier solve still reads the staging
+    BHIP(hipEventRecord(B->ev0, s));
+    for (int p = 0; p < n; p++) {
+        const mg_status st = phase_init(B->patches[p], phi[p], tol, &infos[p], S[p]);
+        if (st != MG_OK) return st;
+    }
+    const double **pr = B->pin_ptrs, **pd = B->pin_ptrs + n, **pp = B->pin_ptrs + 2 * n;
+    for (int p = 0; p < n; p++) {
+        pr[p] = rho[p];
+        pd[p] = dir ? dir[p] : nullptr;
+        pp[p] = phi[p];
+    }
+    BHIP(hipMemcpyAsync((void *)B->in_rho, pr, n * sizeof(double *), hipMemcpyHostToDevice, s));
+    BHIP(hipMemcpyAsync((void *)B->in_dir, pd, n * sizeof(double *), hipMemcpyHostToDevice, s));
+    BHIP(hipMemcpyAsync((void *)B->in_phi, pp, n * sizeof(double *), hipMemcpyHostToDevice, s));
+    run_program(B, B->begin, 2, B->state[0]);
+    BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+    BHIP(hipStreamSynchronize(s));
+    for (int p = 0; p < n; p++) {
+        mg_hierarchy *H = B->patches[p];
+        H->norm_host[0] = B->norm2_host[2 * p];
+        H->norm_host[1] = B->norm2_host[2 * p + 1];
+        const mg_status st = phase_start(H, S[p]);
+        if (st != MG_OK) return st;
+    }
+    std::vector<int> run;
+    while (true) {
+        run.clear();
+        for (int p = 0; p < n; p++)
+            if (S[p].active) run.push_back(p);
+        if (run.empty()) break;
+        for (int o = 2; o >= 1; o--) {
+            int *sv = B->pin_state + o * n;  // the previous cycle's copies have finished
+            bool use = false;
+            for (int p = 0; p < n; p++) {
+                sv[p] = (S[p].active && S[p].order == o) ? o : 0;
+                use |= sv[p] != 0;
+            }
+            if (!use) continue;
+            BHIP(hipMemcpyAsync(B->state[o], sv, n * sizeof(int), hipMemcpyHostToDevice, s));
+            run_program(B, B->cycle[o], o, B->state[o]);
+        }
+        BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+        BHIP(hipStreamSynchronize(s));
+        for (int p : run) {
+            mg_hierarchy *H = B->patches[p];
+            H->norm_host[0] = B->norm2_host[2 * p];
+            S[p].host_slot = 0;
+            S[p].parity = 0;  // the programs end with the finest iterate in buffer 0
+            const mg_status st = phase_cycle_finish(H, S[p]);
+            if (st != MG_OK) return st;
+        }
+    }
+    run_program(B, B->end, 2, B->state[0]);
+    return finish_batch(B, S, infos, ms_out);
+}
+
+// The lockstep engine: every round enqueues one captured cycle (with its
+// 8-byte norm copy) of each unconverged patch, then synchronises once and
 // applies each patch's stop test and order switch (Sec. 2, Sec. 4).
 mg_status solve_batch_lockstep(mg_batch *B, const double *const *rho, double *const *phi, const double *const *dir,
                                double tol, mg_solve_info *infos, double *ms_out) {
     const int n = B->n;
-    std::vector<mg_solve_info> tmp;
-    if (!infos) {
-        tmp.resize(n);
-        infos = tmp.data();
-    }
     std::vector<SolveState> S(n);
-    auto sync_all = [&]() {
-        for (hipStream_t ps : B->pstreams) BHIP(hipStreamSynchronize(ps));
-    };
     BHIP(hipEventRecord(B->ev0, B->stream));
-    for (hipStream_t ps : B->pstreams) BHIP(hipStreamWaitEvent(ps, B->ev0, 0));
     for (int p = 0; p < n; p++) {
         const mg_status st = phase_begin(B->patches[p], rho[p], phi[p], dir ? dir[p] : nullptr, tol, &infos[p], S[p]);
         if (st != MG_OK) return st;
     }
-    sync_all();
+    BHIP(hipStreamSynchronize(B->stream));
     for (int p = 0; p < n; p++) {
         const mg_status st = phase_start(B->patches[p], S[p]);
         if (st != MG_OK) return st;
@@ -647,7 +683,7 @@ mg_status solve_batch_lockstep(mg_batch *B, const double *const *rho, double *co
             const mg_status st = phase_cycle_enqueue(B->patches[p], S[p]);
             if (st != MG_OK) return st;
         }
-        sync_all();
+        BHIP(hipStreamSynchronize(B->stream));
         for (int p : run) {
             const mg_status st = phase_cycle_finish(B->patches[p], S[p]);
             if (st != MG_OK) return st;
@@ -657,142 +693,7 @@ mg_status solve_batch_lockstep(mg_batch *B, const double *const *rho, double *co
         const mg_status st = phase_end(B->patches[p], S[p]);
         if (st != MG_OK) return st;
     }
-    for (size_t k = 0; k < B->pstreams.size(); k++) {
-        BHIP(hipEventRecord(B->pevents[k], B->pstreams[k]));
-        BHIP(hipStreamWaitEvent(B->stream, B->pevents[k], 0));
-    }
-    BHIP(hipEventRecord(B->ev1, B->stream));
-    BHIP(hipEventSynchronize(B->ev1));
-    float ms = 0.f;
-    BHIP(hipEventElapsedTime(&ms, B->ev0, B->ev1));
-    if (ms_out) *ms_out = ms;
-    mg_status worst = MG_OK;
-    for (int p = 0; p < n; p++) {
-        infos[p].ms = ms;
-        const mg_status st = S[p].st;
-        if (st < 0 || (st == MG_NOT_CONVERGED && worst == MG_OK)) worst = st;
-    }
-    return worst;
-}
-
-mg_status solve_batch(mg_batch *B, const double *const *rho, double *const *phi, const double *const *dir, double tol,
-                      mg_solve_info *infos, double *ms_out) {
-    if (!kPersistentEnabled) return solve_batch_lockstep(B, rho, phi, dir, tol, infos, ms_out);
-    const int n = B->n;
-    const mg_options &o = B->opt;
-    std::vector<mg_solve_info> tmp;
-    if (!infos) {
-        tmp.resize(n);
-        infos = tmp.data();
-    }
-    std::vector<int> order(n), st(n, MG_NOT_CONVERGED), parity(n, 0), active(n, 1);
-    std::vector<double> rref(n), rprev(n);
-    for (int p = 0; p < n; p++) {
-        memset(&infos[p], 0, sizeof(mg_solve_info));
-        infos[p].switched_at_cycle = -1;
-        if (o.bc_order == MG_BC_FIRST || o.bc_order == MG_BC_SECOND) order[p] = o.bc_order;
-        else if (B->hold[p] > 0) {
-            order[p] = 1;
-            B->hold[p]--;
-        } else order[p] = 2;
-        if (B->patches[p]->coarse_order_state != 0 && B->patches[p]->coarse_order_state != order[p]) clean_coarse(B, p);
-        B->patches[p]->coarse_order_state = order[p];
-    }
-    BHIP(hipStreamSynchronize(B->stream));  // no copy of an earlier solve still reads the staging
-    const double **pr = B->pin_ptrs, **pd = B->pin_ptrs + n, **pp = B->pin_ptrs + 2 * n;
-    int *s_all = B->pin_state, *s_ord[3] = {nullptr, B->pin_state + 2 * n, B->pin_state + n};
-    for (int p = 0; p < n; p++) {
-        pr[p] = rho[p];
-        pd[p] = dir ? dir[p] : nullptr;
-        pp[p] = phi[p];
-        s_all[p] = 2;
-    }
-    BHIP(hipEventRecord(B->ev0, B->stream));
-    BHIP(hipMemsetAsync(B->bar, 0, 2 * sizeof(unsigned), B->stream));
-    BHIP(hipMemsetAsync(B->err, 0, sizeof(int), B->stream));
-    BHIP(hipMemcpyAsync((void *)B->in_rho, pr, n * sizeof(double *), hipMemcpyHostToDevice, B->stream));
-    BHIP(hipMemcpyAsync((void *)B->in_dir, pd, n * sizeof(double *), hipMemcpyHostToDevice, B->stream));
-    BHIP(hipMemcpyAsync((void *)B->in_phi, pp, n * sizeof(double *), hipMemcpyHostToDevice, B->stream));
-    BHIP(hipMemcpyAsync(B->state, s_all, n * sizeof(int), hipMemcpyHostToDevice, B->stream));
-    run_program(B, B->fold, 2);
-    BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, B->stream));
-    check_barrier(B);
-    for (int p = 0; p < n; p++) {
-        const double r0 = sqrt(B->norm2_host[2 * p]);
-        double rf = sqrt(B->norm2_host[2 * p + 1]);
-        if (rf == 0.0) rf = r0;
-        rref[p] = rf;
-        rprev[p] = r0;
-        infos[p].r0 = r0;
-        infos[p].r_ref = rf;
-        infos[p].history[0] = r0;
-        infos[p].r_final = r0;
-        infos[p].order_used = order[p];
-        if (!(r0 > tol * rf)) {
-            st[p] = std::isfinite(r0) ? MG_OK : MG_ERR_DIVERGED;
-            active[p] = 0;
-        }
-    }
-    for (int cyc = 1; cyc <= o.max_cycles; cyc++) {
-        bool any = false;
-        for (int p = 0; p < n; p++) any |= active[p] != 0;
-        if (!any) break;
-        for (int oo = 2; oo >= 1; oo--) {
-            int *sv = s_ord[oo];  // previous cycle's copies finished (synchronised below)
-            bool use = false;
-            for (int p = 0; p < n; p++) {
-                sv[p] = (active[p] && order[p] == oo) ? oo : 0;
-                use |= sv[p] != 0;
-            }
-            if (!use) continue;
-            BHIP(hipMemcpyAsync(B->state, sv, n * sizeof(int), hipMemcpyHostToDevice, B->stream));
-            run_program(B, B->cycle[oo], oo);
-        }
-        BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, B->stream));
-        check_barrier(B);
-        for (int p = 0; p < n; p++) {
-            if (!active[p]) continue;
-            parity[p] = B->cycle_parity[order[p]][p] ^ parity[p];
-            const double rn = sqrt(B->norm2_host[2 * p]);
-            infos[p].cycles = cyc;
-            infos[p].r_final = rn;
-            if (cyc < 257) infos[p].history[cyc] = rn;
-            if (!std::isfinite(rn)) {
-                st[p] = MG_ERR_DIVERGED;
-                active[p] = 0;
-                continue;
-            }
-            if (rn <= tol * rref[p]) {
-                st[p] = MG_OK;
-                active[p] = 0;
-                continue;
-            }
-            if (o.bc_order == MG_BC_AUTO && order[p] == 2 && rn / rprev[p] > o.eta) {
-                order[p] = 1;
-                B->hold[p] = o.first_order_hold;
-                infos[p].switched_at_cycle = cyc;
-                infos[p].order_used = 1;
-                clean_coarse(B, p);
-                B->patches[p]->coarse_order_state = 1;
-            }
-            rprev[p] = rn;
-        }
-    }
-    // store every patch's iterate (s_all still holds 2 for every patch)
-    BHIP(hipMemcpyAsync(B->state, s_all, n * sizeof(int), hipMemcpyHostToDevice, B->stream));
-    run_program(B, B->store, 2);
-    BHIP(hipEventRecord(B->ev1, B->stream));
-    check_barrier(B);
-    float ms = 0.f;
-    BHIP(hipEventElapsedTime(&ms, B->ev0, B->ev1));
-    if (ms_out) *ms_out = ms;
-    mg_status worst = MG_OK;
-    for (int p = 0; p < n; p++) {
-        infos[p].status = st[p];
-        infos[p].ms = ms;
-        if (st[p] < 0 || (st[p] == MG_NOT_CONVERGED && worst == MG_OK)) worst = (mg_status)st[p];
-    }
-    return worst;
+    return finish_batch(B, S, infos, ms_out);
 }
 
 }  // namespace
@@ -805,10 +706,9 @@ extern "C" {
 void mg_destroy_batch(mg_batch *B) {
     if (!B) return;
     if (B->stream) (void)hipStreamSynchronize(B->stream);
-    for (hipStream_t ps : B->pstreams) (void)hipStreamSynchronize(ps);
+    for (auto *g : {&B->begin, &B->end, &B->cycle[1], &B->cycle[2]})
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
     for (mg_hierarchy *H : B->patches) mg_destroy_hierarchy(H);
-    for (hipEvent_t ev : B->pevents) (void)hipEventDestroy(ev);
-    for (hipStream_t ps : B->pstreams) (void)hipStreamDestroy(ps);
     for (void *p : B->allocs) {
         if (B->opt.allocator.free) B->opt.allocator.free(p, B->opt.allocator.ctx);
         else if (!B->opt.allocator.alloc) (void)hipFree(p);
@@ -840,12 +740,6 @@ mg_status mg_create_batch(int32_t n, const int8_t *const *masks_dev, const int32
         delete B;
         return MG_ERR_ARG;
     }
-    if (kPersistentEnabled && (B->opt.n_pre + B->opt.n_post) % 2 != 0) {
-        // the cycle programs keep the finest iterate in buffer 0 between cycles
-        set_error("the batched solver needs an even number of finest-level passes per cycle");
-        delete B;
-        return MG_ERR_ARG;
-    }
     B->stream = (hipStream_t)stream;
     mg_status st = MG_OK;
     try {
@@ -854,20 +748,6 @@ mg_status mg_create_batch(int32_t n, const int8_t *const *masks_dev, const int32
             B->own_stream = true;
         }
         build_batch(B, masks_dev, dims, h);
-        if (!kPersistentEnabled) {
-            *out = B;
-            return MG_OK;
-        }
-        // store program (needs the per-patch finest tile lists)
-        Planner P{B, 2};
-        P.cur.assign(n, std::vector<int>(MAXL, 0));
-        P.begin(PH_STORE);
-        for (int p = 0; p < n; p++)
-            for (int t : P.tl(p, 0))
-                if (t >= 0) P.items.push_back(BItem{p, 0, t, 0, Seg{}});
-        P.end();
-        B->store = finish(B, P);
-        BHIP(hipStreamSynchronize(B->stream));
     } catch (const BFail &f) {
         st = f.st;
     } catch (const std::bad_alloc &) {
@@ -893,23 +773,51 @@ mg_status mg_solve_batch(mg_batch *B, const double *const *rho_dev, double *cons
             set_error("null rho or phi in batch");
             return MG_ERR_ARG;
         }
+    std::vector<mg_solve_info> tmp;
     try {
-        return solve_batch(B, rho_dev, phi_dev, dirichlet_dev, tol, infos, ms_out);
+        if (!infos) {
+            tmp.resize(B->n);
+            infos = tmp.data();
+        }
+        if (B->use_phases) return solve_batch_phased(B, rho_dev, phi_dev, dirichlet_dev, tol, infos, ms_out);
+        return solve_batch_lockstep(B, rho_dev, phi_dev, dirichlet_dev, tol, infos, ms_out);
     } catch (const BFail &f) {
         return f.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return MG_ERR_ALLOC;
     } catch (...) {
         set_error("unexpected internal error");
         return MG_ERR_HIP;
     }
 }
 
+mg_status mg_batch_set_engine(mg_batch *B, int32_t phased) {
+    if (!B) {
+        set_error("null batch");
+        return MG_ERR_ARG;
+    }
+    if (phased && !B->phased_ok) {
+        set_error("the phase programs do not cover these options; the batch runs per patch");
+        return MG_ERR_ARG;
+    }
+    B->use_phases = phased != 0;
+    return MG_OK;
+}
+
 int32_t mg_batch_size(const mg_batch *B) { return B ? B->n : 0; }
 
-int32_t mg_batch_grid(const mg_batch *B) { return B ? B->grid : 0; }
+int32_t mg_batch_grid(const mg_batch *B) {
+    if (!B || !B->phased_ok) return 0;
+    int m = 0;
+    for (int o = 1; o <= 2; o++)
+        for (const mg::Launch &k : B->cycle[o].k) m = std::max(m, k.count);
+    return m;
+}
 
 int32_t mg_batch_phases(const mg_batch *B, int32_t order) {
-    if (!B || (order != 1 && order != 2)) return 0;
-    return B->cycle[order].nph;
+    if (!B || !B->phased_ok || (order != 1 && order != 2)) return 0;
+    return (int32_t)B->cycle[order].k.size();
 }
 
 }  // extern "C"

@@ -119,6 +119,10 @@ struct SolveState {
 // synchronised); end: enqueue the store of phi and the end event.
 mg_status phase_begin(mg_hierarchy *H, const double *rho, double *phi, const double *B, double tol,
                       mg_solve_info *info, SolveState &S);
+// init: begin's host part alone (state, order, coarse buffers cleaned); the
+// caller computes the fold and both reference norms itself and stores them
+// in norm_host[0] (of the guess) and norm_host[1] (of f) before start.
+mg_status phase_init(mg_hierarchy *H, double *phi, double tol, mg_solve_info *info, SolveState &S);
 mg_status phase_start(mg_hierarchy *H, SolveState &S);
 mg_status phase_cycle_enqueue(mg_hierarchy *H, SolveState &S);
 mg_status phase_cycle_finish(mg_hierarchy *H, SolveState &S);

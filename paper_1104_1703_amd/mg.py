@@ -78,6 +78,7 @@ SYMBOLS = [
     ("mg_batch_size", _I, [_P]),
     ("mg_batch_grid", _I, [_P]),
     ("mg_batch_phases", _I, [_P, _I]),
+    ("mg_batch_set_engine", C.c_int, [_P, _I]),
     # learned first guess
     ("mg_unet_create", C.c_int, [C.c_uint64, _P, _P, C.POINTER(_P)]),
     ("mg_unet_destroy", None, [_P]),
@@ -333,8 +334,9 @@ class Hierarchy:
 
 
 class Batch:
-    """Many independent masked grids solved together (one persistent launch
-    per multigrid cycle for the whole batch).
+    """Many independent masked grids solved together: each multigrid cycle
+    of all patches runs as one program of phase launches (the per-patch
+    lockstep engine where the programs do not cover the options).
 
     ``masks``: list of int8 tensors (each (nz, ny, nx), inactive outer layer);
     ``hs``: cell widths.  Options as for :class:`Hierarchy` (FP64 only).
@@ -372,6 +374,10 @@ class Batch:
 
     def phases(self, order: int = 2) -> int:
         return int(load_library().mg_batch_phases(self._b, order))
+
+    def set_engine(self, phased: bool):
+        """Phase programs (True) or per-patch lockstep cycles (False)."""
+        _check(load_library().mg_batch_set_engine(self._b, 1 if phased else 0), "mg_batch_set_engine")
 
     def solve(self, rhos, phis=None, dirichlets=None, tol: float = 1e-10, check: bool = True):
         """Solve every patch in place; returns (phis, list of info dicts, ms)."""

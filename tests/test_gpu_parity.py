@@ -364,93 +364,51 @@ def _batch_case(mg, probs, **opts):
     B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], **opts)
     rhos = [dev(p.rho) for p in probs]
     dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
-    phis, infos, ms = B.solve(rhos, None, dirs, tol=1e-10)
+    phis, infos, ms = B.solve(rhos, None, dirs, tol=1e-10, check=False)
     return B, [host(x) for x in phis], infos, ms
 
 
-@pytest.mark.skip(reason="persistent batch kernel disabled: its GPU runs ended in HSA_STATUS_ERROR_MEMORY_APERTURE_VIOLATION, cause not yet found")
 @pytest.mark.parametrize("opts", [dict(), dict(bc_order="second"), dict(n_cycles=2)])
 def test_batch_matches_oracle_per_patch(mg, opts):
-    """Uneven patches in one batch: every patch takes the same cycles, switch
-    and solution as the oracle's own solve of that patch."""
+    """Uneven patches in one batch on the phase programs: every patch takes
+    the same cycles, switch and solution as the oracle's own solve of it.  In
+    forced second order the porous patch diverges (features below the coarse
+    cell size, Sec. 4), in the oracle as in the batch."""
     probs = gen.patch_problems(count=6, seed=3) + [gen.sphere_problem(32), gen.holes_problem(n=64, seed=2),
                                                    gen.porous_problem(n=64, seed=4)]
     for p in probs:
         _print_case(p.name, p)
     B, got, infos, ms = _batch_case(mg, probs, **opts)
+    assert B.phases(1) > 0 and B.phases(2) > 0 and B.grid > 0   # phase engine in use
     oo = {k: v for k, v in opts.items() if k in ("bc_order", "n_cycles")}
     for p, x, info in zip(probs, got, infos):
         orc = O.Oracle(p.mask, p.h)
         ref, rinfo = orc.solve(p.rho, None, p.dirichlet, tol=1e-10, **oo)
         act = p.mask == 1
-        assert info["status"] == rinfo["status"] == 0, (p.name, info["status"], rinfo["status"])
+        assert info["status"] == rinfo["status"], (p.name, info["status"], rinfo["status"])
+        if opts.get("bc_order") == "second" and p.name.startswith("porous"):
+            assert info["status"] == mg.MG_ERR_DIVERGED
+            continue
+        assert info["status"] == 0, p.name
         assert info["cycles"] == rinfo["cycles"], (p.name, info["cycles"], rinfo["cycles"])
         assert info["switched_at"] == rinfo["switched_at"], p.name
         assert relerr(x, ref, act) <= TOL, p.name
     B.close()
 
 
-@pytest.mark.skip(reason="persistent batch kernel disabled: its GPU runs ended in HSA_STATUS_ERROR_MEMORY_APERTURE_VIOLATION, cause not yet found")
-def test_batch_equals_single_solves_and_repeats(mg):
-    """The batch gives each patch what mg_solve gives it alone, and a second
-    batch solve (first-order hold in force where a patch switched) matches a
-    second single solve."""
-    probs = gen.patch_problems(count=10, seed=7)
-    B, got, infos, ms = _batch_case(mg, probs)
-    singles = [mg.Hierarchy(dev(p.mask), p.h) for p in probs]
-    for p, x, info, H in zip(probs, got, infos, singles):
-        d = None if p.dirichlet is None else dev(p.dirichlet)
-        phi, sinfo = H.solve(dev(p.rho), None, d, tol=1e-10)
-        assert info["cycles"] == sinfo["cycles"] and info["switched_at"] == sinfo["switched_at"]
-        assert relerr(x, host(phi), p.mask == 1) <= TOL
-    phis2, infos2, _ = B.solve([dev(p.rho) for p in probs], None,
-                               [None if p.dirichlet is None else dev(p.dirichlet) for p in probs], tol=1e-10)
-    for p, x, info, H in zip(probs, phis2, infos2, singles):
-        d = None if p.dirichlet is None else dev(p.dirichlet)
-        phi, sinfo = H.solve(dev(p.rho), None, d, tol=1e-10)
-        assert info["cycles"] == sinfo["cycles"] and info["order_used"] == sinfo["order_used"]
-        assert relerr(host(x), host(phi), p.mask == 1) <= TOL
-        H.close()
-    B.close()
-
-
-@pytest.mark.skip(reason="persistent batch kernel disabled: its GPU runs ended in HSA_STATUS_ERROR_MEMORY_APERTURE_VIOLATION, cause not yet found")
-def test_batch_rejects_odd_pass_count(mg):
-    p = gen.sphere_problem(16)
-    with pytest.raises(mg.MGError) as e:
-        mg.Batch([dev(p.mask)], [p.h], n_pre=1, n_post=2)
-    assert e.value.status == mg.MG_ERR_ARG
-
-
-# The batch API on its per-patch engine (each patch's own captured cycles).
-@pytest.mark.parametrize("opts", [dict(), dict(n_cycles=2)])
-def test_batch_per_patch_engine_matches_oracle(mg, opts):
-    probs = gen.patch_problems(count=5, seed=11) + [gen.sphere_problem(32), gen.porous_problem(n=64, seed=4)]
-    for p in probs:
-        _print_case(p.name, p)
-    B, got, infos, ms = _batch_case(mg, probs, **opts)
-    assert B.grid == 0 and B.phases(2) == 0       # persistent engine off
-    for p, x, info in zip(probs, got, infos):
-        orc = O.Oracle(p.mask, p.h)
-        oo = {k: v for k, v in opts.items() if k in ("n_cycles",)}
-        ref, rinfo = orc.solve(p.rho, None, p.dirichlet, tol=1e-10, **oo)
-        assert info["status"] == rinfo["status"] == 0, p.name
-        assert info["cycles"] == rinfo["cycles"] and info["switched_at"] == rinfo["switched_at"], p.name
-        assert relerr(x, ref, p.mask == 1) <= TOL, p.name
-    B.close()
-
-
-def test_batch_lockstep_equals_single_solves_and_repeats(mg):
-    """24 patches over the engine's streams, solved twice (the second solve
-    starts in first order where the first switched): every patch equals its
-    own single-grid solve bit for bit, with the same cycles and switch."""
+@pytest.mark.parametrize("engine", ["phased", "phased_graph", "lockstep"])
+def test_batch_equals_single_solves_and_repeats(mg, engine):
+    """24 patches solved twice (the second solve starts in first order where
+    the first switched): on either engine every patch equals its own
+    single-grid solve bit for bit, with the same cycles and switch."""
     probs = gen.patch_problems(count=22, seed=12) + [gen.porous_problem(n=64, seed=4), gen.sphere_problem(32)]
-    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs])
+    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], use_graph=int(engine == "phased_graph"))
+    B.set_engine(engine != "lockstep")
     singles = [mg.Hierarchy(dev(p.mask), p.h) for p in probs]
     rhos = [dev(p.rho) for p in probs]
     dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
     for rep in range(2):
-        print(f"[case] lockstep batch of {len(probs)}, solve {rep}", flush=True)
+        print(f"[case] {engine} batch of {len(probs)}, solve {rep}", flush=True)
         got, infos, ms = B.solve(rhos, dirichlets=dirs, tol=1e-10)
         assert ms > 0
         for p, H, x, info, r, d in zip(probs, singles, got, infos, rhos, dirs):
@@ -458,6 +416,69 @@ def test_batch_lockstep_equals_single_solves_and_repeats(mg):
             assert info["status"] == rinfo["status"] == 0, p.name
             assert (info["cycles"], info["switched_at"], info["order_used"]) == \
                 (rinfo["cycles"], rinfo["switched_at"], rinfo["order_used"]), p.name
+            assert info["r0"] == rinfo["r0"] and info["r_ref"] == rinfo["r_ref"], p.name
+            assert info["r_final"] == rinfo["r_final"], p.name
             assert np.array_equal(host(x), host(ref)), p.name
-    assert any(i["switched_at"] > 0 for i in infos) or any(i["order_used"] == 1 for i in infos)
+        if rep == 0:
+            assert any(i["switched_at"] > 0 for i in infos)
+    assert any(i["order_used"] == 1 for i in infos)
+    for H in singles:
+        H.close()
+    B.close()
+
+
+def test_batch_guess_and_max_cycles(mg):
+    """Phase engine with a non-zero guess (junk in inactive cells must not
+    leak) and a cycle cap: the same iterate as single solves, MG_NOT_CONVERGED
+    reported per patch."""
+    probs = gen.patch_problems(count=5, seed=21)
+    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], max_cycles=3)
+    assert B.phases(2) > 0
+    rng = np.random.default_rng(5)
+    guesses = [rng.standard_normal(p.mask.shape) for p in probs]
+    rhos = [dev(p.rho) for p in probs]
+    dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
+    got, infos, _ = B.solve(rhos, [dev(g) for g in guesses], dirs, tol=1e-10)
+    for p, g, x, info, r, d in zip(probs, guesses, got, infos, rhos, dirs):
+        H = mg.Hierarchy(dev(p.mask), p.h, max_cycles=3)
+        ref, rinfo = H.solve(r, dev(g), d, tol=1e-10, check=False)
+        assert info["cycles"] == rinfo["cycles"] == 3 and info["status"] == rinfo["status"] == mg.MG_NOT_CONVERGED
+        assert np.array_equal(host(x), host(ref)), p.name
+        H.close()
+    B.close()
+
+
+def test_batch_odd_pass_count_runs_per_patch(mg):
+    """1 + 2 passes leave the finest iterate in the other buffer after each
+    cycle: no phase programs, the per-patch engine solves, oracle parity."""
+    probs = gen.patch_problems(count=3, seed=5) + [gen.sphere_problem(16)]
+    B, got, infos, ms = _batch_case(mg, probs, n_pre=1, n_post=2)
+    assert B.grid == 0 and B.phases(2) == 0
+    with pytest.raises(mg.MGError) as e:
+        B.set_engine(True)
+    assert e.value.status == mg.MG_ERR_ARG
+    for p, x, info in zip(probs, got, infos):
+        ref, rinfo = O.Oracle(p.mask, p.h).solve(p.rho, None, p.dirichlet, tol=1e-10, n_pre=1, n_post=2)
+        assert info["status"] == rinfo["status"] == 0, p.name
+        assert info["cycles"] == rinfo["cycles"] and info["switched_at"] == rinfo["switched_at"], p.name
+        assert relerr(x, ref, p.mask == 1) <= TOL, p.name
+    B.close()
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(n_cycles=2)])
+def test_batch_per_patch_engine_matches_oracle(mg, opts):
+    probs = gen.patch_problems(count=5, seed=11) + [gen.sphere_problem(32), gen.porous_problem(n=64, seed=4)]
+    for p in probs:
+        _print_case(p.name, p)
+    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], **opts)
+    B.set_engine(False)
+    got, infos, ms = B.solve([dev(p.rho) for p in probs], None,
+                             [None if p.dirichlet is None else dev(p.dirichlet) for p in probs], tol=1e-10)
+    for p, x, info in zip(probs, got, infos):
+        orc = O.Oracle(p.mask, p.h)
+        oo = {k: v for k, v in opts.items() if k in ("n_cycles",)}
+        ref, rinfo = orc.solve(p.rho, None, p.dirichlet, tol=1e-10, **oo)
+        assert info["status"] == rinfo["status"] == 0, p.name
+        assert info["cycles"] == rinfo["cycles"] and info["switched_at"] == rinfo["switched_at"], p.name
+        assert relerr(host(x), ref, p.mask == 1) <= TOL, p.name
     B.close()
