@@ -77,6 +77,8 @@ def parse():
                     help="counter runs: build the 256^3 hierarchy, launch only the finest smoother N times, exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="counter runs: 4 plain device copies of MIB MiB (known bytes), exit")
+    ap.add_argument("--profile-batch", type=int, default=0, metavar="N",
+                    help="kernel runs: N batch solves of the --batch-patches workload after one warm-up, exit")
     ap.add_argument("--profile-unet", type=int, default=0, metavar="N",
                     help="kernel runs: N U-Net inferences (256^3 holes, --learned-stride) and N training steps "
                          "(batch 8 of 64^3), exit")
@@ -168,11 +170,18 @@ def unet_conv_roofline():
             "traffic": None, "avg_launch_us": round(ms * 1e3, 2), "algorithmic_flops_per_launch": flops}
 
 
-def batch_measurement(args):
+def profile_batch(args):
+    """Batch solves alone, for kernel-trace runs: one warm-up, then N solves."""
+    r = batch_measurement(args, solves=args.profile_batch)
+    print(json.dumps({"mode": "profile-batch", "solves": args.profile_batch, **r}), flush=True)
+
+
+def batch_measurement(args, solves=3):
     """The batched workload: `--batch-patches` masked patches (edges log-uniform
     in 16..128, multiples of 8, seed 3), FP64, V(2,2), each to 1e-10; the
     wall time of one mg_solve_batch call (inputs resident), median of 3
-    after one warm-up; the patch hierarchies are built once, untimed."""
+    after one warm-up (`solves` timed solves); the patch hierarchies are
+    built once, untimed."""
     import torch
 
     from paper_1104_1703_amd import gen, mg
@@ -191,7 +200,7 @@ def batch_measurement(args):
     if B_phases == 0:
         raise RuntimeError("the batch has no phase programs for the default options")
     walls, infos = [], None
-    for rep in range(4):
+    for rep in range(solves + 1):
         for x in phis:
             x.zero_()
         torch.cuda.synchronize()
@@ -248,6 +257,8 @@ def main():
         return copy_calibration(args)
     if args.profile_unet:
         return profile_unet(args)
+    if args.profile_batch:
+        return profile_batch(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
               "(domain decomposition is described, not implemented).", file=sys.stderr)
