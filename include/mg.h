@@ -70,6 +70,9 @@ typedef struct {
     int32_t first_order_hold; /* solves kept in first order after a switch (Sec. 4: 10) */
     int32_t use_graph;        /* 1 = replay each cycle as a captured hipGraph; 0 (default) =
                                  launch its kernels directly (measured faster for one solve) */
+    int32_t fuse_passes;      /* 1 = run each pair of consecutive red-black passes on a level
+                                 as one launch (two passes per march: x, f and the diagonal
+                                 read once for both); same results bit for bit (default 0) */
     mg_allocator allocator;
 } mg_options;
 
@@ -189,7 +192,8 @@ mg_status mg_vcycle(mg_hierarchy *H, int32_t order, double *x_dev, const double 
 /*
  * Run the finest-level smoother kernel `launches` times on the hierarchy's
  * own buffers (contents left by the last solve), back to back on the
- * hierarchy stream, for bandwidth measurement.  Host returns at once.
+ * hierarchy stream, for bandwidth measurement (with fuse_passes, each launch
+ * is the fused kernel doing two passes).  Host returns at once.
  */
 mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches);
 

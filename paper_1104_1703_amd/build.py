@@ -25,6 +25,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the smoother marches are fully unrolled (compile-time ring slots and
+    # register sets); the fused two-pass march exceeds the default limit
+    "-mllvm", "-pragma-unroll-threshold=1000000",
     "-I", INCLUDE, "-I", CSRC,
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]

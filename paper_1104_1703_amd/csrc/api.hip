@@ -110,13 +110,18 @@ void build_lists(mg_hierarchy *H, int l, int order) {
     const int npl = item_planes(l);
     od.pmask = alloc_n<unsigned long long>(H, std::max<size_t>(1, segs.size() * npl));
     launch_item_masks(L, l, order, od, npl, od.pmask, H->stream);
+    if (H->opt.fuse_passes) {
+        const int npl2 = item_planes2(l);
+        od.pmask2 = alloc_n<unsigned long long>(H, std::max<size_t>(1, segs.size() * npl2));
+        launch_item_masks(L, l, order, od, npl2, od.pmask2, H->stream, 4);
+    }
     HIPCHK(hipStreamSynchronize(H->stream));
 }
 
 mg_status validate_options(const mg_options &o) {
     if (o.n_pre < 0 || o.n_post < 0 || o.n_cycles < 1 || o.n_coarse_sweeps < 0 || o.min_coarse_dim < 1 ||
         o.max_cycles < 0 || (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.bc_order < 0 ||
-        o.bc_order > 2 || !(o.eta > 0) || o.first_order_hold < 0) {
+        o.bc_order > 2 || !(o.eta > 0) || o.first_order_hold < 0 || o.fuse_passes < 0 || o.fuse_passes > 1) {
         set_error("invalid mg_options");
         return MG_ERR_ARG;
     }
@@ -268,13 +273,26 @@ void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur 
         }
         return;
     }
-    for (int p = 0; p < passes; p++) {
+    // with fuse_passes each pair of passes is one launch (one buffer flip)
+    for (int p = 0; p < passes;) {
         const int a = cur.c[l], b = a ^ 1;
         const bool zin = (p == 0 && zero_start);
-        if (f32) launch_rbgs32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream);
-        else launch_rbgs(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream);
+        if (H->opt.fuse_passes && passes - p >= 2) {
+            if (f32) launch_rbgs2_32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream);
+            else launch_rbgs2(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream);
+            p += 2;
+        } else {
+            if (f32) launch_rbgs32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream);
+            else launch_rbgs(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream);
+            p += 1;
+        }
         cur.c[l] = b;
     }
+}
+
+// Launches (= buffer flips) of `passes` passes.
+int pass_launches(const mg_hierarchy *H, int passes) {
+    return H->opt.fuse_passes ? passes / 2 + passes % 2 : passes;
 }
 
 // One multigrid iteration at level l (Sec. 2 enumerated recipe): N_pre
@@ -306,12 +324,19 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
         return;
     }
     // the first post-smoothing pass applies the prolongation as it loads x
+    // (on the finest level with fuse_passes, fused with the pass after it)
     const OrderData &od = odata(H, l, order);
     const int a = cur.c[l], b = a ^ 1;
-    if (f32) launch_rbgs_prolong32(L, l, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream);
-    else launch_rbgs_prolong(L, l, od, C, C.x[cur.c[l + 1]], L.x[a], L.x[b], L.f, H->stream);
+    const bool fused = H->opt.fuse_passes && l == 0 && o.n_post >= 2;
+    if (fused) {
+        if (f32) launch_rbgs2_prolong32(L, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream);
+        else launch_rbgs2_prolong(L, od, C, C.x[cur.c[l + 1]], L.x[a], L.x[b], L.f, H->stream);
+    } else {
+        if (f32) launch_rbgs_prolong32(L, l, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream);
+        else launch_rbgs_prolong(L, l, od, C, C.x[cur.c[l + 1]], L.x[a], L.x[b], L.f, H->stream);
+    }
     cur.c[l] = b;
-    smooth(H, l, order, o.n_post - 1, false, cur, f32);
+    smooth(H, l, order, o.n_post - (fused ? 2 : 1), false, cur, f32);
 }
 
 // Coarse iterates must be 0 outside the active tiles of the order in use.
@@ -360,10 +385,15 @@ void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *pari
     *parity_out = mixed ? parity ^ 1 : cur.c[0];
 }
 
+// Finest-level buffer flips of one FP64 cycle, as mg_level issues them.
 int cycle_parity_after(const mg_hierarchy *H, int order, int parity) {
     const mg_options &o = H->opt;
-    const int passes = (H->nlev[order] == 1) ? o.n_coarse_sweeps : (o.n_pre + o.n_post);
-    return parity ^ (passes & 1);
+    int flips;
+    if (H->nlev[order] == 1) flips = pass_launches(H, o.n_coarse_sweeps);
+    else if (o.n_post == 0) flips = pass_launches(H, o.n_pre);
+    else if (o.fuse_passes && o.n_post >= 2) flips = pass_launches(H, o.n_pre) + 1 + pass_launches(H, o.n_post - 2);
+    else flips = pass_launches(H, o.n_pre) + 1 + pass_launches(H, o.n_post - 1);
+    return parity ^ (flips & 1);
 }
 
 void run_cycle_kernels(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out, bool decide) {
@@ -872,8 +902,14 @@ mg_status mg_smooth(mg_hierarchy *H, int32_t level, int32_t order, double *x_dev
         zero_level_x(H, level);
         launch_copy_masked(L, level, od, x_dev, L.x[0], H->stream);
         int c = 0;
-        for (int p = 0; p < passes; p++) {
-            launch_rbgs(L, level, od, L.x[c], L.x[c ^ 1], f_dev, H->stream);
+        for (int p = 0; p < passes;) {
+            if (H->opt.fuse_passes && passes - p >= 2) {
+                launch_rbgs2(L, level, od, L.x[c], L.x[c ^ 1], f_dev, H->stream);
+                p += 2;
+            } else {
+                launch_rbgs(L, level, od, L.x[c], L.x[c ^ 1], f_dev, H->stream);
+                p += 1;
+            }
             c ^= 1;
         }
         HIPCHK(hipMemcpyAsync(x_dev, L.x[c], L.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
@@ -979,7 +1015,10 @@ mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches) {
     return guarded([&]() {
         Level &L0 = H->lev[0];
         const OrderData &od0 = odata(H, 0, order);
-        for (int p = 0; p < launches; p++) launch_rbgs(L0, 0, od0, L0.x[p & 1], L0.x[(p & 1) ^ 1], L0.f, H->stream);
+        for (int p = 0; p < launches; p++) {
+            if (H->opt.fuse_passes) launch_rbgs2(L0, 0, od0, L0.x[p & 1], L0.x[(p & 1) ^ 1], L0.f, H->stream);
+            else launch_rbgs(L0, 0, od0, L0.x[p & 1], L0.x[(p & 1) ^ 1], L0.f, H->stream);
+        }
         if (launches & 1)
             HIPCHK(hipMemcpyAsync(L0.x[0], L0.x[1], L0.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
         return MG_OK;

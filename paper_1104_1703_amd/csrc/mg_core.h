@@ -27,6 +27,7 @@ constexpr int item_depth(int level) {
     return level == 0 ? SEG_TILES_FINE * TZ : level == 1 ? SEGZ_COARSE1 : SEGZ_COARSE;
 }
 constexpr int item_planes(int level) { return item_depth(level) + 4; }
+constexpr int item_planes2(int level) { return item_depth(level) + 8; }  // fused pairs of passes
 
 // Stop test of the solve loop evaluated on the device by the norm's final
 // sum (the same FP64 comparisons as the host's): halt when sqrt(sum) <= thresh,
@@ -43,6 +44,7 @@ struct OrderData {
     int *tiles = nullptr;  // active tile ids (device)
     Seg *segs = nullptr;   // smoother work items (device)
     unsigned long long *pmask = nullptr;  // per item and plane activity masks (device)
+    unsigned long long *pmask2 = nullptr; // the same for fused pairs of passes (4-cell halo; fuse_passes)
     int ntiles = 0, nsegs = 0;
     int64_t nact = 0;
 };
@@ -141,9 +143,10 @@ void launch_code0(const Level &L, unsigned long long *nact, hipStream_t s);
 void launch_diag(const Level &L, int level, int order, double *d, unsigned long long *nact, hipStream_t s);
 void launch_tile_flags(const Level &L, int level, int order, uint8_t *flags, hipStream_t s);
 void launch_to_float(const double *a, float *b, size_t n, hipStream_t s);
-// Activity masks of the smoother work items of `od` (npl planes per item).
+// Activity masks of the smoother work items of `od` (npl planes per item)
+// for an xy halo of 2 (single passes) or 4 (fused pairs of passes) cells.
 void launch_item_masks(const Level &L, int level, int order, const OrderData &od, int npl, unsigned long long *pm,
-                       hipStream_t s);
+                       hipStream_t s, int halo = 2);
 
 // -------- smoother (smooth.hip) --------
 // One red-black pass over the segments of `od`; xin == nullptr reads zero.
@@ -158,6 +161,17 @@ void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const L
                          const double *xin, double *xout, const double *f, hipStream_t s);
 void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const Level &C, const float *xc,
                            const float *xin, float *xout, const float *f, hipStream_t s);
+// Two passes in one launch (fused; od.pmask2 must exist): the same result as
+// two launch_rbgs calls xin -> tmp -> xout, bit for bit.
+void launch_rbgs2(const Level &L, int level, const OrderData &od, const double *xin, double *xout, const double *f,
+                  hipStream_t s);
+void launch_rbgs2_32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
+                     hipStream_t s);
+// The prolongation pass and the pass after it in one launch (finest level).
+void launch_rbgs2_prolong(const Level &L, const OrderData &od, const Level &C, const double *xc, const double *xin,
+                          double *xout, const double *f, hipStream_t s);
+void launch_rbgs2_prolong32(const Level &L, const OrderData &od, const Level &C, const float *xc, const float *xin,
+                            float *xout, const float *f, hipStream_t s);
 
 // -------- small levels in one workgroup (coarse.hip) --------
 size_t small_lds_bytes(const mg_hierarchy *H, int order, int ls, bool f32);

@@ -144,26 +144,34 @@ __global__ void k_tile_flags(const int32_t *__restrict__ cnt, int nx, int ny, in
 
 // One block per smoother work item: its activity masks (one word per plane
 // z0-2 .. z0+npl-3; bit layout of item_mask_bit).
+// Activity masks of smoother work items with an xy halo of HH cells (2: one
+// pass per launch, smooth_core.h; 4: two fused passes, smooth2_core.h): per
+// item and plane z0-HH .. z0-HH+npl-1, bit 4 v + g for row y0-HH+v and the
+// 16-cell granule g of the row (granule boundaries at x0-16, x0, x0+16,
+// x0+32); planes outside the box or past z1+HH-1 get no bits.
+template <int HH>
 __global__ void k_item_masks(const int32_t *__restrict__ cnt, int nx, int ny, int nz, int level, int order,
                              const Seg *__restrict__ segs, int npl, unsigned long long *__restrict__ pm) {
-    __shared__ unsigned rowbits[rb::MAXPL * rb::PY];
+    constexpr int RY = TY + 2 * HH, RX = TX + 2 * HH;
+    static_assert(4 * RY <= 64, "one 64-bit word per plane");
+    __shared__ unsigned rowbits[(SEG_TILES_FINE * TZ + 2 * HH) * RY];
     const Seg sg = segs[blockIdx.x];
-    for (int r = threadIdx.x; r < npl * rb::PY; r += blockDim.x) {
-        const int pi = r / rb::PY, v = r % rb::PY;
-        const int k = sg.z0 - 2 + pi, y = sg.y0 - 2 + v;
+    for (int r = threadIdx.x; r < npl * RY; r += blockDim.x) {
+        const int pi = r / RY, v = r % RY;
+        const int k = sg.z0 - HH + pi, y = sg.y0 - HH + v;
         unsigned bits = 0;
-        if (k >= 0 && k < nz && k <= sg.z1 + 1 && y >= 0 && y < ny)
-            for (int u = 0; u < rb::PX; u++) {
-                const int x = sg.x0 - 2 + u;
+        if (k >= 0 && k < nz && k <= sg.z1 + HH - 1 && y >= 0 && y < ny)
+            for (int u = 0; u < RX; u++) {
+                const int x = sg.x0 - HH + u;
                 if (x >= 0 && x < nx && is_active(cnt[((size_t)k * ny + y) * nx + x], level, order))
-                    bits |= 1u << (item_mask_bit(u, v) - 4 * v);
+                    bits |= 1u << ((u + 16 - HH) >> 4);
             }
         rowbits[r] = bits;
     }
     __syncthreads();
     for (int pi = threadIdx.x; pi < npl; pi += blockDim.x) {
         unsigned long long w = 0;
-        for (int v = 0; v < rb::PY; v++) w |= (unsigned long long)rowbits[pi * rb::PY + v] << (4 * v);
+        for (int v = 0; v < RY; v++) w |= (unsigned long long)rowbits[pi * RY + v] << (4 * v);
         pm[(size_t)blockIdx.x * npl + pi] = w;
     }
 }
@@ -211,9 +219,12 @@ void launch_tile_flags(const Level &L, int level, int order, uint8_t *flags, hip
 }
 
 void launch_item_masks(const Level &L, int level, int order, const OrderData &od, int npl, unsigned long long *pm,
-                       hipStream_t s) {
+                       hipStream_t s, int halo) {
     if (od.nsegs == 0) return;
-    k_item_masks<<<od.nsegs, 256, 0, s>>>(L.cnt, L.nx, L.ny, L.nz, level, order, od.segs, npl, pm);
+    if (halo == 4)
+        k_item_masks<4><<<od.nsegs, 256, 0, s>>>(L.cnt, L.nx, L.ny, L.nz, level, order, od.segs, npl, pm);
+    else
+        k_item_masks<2><<<od.nsegs, 256, 0, s>>>(L.cnt, L.nx, L.ny, L.nz, level, order, od.segs, npl, pm);
 }
 
 void launch_to_float(const double *a, float *b, size_t n, hipStream_t s) {

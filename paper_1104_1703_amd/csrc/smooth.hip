@@ -23,7 +23,7 @@
 // stored.  Net HBM traffic per pass: one read of x, f and the code/diagonal
 // and one write of x, on granules holding active cells.
 #include "mg_core.h"
-#include "smooth_core.h"
+#include "smooth2_core.h"
 
 namespace mg {
 
@@ -44,6 +44,22 @@ __global__ __launch_bounds__(NT, 5) void k_rbgs(const T *__restrict__ xin, T *__
     if (item >= nsegs || (halt && *halt)) return;
     rbgs_item<T, FINE, SEGZ, PRO>(lds, xin, xout, f, code, dco, nx, ny, nz, h2, segs[item],
                                   pm + (size_t)item * (SEGZ + 4), xc, cnx, cny, cnz);
+}
+
+// Two passes per launch (smooth2_core.h): LDS allows two FP64 blocks per CU.
+template <typename T, bool FINE, int SEGZ, bool PRO = false>
+__global__ __launch_bounds__(NT, 2) void k_rbgs2(const T *__restrict__ xin, T *__restrict__ xout,
+                                               const T *__restrict__ f, const uint8_t *__restrict__ code,
+                                               const T *__restrict__ dco, int nx, int ny, int nz, T h2,
+                                               const Seg *__restrict__ segs, const unsigned long long *__restrict__ pm,
+                                               int nsegs, const int *__restrict__ halt,
+                                               const T *__restrict__ xc = nullptr, int cnx = 0, int cny = 0,
+                                               int cnz = 0) {
+    __shared__ rb2::Lds<T, FINE, PRO> lds;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= nsegs || (halt && *halt)) return;
+    rb2::rbgs2_item<T, FINE, SEGZ, PRO>(lds, xin, xout, f, code, dco, nx, ny, nz, h2, segs[item],
+                                        pm + (size_t)item * (SEGZ + 2 * rb2::H), xc, cnx, cny, cnz);
 }
 
 inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
@@ -102,6 +118,51 @@ void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const
             C.nz);
     else
         launch_coarse<float, true>(item_depth(level), xin, xout, f, od.d32, L, od, h2, s, xc, &C);
+}
+
+template <typename T>
+void launch_fused(const Level &L, int level, const OrderData &od, const T *xin, T *xout, const T *f, const T *d,
+                  T h2, hipStream_t s) {
+    if (od.nsegs == 0) return;
+    const unsigned g = grid8(od.nsegs);
+    if (level == 0)
+        k_rbgs2<T, true, SEG_TILES_FINE * TZ><<<g, NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
+                                                               od.segs, od.pmask2, od.nsegs, L.halt);
+    else if (item_depth(level) == 8)
+        k_rbgs2<T, false, 8><<<g, NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs, od.pmask2,
+                                              od.nsegs, L.halt);
+    else if (item_depth(level) == 4)
+        k_rbgs2<T, false, 4><<<g, NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs, od.pmask2,
+                                              od.nsegs, L.halt);
+    else
+        k_rbgs2<T, false, 2><<<g, NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs, od.pmask2,
+                                              od.nsegs, L.halt);
+}
+
+void launch_rbgs2(const Level &L, int level, const OrderData &od, const double *xin, double *xout, const double *f,
+                  hipStream_t s) {
+    launch_fused<double>(L, level, od, xin, xout, f, od.d, L.h * L.h, s);
+}
+
+void launch_rbgs2_32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
+                     hipStream_t s) {
+    launch_fused<float>(L, level, od, xin, xout, f, od.d32, (float)(L.h * L.h), s);
+}
+
+void launch_rbgs2_prolong(const Level &L, const OrderData &od, const Level &C, const double *xc, const double *xin,
+                          double *xout, const double *f, hipStream_t s) {
+    if (od.nsegs == 0) return;
+    k_rbgs2<double, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
+        xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, L.h * L.h, od.segs, od.pmask2, od.nsegs, L.halt, xc, C.nx,
+        C.ny, C.nz);
+}
+
+void launch_rbgs2_prolong32(const Level &L, const OrderData &od, const Level &C, const float *xc, const float *xin,
+                            float *xout, const float *f, hipStream_t s) {
+    if (od.nsegs == 0) return;
+    k_rbgs2<float, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
+        xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, (float)(L.h * L.h), od.segs, od.pmask2, od.nsegs, L.halt,
+        xc, C.nx, C.ny, C.nz);
 }
 
 void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,

@@ -32,7 +32,7 @@ class Options(C.Structure):
     _fields_ = [("n_pre", C.c_int32), ("n_post", C.c_int32), ("n_cycles", C.c_int32), ("n_coarse_sweeps", C.c_int32),
                 ("min_coarse_dim", C.c_int32), ("max_cycles", C.c_int32), ("precision", C.c_int32),
                 ("bc_order", C.c_int32), ("eta", C.c_double), ("first_order_hold", C.c_int32),
-                ("use_graph", C.c_int32), ("allocator", Allocator)]
+                ("use_graph", C.c_int32), ("fuse_passes", C.c_int32), ("allocator", Allocator)]
 
 
 class SolveInfo(C.Structure):

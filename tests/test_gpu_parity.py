@@ -482,3 +482,48 @@ def test_batch_per_patch_engine_matches_oracle(mg, opts):
         assert info["cycles"] == rinfo["cycles"] and info["switched_at"] == rinfo["switched_at"], p.name
         assert relerr(host(x), ref, p.mask == 1) <= TOL, p.name
     B.close()
+
+
+# ---------------------------------------------------------------- fused pairs of passes
+@pytest.mark.parametrize("name", ["sphere32", "holes64", "rand_ragged", "rand_dirichlet", "patch_odd"])
+def test_fused_passes_equal_single_passes_each_level(mg, name):
+    """Two passes in one march (4-cell halo, four half-sweeps one plane apart)
+    give what two single passes give, bit for bit, on every level and order,
+    for 2, 3 and 4 passes (the odd one left as a single pass)."""
+    p, H1, orc = _pair(name, mg)
+    H2 = mg.Hierarchy(dev(p.mask), p.h, fuse_passes=1)
+    for order in (1, 2):
+        for l in range(orc.nlevels(order)):
+            act = orc.active(l, order).astype(bool)
+            x = dev(_rand_on(act, 30 + l))
+            f = dev(_rand_on(act, 40 + l) * (1.0 + l))
+            for passes in (2, 3, 4):
+                a = host(H1.smooth(l, x, f, passes=passes, order=order))
+                b = host(H2.smooth(l, x, f, passes=passes, order=order))
+                assert np.array_equal(a, b), (name, order, l, passes)
+    H1.close()
+    H2.close()
+
+
+@pytest.mark.parametrize("name", ["sphere32", "holes64", "rand_dirichlet", "porous64", "patch_odd"])
+@pytest.mark.parametrize("opts", [dict(), dict(precision="mixed"), dict(n_pre=3, n_post=3), dict(n_pre=1, n_post=2),
+                                  dict(n_cycles=2), dict(n_post=0)])
+def test_fused_solve_equals_unfused_solve(mg, name, opts):
+    """Whole solves with fused pairs of passes (the finest prolongation pass
+    fused with the pass after it) equal the unfused solves bit for bit:
+    cycles, switch, norm history and solution."""
+    p = PROBLEMS[name]()
+    _print_case(name, p)
+    rho = dev(p.rho)
+    d = None if p.dirichlet is None else dev(p.dirichlet)
+    out = []
+    for fuse in (0, 1):
+        H = mg.Hierarchy(dev(p.mask), p.h, fuse_passes=fuse, **opts)
+        phi, info = H.solve(rho, None, d, tol=1e-10)
+        out.append((host(phi), info))
+        H.close()
+    (a, ia), (b, ib) = out
+    assert ia["status"] == ib["status"] == 0, (name, opts)
+    assert (ia["cycles"], ia["switched_at"], ia["order_used"]) == (ib["cycles"], ib["switched_at"], ib["order_used"])
+    assert ia["history"] == ib["history"]
+    assert np.array_equal(a, b)
