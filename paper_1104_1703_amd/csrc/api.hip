@@ -238,6 +238,11 @@ void create(mg_hierarchy *H, const int8_t *mask, int nx, int ny, int nz, double 
                 H->ls[o] = l;
                 break;
             }
+        // a deepest level above that size (an edge that stops halving early)
+        // still goes to the workgroup when it fits its LDS: its n_coarse
+        // sweeps are then one launch instead of one launch each
+        const int last = H->nlev[o] - 1;
+        if (H->ls[o] < 0 && last >= 1 && small_lds_bytes(H, o, last, false) <= (size_t)small_lim) H->ls[o] = last;
     }
     H->part_cap = std::max(1, lev[0].od[2].ntiles * TZ);
     H->part = alloc_n<double>(H, (size_t)H->part_cap);
