@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--learned-stride", type=int, default=4, help="U-Net runs on the 1/stride grid")
     ap.add_argument("--batch-patches", type=int, default=512,
                     help="patches of the batched workload timed beside the main line (0: skip)")
+    ap.add_argument("--large-n", type=int, default=512,
+                    help="edge of the porous mixed-precision workload timed beside the main line (0: skip)")
     ap.add_argument("--weights", default=None, help="U-Net weights (default: the package's trained file)")
     ap.add_argument("--smoother-launches", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -168,6 +170,62 @@ def unet_conv_roofline():
                                        f"{n} x {d}^3 voxels)",
             "achieved": round(tf, 1), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_BF16_TFLOPS, 4),
             "traffic": None, "avg_launch_us": round(ms * 1e3, 2), "algorithmic_flops_per_launch": flops}
+
+
+def large_measurement(args):
+    """The porous workload at --large-n^3 (seed 4: 4096 holes with radii
+    U[0.005, 0.02), k^-2 random-field rho, Dirichlet 0): time to 1e-10 from a
+    zero guess in FP64 and in mixed precision (median of 3 after one warm-up,
+    wall time with inputs resident), the mixed solution's largest difference
+    from the FP64 one, and the finest smoother pass at this size, where the
+    working set far exceeds the 256 MB MALL."""
+    import torch
+
+    from paper_1104_1703_amd import gen, mg
+    t0 = time.perf_counter()
+    p = gen.porous_problem(args.large_n, seed=4)
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    mask = torch.from_numpy(p.mask).to(dev)
+    rho = torch.from_numpy(p.rho).to(dev)
+    phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
+    res, phi64 = {}, None
+    for prec in ("fp64", "mixed"):
+        H = mg.Hierarchy(mask, p.h, precision=prec)
+        walls, info = [], None
+        for rep in range(4):
+            phi.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = H.solve(rho, phi, None, tol=args.tol)[1]
+            torch.cuda.synchronize()
+            if rep:
+                walls.append(time.perf_counter() - t0)
+        r = {"ms": round(float(np.median(walls)) * 1e3, 3), "cycles": info["cycles"],
+             "switched_at": info["switched_at"], "final_rel_residual": info["r_final"] / info["r_ref"]}
+        if prec == "fp64":
+            n_act = H.n_active(0)
+            H.time_smoother(4)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(H.stream)
+            H.time_smoother(20)
+            e1.record(H.stream)
+            e1.synchronize()
+            us = e0.elapsed_time(e1) / 20 * 1e3
+            gbs = SMOOTH_BYTES_FP64 * n_act / (us * 1e-6) / 1e9
+            r["smoother_us"] = round(us, 2)
+            r["smoother_algorithmic_gbs"] = round(gbs, 1)
+            r["smoother_frac"] = round(gbs / PEAK_HBM_GBS, 4)
+            phi64 = phi.clone()
+        else:
+            r["max_rel_diff_vs_fp64_solution"] = float((phi - phi64).abs().max() / phi64.abs().max())
+        res[prec] = r
+        H.close()
+    res["mixed"]["speedup_vs_fp64"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
+    return {"workload": f"porous{args.large_n}: {args.large_n}^3 box minus 4096 seeded spheres (seed 4), "
+                        f"{p.n_active} active, k^-2 random-field rho, Dirichlet 0, zero guess, tol {args.tol:g}",
+            **res, "generate_s": round(t_gen, 1)}
 
 
 def profile_batch(args):
@@ -394,6 +452,8 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per,
         },
     }
+    if args.large_n > 0:
+        out["large"] = large_measurement(args)
     if args.batch_patches > 0:
         out["batch"] = batch_measurement(args)
     try:

@@ -328,6 +328,30 @@ def test_full_size_holes256_two_cycles_and_converged_residual(mg):
     H.close()
 
 
+def test_full_size_porous512_mixed_and_fp64(mg):
+    """The 512^3 porous workload (4096 holes, most below the coarse cell size;
+    k^-2 random-field rho) solved to 1e-10 in mixed precision and in FP64:
+    both converged solutions pass the oracle's own FP64 residual test, and
+    the mixed solution agrees with the FP64 one to 1e-9."""
+    p = gen.porous_problem(512, seed=4)
+    _print_case("porous512", p)
+    act = p.mask == 1
+    orc = O.Oracle(p.mask, p.h)
+    out = {}
+    for prec in ("mixed", "fp64"):
+        H = mg.Hierarchy(dev(p.mask), p.h, precision=prec)
+        phi, info = H.solve(dev(p.rho), tol=1e-10)
+        print(f"[porous512] {prec}: status {info['status']} cycles {info['cycles']} "
+              f"switched at {info['switched_at']} ms {info['ms']:.1f}", flush=True)
+        assert info["status"] == 0
+        got = host(phi)
+        H.close()
+        rr = orc.residual_norm(p.rho, np.where(act, got, 0.0))
+        assert rr <= 1e-10 * info["r_ref"] * (1 + 1e-6), (prec, rr / info["r_ref"])
+        out[prec] = got
+    assert relerr(out["mixed"], out["fp64"], act) <= 1e-9
+
+
 # ---------------------------------------------------------------- mixed precision
 @pytest.mark.parametrize("name", ["sphere32", "holes64", "porous64", "rand_dirichlet"])
 def test_mixed_precision_matches_converged_oracle(mg, name):
