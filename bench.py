@@ -318,8 +318,8 @@ def main():
     if args.profile_batch:
         return profile_batch(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
-              "(domain decomposition is described, not implemented).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(its domain decomposition over GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
