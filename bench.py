@@ -79,6 +79,9 @@ def parse():
                     help="counter runs: build the 256^3 hierarchy, launch only the finest smoother N times, exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="counter runs: 4 plain device copies of MIB MiB (known bytes), exit")
+    ap.add_argument("--schedules", type=int, default=0, metavar="N",
+                    help="study: the sphere at N^3 to 1e-10 with N_cycles 1, 2, 3 in each boundary order "
+                         "(cycles, mean rate, ms), exit")
     ap.add_argument("--profile-batch", type=int, default=0, metavar="N",
                     help="kernel runs: N batch solves of the --batch-patches workload after one warm-up, exit")
     ap.add_argument("--profile-unet", type=int, default=0, metavar="N",
@@ -228,6 +231,40 @@ def large_measurement(args):
             **res, "generate_s": round(t_gen, 1)}
 
 
+def schedules(args):
+    """Multigrid schedules on the sphere (the domain where second order
+    converges): N_cycles = 1 (V), 2 (W) and 3 in first and second order, each
+    to 1e-10 from a zero guess (median of 3 solves after one warm-up)."""
+    import torch
+
+    from paper_1104_1703_amd import gen, mg
+    p = gen.sphere_problem(args.schedules)
+    dev = torch.device("cuda:0")
+    mask = torch.from_numpy(p.mask).to(dev)
+    rho = torch.from_numpy(p.rho).to(dev)
+    phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
+    rows = []
+    for nc in (1, 2, 3):
+        for bo in ("second", "first"):
+            H = mg.Hierarchy(mask, p.h, n_cycles=nc, bc_order=bo)
+            walls, info = [], None
+            for rep in range(4):
+                phi.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = H.solve(rho, phi, None, tol=args.tol)[1]
+                torch.cuda.synchronize()
+                if rep:
+                    walls.append(time.perf_counter() - t0)
+            h = info["history"]
+            rows.append({"n_cycles": nc, "order": bo, "cycles": info["cycles"],
+                         "mean_rate": (h[-1] / h[0]) ** (1.0 / max(1, info["cycles"])),
+                         "ms": round(float(np.median(walls)) * 1e3, 3)})
+            H.close()
+    print(json.dumps({"mode": "schedules", "workload": f"sphere{args.schedules}: R = 0.4 Dirichlet 0, "
+                      f"rho = 1 inside r = 0.2, tol {args.tol:g}", "rows": rows}), flush=True)
+
+
 def profile_batch(args):
     """Batch solves alone, for kernel-trace runs: one warm-up, then N solves."""
     r = batch_measurement(args, solves=args.profile_batch)
@@ -317,6 +354,8 @@ def main():
         return profile_unet(args)
     if args.profile_batch:
         return profile_batch(args)
+    if args.schedules:
+        return schedules(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
               "(its domain decomposition over GPUs is not implemented).", file=sys.stderr)
