@@ -82,6 +82,9 @@ def parse():
     ap.add_argument("--schedules", type=int, default=0, metavar="N",
                     help="study: the sphere at N^3 to 1e-10 with N_cycles 1, 2, 3 in each boundary order "
                          "(cycles, mean rate, ms), exit")
+    ap.add_argument("--amr", default="", metavar="N,N,...",
+                    help="study: one-way nested levels (3 refinements) of the ln profile at these base sizes: "
+                         "errors, orders and time, exit")
     ap.add_argument("--profile-batch", type=int, default=0, metavar="N",
                     help="kernel runs: N batch solves of the --batch-patches workload after one warm-up, exit")
     ap.add_argument("--profile-unet", type=int, default=0, metavar="N",
@@ -231,6 +234,28 @@ def large_measurement(args):
             **res, "generate_s": round(t_gen, 1)}
 
 
+def amr_study(args):
+    """One-way nested levels (the accuracy tests of Sec. 5.1 in 3D): the ln
+    profile (r0 = 0.1) on a base n^3 box plus 3 refined n^3 levels around the
+    centre, each solved to 1e-12 with Dirichlet values interpolated from the
+    level above; composite-grid errors of the potential and of the 5-point
+    gradient, their orders between successive n, and the GPU time of the whole
+    chain (one warm-up chain first)."""
+    from paper_1104_1703_amd import amr
+    ns = [int(v) for v in args.amr.split(",") if v]
+    amr.solve_nested(ns[0], 3)  # warm-up
+    rows = []
+    for n in ns:
+        levels, ms = amr.solve_nested(n, 3)
+        e = amr.composite_errors(levels)
+        rows.append({"n": n, "finest_h": levels[-1].h, "ms": round(ms, 3),
+                     "cycles": [L.info["cycles"] for L in levels], **e})
+    for a, b in zip(rows, rows[1:]):
+        b["orders"] = {k: round(float(np.log2(a[k] / b[k])), 3) for k in ("phi_linf", "phi_l2", "grad_linf", "grad_l2")}
+    print(json.dumps({"mode": "amr", "workload": "ln profile r0 = 0.1, base n^3 box + 3 nested n^3 levels "
+                      "(central 1/2, 1/4, 1/8), tol 1e-12", "rows": rows}), flush=True)
+
+
 def schedules(args):
     """Multigrid schedules on the sphere (the domain where second order
     converges): N_cycles = 1 (V), 2 (W) and 3 in first and second order, each
@@ -356,6 +381,8 @@ def main():
         return profile_batch(args)
     if args.schedules:
         return schedules(args)
+    if args.amr:
+        return amr_study(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
               "(its domain decomposition over GPUs is not implemented).", file=sys.stderr)

@@ -253,6 +253,49 @@ int32_t mg_batch_phases(const mg_batch *B, int32_t order);
  * lockstep cycles.  Both give the same results. */
 mg_status mg_batch_set_engine(mg_batch *B, int32_t phased);
 
+/* ---------------- one-way nested levels (AMR) ----------------
+ * A refined level is solved after the next coarser one (Sec. 3, one-way
+ * interface; Sec. 5.1): its Dirichlet values are the coarser potential
+ * interpolated linearly to its boundary faces, and the gradient of the
+ * potential takes the values it needs beyond the level from the coarser level
+ * the same way (Fig. "force-ramses").  A level is a box array (nz, ny, nx) of
+ * cells of width h whose lower corner is at origin = (x0, y0, z0) (host, 3
+ * doubles); cell (i, j, k) is centred at origin + ((i, j, k) + 1/2) h.
+ * Linear interpolation between cell centres is trilinear.  Both calls only
+ * enqueue on `stream` (void* hipStream_t, NULL = default).
+ */
+
+/*
+ * Dirichlet field of a refined patch whose outer layer is its boundary and
+ * whose interior is active, in the solver's cell-centred form (the face value
+ * between active i and inactive j is (B_i + B_j) / 2): interior cells get the
+ * interpolated coarser potential at their centre, a frame cell sharing a face
+ * with one interior cell gets 2 g - B_i (g = the interpolated potential at
+ * that face's centre), edge and corner frame cells 0.
+ *   phi_c_dev: coarser level (cnz, cny, cnx), cell width hc, corner origin_c.
+ *   b_dev:     output (nz, ny, nx), cell width hf, corner origin_f.
+ * MG_ERR_ARG for null pointers, dims below 3, h <= 0, or when the coarser
+ * array does not hold the interpolation stencil of every point used.
+ */
+mg_status mg_amr_dirichlet(const double *phi_c_dev, int32_t cnx, int32_t cny, int32_t cnz, double hc,
+                           const double *origin_c, int32_t nx, int32_t ny, int32_t nz, double hf,
+                           const double *origin_f, double *b_dev, void *stream);
+
+/*
+ * Gradient of phi on the active cells (mask == +1) of a level by the 5-point
+ * difference (Sec. 5.1): d/dx phi = (4/3)(phi[i+1] - phi[i-1])/(2h)
+ * - (1/3)(phi[i+2] - phi[i-2])/(4h), likewise in y and z.  A value at a cell
+ * that is not an active cell of the level comes from the coarser level
+ * (phi_c_dev, may be NULL) at that cell's centre; with no coarser level, from
+ * bnd_dev (the level's Dirichlet field, may be NULL) inside the array, NaN
+ * beyond.  grad_dev: 3 * nz * ny * nx doubles, components x, y, z one after
+ * the other; inactive cells get 0.  MG_ERR_ARG as above, or when the coarser
+ * array does not cover the level plus a 2-cell margin.
+ */
+mg_status mg_amr_grad5(const double *phi_dev, const int8_t *mask_dev, int32_t nx, int32_t ny, int32_t nz, double h,
+                       const double *origin, const double *phi_c_dev, int32_t cnx, int32_t cny, int32_t cnz,
+                       double hc, const double *origin_c, const double *bnd_dev, double *grad_dev, void *stream);
+
 /* ---------------- learned first guess (U-Net) ----------------
  * The iteration of Sec. 2 converges from any first guess, and the paper's
  * convergence is insensitive to it (Sec. 2, Sec. 6); these calls produce a

@@ -32,6 +32,10 @@ __all__ = [
     "patch_problems",
     "random_small_problem",
     "training_sample",
+    "nested_levels",
+    "level_centres",
+    "frame_mask",
+    "ln_profile",
 ]
 
 
@@ -263,3 +267,50 @@ def training_sample(n: int = 64, seed: int = 10000) -> Problem:
     """One learned-guess training sample drawn like the 256^3 holes workload
     (same physical radii and widths), at ``n^3``."""
     return holes_problem(n=n, seed=seed)
+
+
+# ------------------------------------------------------- nested levels (AMR)
+def nested_levels(n: int, depth: int):
+    """Geometry of nested refined levels around the box centre, standing in
+    for the paper's quasi-Lagrangian AMR of a centrally concentrated profile
+    (Sec. 5.1): level 0 is the unit box as an n^3 array, level k an n^3 array
+    of cells 1/(n 2^k) covering the central 1/2^k of the box.  Each level's
+    outer layer of cells is its boundary.  Returns [(shape, h, origin)] with
+    origin = (x0, y0, z0) the lower corner of the array."""
+    levels = []
+    for k in range(depth + 1):
+        h = 1.0 / (n * 2 ** k)
+        o = 0.5 - 0.5 * n * h
+        levels.append(((n, n, n), h, (o, o, o)))
+    return levels
+
+
+def level_centres(shape, h: float, origin) -> np.ndarray:
+    """Cell-centre coordinates (nz, ny, nx, 3) as (x, y, z) of an array of
+    cells of width h whose lower corner is at origin."""
+    nz, ny, nx = shape
+    x = origin[0] + (np.arange(nx) + 0.5) * h
+    y = origin[1] + (np.arange(ny) + 0.5) * h
+    z = origin[2] + (np.arange(nz) + 0.5) * h
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return np.stack([X, Y, Z], axis=-1)
+
+
+def frame_mask(shape) -> np.ndarray:
+    """All cells active except the outer layer."""
+    m = -np.ones(shape, dtype=np.int8)
+    m[1:-1, 1:-1, 1:-1] = 1
+    return m
+
+
+def ln_profile(pts: np.ndarray, r0: float = 0.1):
+    """3D analogue of the paper's accuracy-test profile (Sec. 5.1) around the
+    box centre: phi = ln((r/r0)^2 + 1), rho = Laplacian(phi) =
+    (6 r0^2 + 2 r^2) / (r^2 + r0^2)^2 and grad(phi) = 2 (x - c) / (r^2 + r0^2).
+    Returns (phi, rho, grad) at the points (..., 3)."""
+    d = pts - 0.5
+    r2 = (d ** 2).sum(-1)
+    phi = np.log(r2 / r0 ** 2 + 1.0)
+    rho = (6.0 * r0 ** 2 + 2.0 * r2) / (r2 + r0 ** 2) ** 2
+    grad = 2.0 * d / (r2 + r0 ** 2)[..., None]
+    return phi, rho, grad

@@ -79,6 +79,8 @@ SYMBOLS = [
     ("mg_batch_grid", _I, [_P]),
     ("mg_batch_phases", _I, [_P, _I]),
     ("mg_batch_set_engine", C.c_int, [_P, _I]),
+    ("mg_amr_dirichlet", C.c_int, [_P, _I, _I, _I, _D, _P, _I, _I, _I, _D, _P, _P, _P]),
+    ("mg_amr_grad5", C.c_int, [_P, _P, _I, _I, _I, _D, _P, _P, _I, _I, _I, _D, _P, _P, _P, _P]),
     # learned first guess
     ("mg_unet_create", C.c_int, [C.c_uint64, _P, _P, C.POINTER(_P)]),
     ("mg_unet_destroy", None, [_P]),
@@ -544,6 +546,41 @@ def upsample_guess(phi_c, mask, out=None):
     st = load_library().mg_upsample_guess(_ptr(phi_c), nxc, nyc, nzc, _ptr(mask), _ptr(out),
                                           C.c_void_p(torch.cuda.current_stream(phi_c.device).cuda_stream))
     _check(st, "mg_upsample_guess")
+    return out
+
+
+def _origin(o):
+    return (C.c_double * 3)(*[float(v) for v in o])
+
+
+def amr_dirichlet(phi_c, hc: float, origin_c, shape, hf: float, origin_f, out=None):
+    """Dirichlet field of a refined patch (shape, hf, corner origin_f) from
+    the coarser potential phi_c (cell width hc, corner origin_c): the
+    one-way interface values of mg_amr_dirichlet."""
+    cnz, cny, cnx = phi_c.shape
+    nz, ny, nx = shape
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=phi_c.device)
+    st = load_library().mg_amr_dirichlet(_ptr(phi_c), cnx, cny, cnz, float(hc), _origin(origin_c), nx, ny, nz,
+                                         float(hf), _origin(origin_f), _ptr(out),
+                                         C.c_void_p(torch.cuda.current_stream(phi_c.device).cuda_stream))
+    _check(st, "mg_amr_dirichlet")
+    return out
+
+
+def amr_grad5(phi, mask, h: float, origin, coarse=None, bnd=None, out=None):
+    """5-point gradient (3, nz, ny, nx) of phi on the active cells of mask;
+    coarse = (phi_c, hc, origin_c) supplies values beyond the level, else
+    bnd (the level's Dirichlet field) inside the array."""
+    nz, ny, nx = phi.shape
+    if out is None:
+        out = torch.empty((3,) + tuple(phi.shape), dtype=torch.float64, device=phi.device)
+    pc, hc, oc = coarse if coarse is not None else (None, 1.0, (0.0, 0.0, 0.0))
+    cnz, cny, cnx = pc.shape if pc is not None else (0, 0, 0)
+    st = load_library().mg_amr_grad5(_ptr(phi), _ptr(mask), nx, ny, nz, float(h), _origin(origin), _ptr(pc), cnx,
+                                     cny, cnz, float(hc), _origin(oc), _ptr(bnd), _ptr(out),
+                                     C.c_void_p(torch.cuda.current_stream(phi.device).cuda_stream))
+    _check(st, "mg_amr_grad5")
     return out
 
 
