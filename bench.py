@@ -240,7 +240,8 @@ def amr_study(args):
     centre, each solved to 1e-12 with Dirichlet values interpolated from the
     level above; composite-grid errors of the potential and of the 5-point
     gradient, their orders between successive n, and the GPU time of the whole
-    chain (one warm-up chain first)."""
+    chain (one warm-up chain first); the same from the interpolated first
+    guess on the refined levels."""
     from paper_1104_1703_amd import amr
     ns = [int(v) for v in args.amr.split(",") if v]
     amr.solve_nested(ns[0], 3)  # warm-up
@@ -248,8 +249,12 @@ def amr_study(args):
     for n in ns:
         levels, ms = amr.solve_nested(n, 3)
         e = amr.composite_errors(levels)
+        li, ms_i = amr.solve_nested(n, 3, guess="interp")
+        ei = amr.composite_errors(li)
         rows.append({"n": n, "finest_h": levels[-1].h, "ms": round(ms, 3),
-                     "cycles": [L.info["cycles"] for L in levels], **e})
+                     "cycles": [L.info["cycles"] for L in levels], **e,
+                     "interp_guess": {"ms": round(ms_i, 3), "cycles": [L.info["cycles"] for L in li],
+                                      "phi_linf": ei["phi_linf"], "grad_linf": ei["grad_linf"]}})
     for a, b in zip(rows, rows[1:]):
         b["orders"] = {k: round(float(np.log2(a[k] / b[k])), 3) for k in ("phi_linf", "phi_l2", "grad_linf", "grad_l2")}
     print(json.dumps({"mode": "amr", "workload": "ln profile r0 = 0.1, base n^3 box + 3 nested n^3 levels "

@@ -22,11 +22,15 @@ class Level:
         self.mask, self.rho, self.B, self.phi, self.grad, self.info = mask, rho, B, phi, grad, info
 
 
-def solve_nested(n: int, depth: int, r0: float = 0.1, tol: float = 1e-12, device="cuda", **options):
+def solve_nested(n: int, depth: int, r0: float = 0.1, tol: float = 1e-12, guess: str = "zero", device="cuda",
+                 **options):
     """Levels 0..depth of ``gen.nested_levels(n, depth)``, each an n^3 box
     (outer layer = boundary), solved one way from the coarsest; returns the
     list of ``Level`` (device tensors) and the wall time in ms of the whole
-    chain (interface values, solves, gradients; hierarchy builds excluded)."""
+    chain (interface values, solves, gradients; hierarchy builds excluded).
+    guess = "interp" starts each refined level from the coarser solution
+    interpolated to its cell centres (the paper's multilevel first guess,
+    Sec. 5.2), which is the interior of its Dirichlet field; "zero" from 0."""
     geo = gen.nested_levels(n, depth)
     inputs = []
     for shape, h, origin in geo:
@@ -44,7 +48,8 @@ def solve_nested(n: int, depth: int, r0: float = 0.1, tol: float = 1e-12, device
         else:
             c = levels[-1]
             B = mg.amr_dirichlet(c.phi, c.h, c.origin, shape, h, origin)
-        phi, info = H.solve(rho, None, B, tol=tol)
+        phi0 = B.clone() if (k > 0 and guess == "interp") else None
+        phi, info = H.solve(rho, phi0, B, tol=tol)
         if k == 0:
             grad = mg.amr_grad5(phi, mask, h, origin, bnd=B)
         else:
