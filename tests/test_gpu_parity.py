@@ -49,6 +49,9 @@ PROBLEMS = {
     "rand_dirichlet": lambda: gen.random_small_problem((32, 32, 32), 5, active_frac=0.8, blur=1.0),
     "porous64": lambda: gen.porous_problem(n=64, seed=4),
     "patch_odd": lambda: gen.patch_problems(count=3, seed=3)[2],
+    # 24 halves only to 6: the deepest level (6 x 32 x 32 = 6144 cells) is above the
+    # 4096-cell small-level size and runs alone in the one-workgroup kernel
+    "deep_6144": lambda: gen.random_small_problem((24, 128, 128), 9, active_frac=0.75, blur=2.0),
 }
 
 
@@ -160,7 +163,7 @@ def _solve_pair(mg, name, tol=1e-10, **opts):
     return p, H, host(phi), info, ref, rinfo
 
 
-@pytest.mark.parametrize("name", ["sphere32", "holes64", "rand_ragged", "rand_dirichlet", "patch_odd"])
+@pytest.mark.parametrize("name", ["sphere32", "holes64", "rand_ragged", "rand_dirichlet", "patch_odd", "deep_6144"])
 def test_solve_matches_oracle(mg, name):
     p, H, got, info, ref, rinfo = _solve_pair(mg, name)
     act = p.mask == 1
