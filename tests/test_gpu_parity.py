@@ -534,11 +534,13 @@ def test_fused_passes_equal_single_passes_each_level(mg, name):
 
 @pytest.mark.parametrize("name", ["sphere32", "holes64", "rand_dirichlet", "porous64", "patch_odd"])
 @pytest.mark.parametrize("opts", [dict(), dict(precision="mixed"), dict(n_pre=3, n_post=3), dict(n_pre=1, n_post=2),
-                                  dict(n_cycles=2), dict(n_post=0)])
+                                  dict(n_cycles=2), dict(n_post=0), dict(use_graph=1),
+                                  dict(use_graph=1, n_pre=3, n_post=3), dict(use_graph=1, n_pre=1, n_post=2)])
 def test_fused_solve_equals_unfused_solve(mg, name, opts):
     """Whole solves with fused pairs of passes (the finest prolongation pass
     fused with the pass after it) equal the unfused solves bit for bit:
-    cycles, switch, norm history and solution."""
+    cycles, switch, norm history and solution; with captured graphs the
+    replays track the finest buffer across cycles by the fused launch count."""
     p = PROBLEMS[name]()
     _print_case(name, p)
     rho = dev(p.rho)
