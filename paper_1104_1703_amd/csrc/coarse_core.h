@@ -1,5 +1,5 @@
 // Core of the one-workgroup multigrid call on small levels, shared by the
-// per-level path (coarse.hip) and the batched persistent kernel (batch.hip).
+// per-level path (coarse.hip) and the batched phase kernels (batch.hip).
 #pragma once
 
 #include "mg_core.h"

@@ -1,5 +1,5 @@
 // Core of the red-black smoother, shared by the per-level kernels
-// (smooth.hip) and the batched persistent kernel (batch.hip).
+// (smooth.hip) and the batched phase kernels (batch.hip).
 #pragma once
 
 #include <type_traits>

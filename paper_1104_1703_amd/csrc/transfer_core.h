@@ -1,6 +1,6 @@
 // Per-cell and per-column bodies of the residual, restriction, prolongation,
 // norm and boundary-folding kernels, shared by the per-level kernels
-// (transfer.hip) and the batched persistent kernel (batch.hip).
+// (transfer.hip) and the batched phase kernels (batch.hip).
 //
 // A block of 256 threads covers the TX x TY cross-section of one tile.  The
 // stencil bodies give each thread a short z-column and issue every load of the
