@@ -31,6 +31,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+# Algorithmic bytes of one FP64 V(2,2) cycle per active finest cell: four
+# passes of 25 B, the residual with restriction (18 B) and the prolongation
+# (18 B) on the finest level, times 8/7 for the coarser levels (each about an
+# eighth of the one above).
+VCYCLE_BYTES_FP64 = 155
 SMOOTH_BYTES_FP64 = 25.0    # per active cell per pass: x read + x write + f read (8 B each) + code (1 B)
 SMOOTH_BYTES_FP32 = 13.0
 
@@ -178,6 +183,15 @@ def unet_conv_roofline():
             "traffic": None, "avg_launch_us": round(ms * 1e3, 2), "algorithmic_flops_per_launch": flops}
 
 
+def vcycle_rate(n_act, ms_solve, cycles):
+    """Whole-cycle throughput: VCYCLE_BYTES_FP64 per active finest cell over
+    the solve's time per cycle (the fold and norm readbacks included)."""
+    us = ms_solve * 1e3 / max(1, cycles)
+    gbs = VCYCLE_BYTES_FP64 * n_act / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "algorithmic_bytes_per_cycle": VCYCLE_BYTES_FP64 * n_act, "us_per_cycle": round(us, 2),
+            "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
 def large_measurement(args):
     """The porous workload at --large-n^3 (seed 4: 4096 holes with radii
     U[0.005, 0.02), k^-2 random-field rho, Dirichlet 0): time to 1e-10 from a
@@ -223,6 +237,7 @@ def large_measurement(args):
             r["smoother_us"] = round(us, 2)
             r["smoother_algorithmic_gbs"] = round(gbs, 1)
             r["smoother_frac"] = round(gbs / PEAK_HBM_GBS, 4)
+            r["vcycle"] = vcycle_rate(n_act, r["ms"], info["cycles"])
             phi64 = phi.clone()
         else:
             r["max_rel_diff_vs_fp64_solution"] = float((phi - phi64).abs().max() / phi64.abs().max())
@@ -522,6 +537,7 @@ def main():
             "avg_launch_us": round(smooth_ms * 1e3, 3),
             "algorithmic_bytes_per_launch": bytes_per,
         },
+        "vcycle": vcycle_rate(n_act, ms_events, last["cycles"]),
     }
     if args.large_n > 0:
         out["large"] = large_measurement(args)
