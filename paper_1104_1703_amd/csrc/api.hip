@@ -267,8 +267,20 @@ struct Cur {
     int c[MAXL];
 };
 
+// The residual norm of a cycle's input formed by its first finest pass
+// (launch_rbgs_norm), its final sum right after that pass (with `stop`, the
+// device stop test), and a copy of the sum to `host` followed by `ev`.
+struct InputNorm {
+    const StopTest *stop;
+    double *host;
+    hipEvent_t ev;
+};
+
 // `passes` red-black passes on level l; zero_start: the iterate starts at 0.
-void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur &cur, bool f32) {
+// in (finest level, FP64, single passes): the first pass also forms the
+// residual norm of its input.
+void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur &cur, bool f32,
+            const InputNorm *in = nullptr) {
     Level &L = H->lev[l];
     const OrderData &od = odata(H, l, order);
     if (passes == 0) {
@@ -282,7 +294,15 @@ void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur 
     for (int p = 0; p < passes;) {
         const int a = cur.c[l], b = a ^ 1;
         const bool zin = (p == 0 && zero_start);
-        if (H->opt.fuse_passes && passes - p >= 2) {
+        if (in && p == 0 && l == 0 && !f32 && !zin) {
+            launch_rbgs_norm(L, od, L.x[a], L.x[b], L.f, H->part, H->stream);
+            launch_finalize(L, H->part, od.nsegs, H->norm_dev, 0, in->stop, H->stream);
+            if (in->host) {
+                HIPCHK(hipMemcpyAsync(in->host, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
+                HIPCHK(hipEventRecord(in->ev, H->stream));
+            }
+            p += 1;
+        } else if (H->opt.fuse_passes && passes - p >= 2) {
             if (f32) launch_rbgs2_32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream);
             else launch_rbgs2(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream);
             p += 2;
@@ -304,7 +324,8 @@ int pass_launches(const mg_hierarchy *H, int passes) {
 // passes, residual and R1 restriction, N_cycles iterations of the coarse
 // correction problem from zero, P2 prolongation and correction, N_post passes.
 // The deepest level is relaxed n_coarse_sweeps times.
-void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool f32) {
+void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool f32,
+              const InputNorm *in = nullptr) {
     const mg_options &o = H->opt;
     const int last = H->nlev[order] - 1;
     Level &L = H->lev[l];
@@ -319,7 +340,7 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
         return;
     }
     Level &C = H->lev[l + 1];
-    smooth(H, l, order, o.n_pre, zero_start, cur, f32);
+    smooth(H, l, order, o.n_pre, zero_start, cur, f32, in);
     if (f32) launch_restrict32(L, C, l, order, L.x32[cur.c[l]], L.f32, C.f32, H->stream);
     else launch_restrict(L, C, l, order, L.x[cur.c[l]], L.f, C.f, H->stream);
     for (int c = 0; c < o.n_cycles; c++) mg_level(H, l + 1, order, c == 0, cur, f32);
@@ -370,8 +391,14 @@ void zero_level_x(mg_hierarchy *H, int l) {
 // from e = 0, x += e, and the FP64 residual norm that also writes the next
 // inner right-hand side.  decide: the norm's final sum also runs the stop
 // test on the device and sets the halt flag that makes every kernel of a
-// following cycle return at once.
-void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out, bool decide) {
+// following cycle return at once.  FP64 modes: NORM_AFTER as above;
+// NORM_INPUT: no norm after the cycle, its first finest pass forms the norm
+// of its input (the previous cycle's iterate) as `in` describes; NORM_NONE:
+// no norm at all.
+enum { NORM_AFTER = 0, NORM_INPUT = 1, NORM_NONE = 2 };
+
+void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out, bool decide,
+                   int mode = NORM_AFTER, const InputNorm *in = nullptr) {
     const StopTest *stop = decide ? H->stop_dev : nullptr;
     Cur cur;
     for (int l = 0; l < MAXL; l++) cur.c[l] = 0;
@@ -379,8 +406,9 @@ void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *pari
     const OrderData &od0 = odata(H, 0, order);
     if (!mixed) {
         cur.c[0] = parity;
-        mg_level(H, 0, order, false, cur, false);
-        launch_resnorm(L0, 0, od0, L0.x[cur.c[0]], L0.f, H->part, H->norm_dev, 0, H->stream, stop);
+        mg_level(H, 0, order, false, cur, false, mode == NORM_INPUT ? in : nullptr);
+        if (mode == NORM_AFTER)
+            launch_resnorm(L0, 0, od0, L0.x[cur.c[0]], L0.f, H->part, H->norm_dev, 0, H->stream, stop);
     } else {
         mg_level(H, 0, order, true, cur, true);
         // x + e goes to the other FP64 buffer (unused by the FP32 inner cycle)
@@ -390,7 +418,6 @@ void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *pari
     *parity_out = mixed ? parity ^ 1 : cur.c[0];
 }
 
-// Finest-level buffer flips of one FP64 cycle, as mg_level issues them.
 int cycle_parity_after(const mg_hierarchy *H, int order, int parity) {
     const mg_options &o = H->opt;
     int flips;
@@ -575,6 +602,57 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
     HIPCHK(hipStreamSynchronize(s));
     solve_start(H, S);
     if (S.active) set_device_stop(H, S);
+    const mg_options &o = H->opt;
+    if (!S.mixed && !o.use_graph && !o.fuse_passes && o.n_pre >= 1 && H->nlev[1] > 1 && H->nlev[2] > 1) {
+        // The norm of cycle k's iterate is formed by the first finest pass of
+        // cycle k + 1, so the host decides on it while the rest of cycle k + 1
+        // runs; a stop or an order switch halts that rest on the device (its
+        // first pass wrote the other buffer only, x_k stays intact).  The last
+        // allowed cycle's norm comes from the residual-norm march.
+        bool launched = false;  // cycle S.n + 1 is in the stream
+        int par_next = S.parity;  // buffer of the iterate of cycle S.n + 1
+        while (S.active) {
+            if (!launched) {
+                enqueue_cycle(H, S.order, S.parity, false, &par_next, false, NORM_NONE);
+                launched = true;
+            }
+            const int k = S.n + 1;
+            const int slot = 4 + (k & 1);
+            int par_after = par_next;
+            if (k + 1 <= o.max_cycles) {
+                const InputNorm in{H->stop_dev, H->norm_host + slot, H->evq[k & 1]};
+                enqueue_cycle(H, S.order, par_next, false, &par_after, true, NORM_INPUT, &in);
+            } else {
+                Level &L0 = H->lev[0];
+                launch_resnorm(L0, 0, odata(H, 0, S.order), L0.x[par_next], L0.f, H->part, H->norm_dev, 0, s,
+                               H->stop_dev);
+                HIPCHK(hipMemcpyAsync(H->norm_host + slot, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipEventRecord(H->evq[k & 1], s));
+            }
+            HIPCHK(hipEventSynchronize(H->evq[k & 1]));
+            const int order_before = S.order;
+            S.host_slot = slot;
+            solve_cycle_finish(H, S);
+            S.parity = par_next;
+            if (!S.active || S.order != order_before) {
+                // the device stop test halted the rest of cycle k + 1
+                launched = false;
+                if (S.active) {
+                    launch_set_halt(H->halt_dev, 0, s);
+                    set_device_stop(H, S);
+                }
+            } else {
+                par_next = par_after;  // cycle k + 1 is in flight
+            }
+        }
+        launch_set_halt(H->halt_dev, 0, s);
+        solve_end(H, S);
+        HIPCHK(hipEventSynchronize(H->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, H->ev0, H->ev1));
+        info->ms = ms;
+        return S.st;
+    }
     struct Flight {
         int parity_out, slot, ev;
     } fl[2];

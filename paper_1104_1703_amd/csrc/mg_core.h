@@ -154,6 +154,11 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
                  const double *f, hipStream_t s);
 void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
                    hipStream_t s);
+// A finest-level FP64 pass (xin != nullptr) that also writes the residual
+// norm partials of its input xin, one per work item, to part[0 .. od.nsegs):
+// the same values, bit for bit, as launch_resnorm's partials of xin.
+void launch_rbgs_norm(const Level &L, const OrderData &od, const double *xin, double *xout, const double *f,
+                      double *part, hipStream_t s);
 // A pass that first adds the P2 prolongation of the coarse iterate xc (level
 // level + 1, dims of C) to xin on active cells, as launch_prolong would, then
 // relaxes; xin is left unchanged.
@@ -193,6 +198,10 @@ void launch_copy_masked(const Level &L, int level, const OrderData &od, const do
 // the stop test and sets the level's halt flag.
 void launch_resnorm(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *part,
                     double *out, int slot, hipStream_t s, const StopTest *stop = nullptr);
+// The fixed-order total of n partials into out[slot], with `stop` also the
+// stop test on it (halt flag of L) -- the final step of launch_resnorm.
+void launch_finalize(const Level &L, const double *part, int n, double *out, int slot, const StopTest *stop,
+                     hipStream_t s);
 // Device flags of the solve loop (small kernels, safe inside captured graphs).
 void launch_set_halt(int *halt, int v, hipStream_t s);
 void launch_set_stop(StopTest *st, double thresh, double rprev, double eta, int check_switch, hipStream_t s);

@@ -24,6 +24,7 @@
 // and one write of x, on granules holding active cells.
 #include "mg_core.h"
 #include "smooth2_core.h"
+#include "transfer_core.h"
 
 namespace mg {
 
@@ -44,6 +45,25 @@ __global__ __launch_bounds__(NT, 5) void k_rbgs(const T *__restrict__ xin, T *__
     if (item >= nsegs || (halt && *halt)) return;
     rbgs_item<T, FINE, SEGZ, PRO>(lds, xin, xout, f, code, dco, nx, ny, nz, h2, segs[item],
                                   pm + (size_t)item * (SEGZ + 4), xc, cnx, cny, cnz);
+}
+
+// The finest pass that also forms the residual-norm partials of its input,
+// one per work item, as the residual-norm march does.
+__global__ __launch_bounds__(NT, 5) void k_rbgs_norm(const double *__restrict__ xin, double *__restrict__ xout,
+                                                   const double *__restrict__ f, const uint8_t *__restrict__ code,
+                                                   int nx, int ny, int nz, double h2, double ih2,
+                                                   const Seg *__restrict__ segs,
+                                                   const unsigned long long *__restrict__ pm, int nsegs,
+                                                   const int *__restrict__ halt, double *__restrict__ part) {
+    __shared__ RbgsLds<double, true, false> lds;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= nsegs || (halt && *halt)) return;
+    constexpr int SZ = SEG_TILES_FINE * TZ;
+    const double sq = rbgs_item<double, true, SZ, false, true>(lds, xin, xout, f, code, nullptr, nx, ny, nz, h2,
+                                                               segs[item], pm + (size_t)item * (SZ + 4), nullptr, 0,
+                                                               0, 0, ih2);
+    const double t = tr::block_sum(sq);
+    if (threadIdx.x == 0) part[item] = t;
 }
 
 // Two passes per launch (smooth2_core.h): LDS allows two FP64 blocks per CU.
@@ -94,6 +114,13 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
             xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
     else
         launch_coarse<double>(item_depth(level), xin, xout, f, od.d, L, od, h2, s);
+}
+
+void launch_rbgs_norm(const Level &L, const OrderData &od, const double *xin, double *xout, const double *f,
+                      double *part, hipStream_t s) {
+    if (od.nsegs == 0) return;
+    k_rbgs_norm<<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, L.nx, L.ny, L.nz, L.h * L.h, 1.0 / (L.h * L.h),
+                                               od.segs, od.pmask, od.nsegs, L.halt, part);
 }
 
 void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const Level &C, const double *xc,

@@ -80,13 +80,24 @@ struct RbgsLds {
 // SEGZ + 4 activity masks, or nullptr to load every in-box cell.  A plane of
 // the level must hold fewer than 2^31 bytes.  PRO: xc is the next coarser
 // level's iterate (cnx x cny x cnz); the item's x0, y0 and z0 are even.
-template <typename T, bool FINE, int SEGZ, bool PRO = false>
-__device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__restrict__ xin,
-                                          T *__restrict__ xout, const T *__restrict__ f,
-                                          const uint8_t *__restrict__ code, const T *__restrict__ dco, int nx,
-                                          int ny, int nz, T h2, const Seg sg, const unsigned long long *__restrict__ pm,
-                                          const T *__restrict__ xc = nullptr, int cnx = 0, int cny = 0, int cnz = 0) {
+// NORMIN (finest level): the pass also returns the thread's sum over the
+// item's planes of r^2, r = (L xin - f) at its own tile cell, the residual
+// of the pass's input.  A plane committed at step st is not relaxed before
+// step st + 1, so right after the step's first barrier each thread reads its
+// cell and the four in-plane neighbours there; with the two planes before
+// it in registers, the residual of the plane below is formed with the same
+// expression and plane order as the residual-norm march, so the block sums
+// are bit for bit the march's.
+template <typename T, bool FINE, int SEGZ, bool PRO = false, bool NORMIN = false>
+__device__ __forceinline__ double rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__restrict__ xin,
+                                            T *__restrict__ xout, const T *__restrict__ f,
+                                            const uint8_t *__restrict__ code, const T *__restrict__ dco, int nx,
+                                            int ny, int nz, T h2, const Seg sg,
+                                            const unsigned long long *__restrict__ pm,
+                                            const T *__restrict__ xc = nullptr, int cnx = 0, int cny = 0,
+                                            int cnz = 0, T ih2 = T(0)) {
     static_assert(SEGZ + 4 <= MAXPL, "work item longer than the mask array");
+    static_assert(!NORMIN || (FINE && !PRO), "the input residual is formed on the finest level only");
     using DT = typename RbgsLds<T, FINE, PRO>::DT;
     using Regs = PlaneRegs<T, FINE, PRO>;
     constexpr bool SLIM = Rings<T, FINE>::SLIM;
@@ -297,6 +308,12 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__r
     Regs r[PF];
 #pragma unroll
     for (int q = 0; q < PF; q++) fetch(r[q], z0 - 2 + q, q);
+    // NORMIN: own tile cell, its x at the last two positions read, the
+    // in-plane neighbour sum of the newer one, and the thread's sum of r^2
+    const int q0 = (tid / BX + 2) * PX + (tid % BX + 2);
+    const int qf = (tid / BX + 1) * QX + (tid % BX + 1);
+    T xa = T(0), xb = T(0), nb = T(0);
+    double sq = 0.0;
 #pragma unroll
     for (int st = 0; st <= NSTEP; st++) {
         const int j = st - 4;  // plane z0 + j is black-relaxed in this step
@@ -312,6 +329,23 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__r
             if (st + PF < NSTEP) fetch(r[st % PF], z0 + j + 2 + PF, st + PF);
         }
         __syncthreads();
+        if constexpr (NORMIN) {
+            if (st >= 1 && st < NSTEP) {  // position st - 2 was committed in this step
+                const T *cp = sx[xslot(st - 2)];
+                const T xn = cp[q0];
+                const T sn = (cp[q0 - 1] + cp[q0 + 1]) + (cp[q0 - PX] + cp[q0 + PX]);
+                if (st >= 3 && st - 3 < z1 - z0) {  // residual of position st - 3
+                    const T fv = sf[fslot(st - 3)][qf];
+                    const T d = T((int)sd[fslot(st - 3)][qf]);
+                    T rr = T(0);
+                    if (d != T(0)) rr = ((nb + (xa + xn)) - d * xb) * ih2 - fv;
+                    sq += (double)rr * (double)rr;
+                }
+                xa = xb;
+                xb = xn;
+                nb = sn;
+            }
+        }
         if (st == 3) {
             relax(-1, 0, 1);
             relax(0, 0, 1);
@@ -327,6 +361,7 @@ __device__ __forceinline__ void rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *__r
         if constexpr (SLIM)
             if (st >= 3 && st < NSTEP) __syncthreads();
     }
+    return sq;
 }
 
 }  // namespace rb

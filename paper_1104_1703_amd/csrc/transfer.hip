@@ -291,6 +291,11 @@ void launch_resnorm(const Level &L, int level, const OrderData &od, const double
     k_finalize<<<1, 1024, 0, s>>>(part, od.ntiles * NQ, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
 }
 
+void launch_finalize(const Level &L, const double *part, int n, double *out, int slot, const StopTest *stop,
+                     hipStream_t s) {
+    k_finalize<<<1, 1024, 0, s>>>(part, n, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
+}
+
 void launch_set_halt(int *halt, int v, hipStream_t s) { k_set_halt<<<1, 1, 0, s>>>(halt, v); }
 
 void launch_set_stop(StopTest *st, double thresh, double rprev, double eta, int check_switch, hipStream_t s) {

@@ -220,6 +220,35 @@ def test_graph_replays_match_direct_launches(mg):
     Hg.close()
 
 
+@pytest.mark.parametrize("name", ["sphere32", "holes64", "porous64", "rand_dirichlet"])
+@pytest.mark.parametrize("opts", [dict(), dict(max_cycles=5), dict(bc_order="second"), dict(bc_order="first"),
+                                  dict(n_pre=1, n_post=2), dict(n_cycles=2), dict(max_cycles=1)])
+def test_input_norm_loop_equals_trailing_norm_loop(mg, name, opts):
+    """FP64 solves with direct launches take each cycle's norm from the next
+    cycle's first finest pass (deciding while that cycle runs); with captured
+    graphs each cycle ends with the residual-norm march.  Both give the same
+    norms bit for bit, so the same cycles, switch, histories and solution,
+    through stops, order switches, the cycle cap and repeated solves."""
+    p = PROBLEMS[name]()
+    _print_case(name, p)
+    rho = dev(p.rho)
+    d = None if p.dirichlet is None else dev(p.dirichlet)
+    Hd = mg.Hierarchy(dev(p.mask), p.h, use_graph=0, **opts)
+    Hg = mg.Hierarchy(dev(p.mask), p.h, use_graph=1, **opts)
+    for _ in range(2):
+        ref, rinfo = Hg.solve(rho, None, d, tol=1e-10, check=False)
+        got, info = Hd.solve(rho, None, d, tol=1e-10, check=False)
+        assert (info["status"], info["cycles"], info["switched_at"], info["order_used"]) == \
+            (rinfo["status"], rinfo["cycles"], rinfo["switched_at"], rinfo["order_used"]), (name, opts)
+        assert info["history"] == rinfo["history"]
+        assert np.array_equal(host(got), host(ref))
+    # the halt flag is clear after the solve: an entry point still works
+    x = Hd.smooth(0, got, Hd.fold(rho, d), passes=1)
+    assert np.isfinite(host(x)).all()
+    Hd.close()
+    Hg.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_entry_points_after_a_solve(mg, precision):
     """A solve keeps one cycle in flight and lets the device stop it; the
