@@ -52,8 +52,6 @@ def interp(phi_c, hc, origin_c, pts):
     return out
 
 
-
-
 def patch_dirichlet(phi_c, hc, origin_c, shape, hf, origin_f):
     """Dirichlet field B (cell-centred, as the solver reads it: the face value
     between an active cell i and an inactive cell j is (B_i + B_j)/2) for a
@@ -135,10 +133,6 @@ def grad5(phi, active, h, origin, coarse=None, bnd=None, exact=None):
 # ------------------------------------------------------------------ study --
 # (inputs: the profile, the level geometry and masks come from the seeded
 # input module shared with the GPU path)
-
-
-
-
 
 
 def solve_nested(n, depth, r0, solve, exact_interface=False):
