@@ -136,6 +136,61 @@ __device__ __forceinline__ void smooth_wave(const Lv<T> &L, int passes) {
         }
 }
 
+// Levels with at most two cells of one colour per thread: each thread keeps
+// its cells' index, neighbour validity, diagonal and f in registers for all
+// passes of the call (the same expression as half_sweep).
+template <typename T, int NTH>
+__device__ void smooth_regs(const Lv<T> &L, int passes) {
+    const int slots = L.hx * L.ny * L.nz;
+    const int nxy = L.nx * L.ny;
+    int e[2][2];
+    unsigned nb[2][2];
+    T dg[2][2], fv[2][2];
+#pragma unroll
+    for (int col = 0; col < 2; col++)
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            e[col][u] = -1;
+            nb[col][u] = 0u;
+            dg[col][u] = T(1);
+            fv[col][u] = T(0);
+            const int s = threadIdx.x + u * NTH;
+            if (s >= slots) continue;
+            const int k = qdiv(s, L.mhy);
+            const int r = s - k * L.hx * L.ny;
+            const int j = qdiv(r, L.mh);
+            const int i = 2 * (r - j * L.hx) + ((col + j + k) & 1);
+            if (i >= L.nx) continue;
+            const int c = (k * L.ny + j) * L.nx + i;
+            const T d = L.d[c];
+            if (d == T(0)) continue;
+            e[col][u] = c;
+            dg[col][u] = d;
+            fv[col][u] = L.f[c];
+            nb[col][u] = (unsigned)(i > 0) | (unsigned)(i < L.nx - 1) << 1 | (unsigned)(j > 0) << 2 |
+                         (unsigned)(j < L.ny - 1) << 3 | (unsigned)(k > 0) << 4 | (unsigned)(k < L.nz - 1) << 5;
+        }
+    for (int p = 0; p < passes; p++)
+#pragma unroll
+        for (int col = 0; col < 2; col++) {
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int c = e[col][u];
+                if (c < 0) continue;
+                const unsigned m = nb[col][u];
+                const T *x = L.x;
+                const T xm = (m & 1u) ? x[c - 1] : T(0);
+                const T xp = (m & 2u) ? x[c + 1] : T(0);
+                const T ym = (m & 4u) ? x[c - L.nx] : T(0);
+                const T yp = (m & 8u) ? x[c + L.nx] : T(0);
+                const T zm = (m & 16u) ? x[c - nxy] : T(0);
+                const T zp = (m & 32u) ? x[c + nxy] : T(0);
+                L.x[c] = (((xm + xp) + (ym + yp) + (zm + zp)) - L.h2 * fv[col][u]) / dg[col][u];
+            }
+            __syncthreads();
+        }
+}
+
 // Red-black passes; each half-sweep visits only the cells of its colour.
 template <typename T, int NTH>
 __device__ void smooth(const Lv<T> &L, int passes) {
@@ -143,6 +198,10 @@ __device__ void smooth(const Lv<T> &L, int passes) {
     if (slots <= WAVE_SLOTS) {
         if (threadIdx.x < 64) smooth_wave(L, passes);
         __syncthreads();
+        return;
+    }
+    if (slots <= 2 * NTH) {
+        smooth_regs<T, NTH>(L, passes);
         return;
     }
     for (int p = 0; p < passes; p++)
@@ -213,6 +272,7 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
     __shared__ int s_nx[MAXS], s_ny[MAXS], s_nz[MAXS], s_off[MAXS];
     __shared__ unsigned long long s_mx[MAXS], s_mxy[MAXS], s_mh[MAXS], s_mhy[MAXS];
     __shared__ T s_h2[MAXS], s_ih2[MAXS];
+    __shared__ const T *s_d[MAXS];
     if (threadIdx.x < (unsigned)S.n) {
         const int l = threadIdx.x;
         s_nx[l] = S.nx[l];
@@ -225,6 +285,7 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
         s_mhy[l] = S.mhy[l];
         s_h2[l] = S.h2[l];
         s_ih2[l] = S.ih2[l];
+        s_d[l] = S.d[l];
     }
     __syncthreads();
     auto level = [&](int l) {
@@ -245,13 +306,37 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
         v.ih2 = s_ih2[l];
         return v;
     };
-    for (int l = 0; l < S.n; l++) {
-        const Lv<T> v = level(l);
-        const T *dg = S.d[l];
-        for (int e = threadIdx.x; e < v.n; e += NTH) {
-            v.d[e] = dg[e];
-            v.x[e] = (l == 0 && load_x) ? x0[e] : T(0);
-            if (l == 0) v.f[e] = f0[e];
+    // Copy-in: every level's cells as one flat range, U elements per thread
+    // loaded before any is stored, so that their global loads overlap.
+    auto cells = [&](int l) { return s_nx[l] * s_ny[l] * s_nz[l]; };
+    int tot = 0;
+    for (int l = 0; l < S.n; l++) tot += cells(l);
+    constexpr int U = 8;
+    for (int q0 = threadIdx.x; q0 < tot; q0 += U * NTH) {
+        T dv[U], fv[U], xv[U];
+        int lv[U], ev[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            int l = 0, e = q0 + u * NTH;
+            lv[u] = -1;
+            if (e >= tot) continue;
+            while (e >= cells(l)) {
+                e -= cells(l);
+                l++;
+            }
+            lv[u] = l;
+            ev[u] = e;
+            dv[u] = s_d[l][e];
+            fv[u] = l == 0 ? f0[e] : T(0);
+            xv[u] = (l == 0 && load_x) ? x0[e] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (lv[u] < 0) continue;
+            const Lv<T> v = level(lv[u]);
+            v.d[ev[u]] = dv[u];
+            v.x[ev[u]] = xv[u];
+            if (lv[u] == 0) v.f[ev[u]] = fv[u];
         }
     }
     __syncthreads();
