@@ -90,6 +90,9 @@ def parse():
     ap.add_argument("--amr", default="", metavar="N,N,...",
                     help="study: one-way nested levels (3 refinements) of the ln profile at these base sizes: "
                          "errors, orders and time, exit")
+    ap.add_argument("--profile-solves", type=int, default=0, metavar="N",
+                    help="counter runs: N complete FP64 solves and N mixed-precision solves of the main workload "
+                         "after one warm-up each, exit")
     ap.add_argument("--profile-batch", type=int, default=0, metavar="N",
                     help="kernel runs: N batch solves of the --batch-patches workload after one warm-up, exit")
     ap.add_argument("--profile-unet", type=int, default=0, metavar="N",
@@ -124,6 +127,32 @@ def copy_calibration(args):
     torch.cuda.synchronize()
     print(json.dumps({"mode": "copy-calibration", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
                       "copies": 4}), flush=True)
+
+
+def profile_solves(args):
+    """Whole solves of the main workload, FP64 then mixed precision, for
+    counter runs that attribute HBM traffic to every kernel of a cycle."""
+    import torch
+
+    from paper_1104_1703_amd import gen, mg
+    p = gen.holes_problem(n=args.n, seed=args.seed)
+    mask = torch.from_numpy(p.mask).cuda()
+    rho = torch.from_numpy(p.rho).cuda()
+    out = {}
+    for prec in ("fp64", "mixed"):
+        H = mg.Hierarchy(mask, p.h, precision=prec)
+        phi = torch.zeros_like(rho)
+        H.solve(rho, phi, tol=args.tol)
+        cycles = []
+        for _ in range(args.profile_solves):
+            phi.zero_()
+            _, info = H.solve(rho, phi, tol=args.tol)
+            cycles.append(info["cycles"])
+        torch.cuda.synchronize()
+        out[prec] = cycles
+        H.close()
+    print(json.dumps({"mode": "profile-solves", "solves": args.profile_solves, "cycles": out,
+                      "active_cells": int((p.mask > 0).sum())}), flush=True)
 
 
 def profile_unet(args):
@@ -399,6 +428,8 @@ def main():
         return profile_unet(args)
     if args.profile_batch:
         return profile_batch(args)
+    if args.profile_solves:
+        return profile_solves(args)
     if args.schedules:
         return schedules(args)
     if args.amr:
