@@ -7,9 +7,6 @@
 namespace mg {
 namespace small {
 
-
-constexpr int NT = 256;  // the levels are tiny: fewer waves, cheaper barriers
-
 template <typename T>
 struct SmallLevels {
     int n;                 // number of levels held (ls..last)
@@ -266,7 +263,7 @@ __device__ void prolong_from(const Lv<T> &L, const Lv<T> &C) {
 // `sm` (LDS, or global memory for levels too large for LDS); f0 is level ls's
 // right-hand side and x0 its iterate (in/out), started from zero unless
 // load_x.  Called by all NTH threads of a block.
-template <typename T, int NTH = NT>
+template <typename T, int NTH>
 __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, bool load_x) {
     // level descriptors live in LDS (dynamic indexing without private memory)
     __shared__ int s_nx[MAXS], s_ny[MAXS], s_nz[MAXS], s_off[MAXS];
