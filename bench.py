@@ -408,10 +408,17 @@ def cpu_baseline(p, repeats):
         _, info = orc.solve(p.rho, np.zeros(p.shape), None, tol=1e-10)
         times.append(time.perf_counter() - t0)
         cycles.append(info["cycles"])
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": float(np.mean(times)) * 1e3,
         "unit": "ms",
         "cores": O.num_threads(),
+        "host_cpu": f"{cpu}, {os.cpu_count()} logical CPUs visible",
         "kind": "oracle",
         "sample": f"{len(times)} complete oracle solves of the {p.shape[0]}^3 holes workload to 1e-10 "
                   f"({cycles} cycles, {sum(times):.1f} s in all); value = mean wall time per solve",
