@@ -207,8 +207,11 @@ void *mg_stream(const mg_hierarchy *H);
  * bit the result mg_solve gives it.  One multigrid cycle of all unconverged
  * patches runs as one program of launches on the batch stream, each launch
  * one phase of the cycle (a red-black pass on level l, a restriction, the
- * small levels, the norm) over the work items of every patch that reaches
- * it; the host reads all patch norms once per cycle.  Options the programs
+ * small levels) over the work items of every patch that reaches it.  A
+ * cycle's first finest pass runs ahead of the host's decisions and also
+ * forms the residual norm of its input (the norm-forming pass of mg_solve),
+ * so the host reads all patch norms once per cycle, between that pass and
+ * the rest of the cycle, and a patch that stops keeps that input.  Options the programs
  * do not cover (odd finest-level pass counts per cycle, n_post == 0, a
  * zero-pass relaxation from zero) run each patch's own captured cycle in
  * lockstep instead.  use_graph = 1 replays each program from a captured
@@ -242,8 +245,9 @@ mg_status mg_solve_batch(mg_batch *B, const double *const *rho_dev, double *cons
 void mg_destroy_batch(mg_batch *B);
 
 /* Number of patches; work items of the largest launch of the cycle programs,
- * and launches of the cycle program of boundary order `order` (1 or 2), both
- * 0 when the batch runs on the per-patch lockstep engine only. */
+ * and launches per cycle in boundary order `order` (1 or 2; the pass that
+ * forms the norm, the norm's sum and the rest of the cycle), both 0 when the
+ * batch runs on the per-patch lockstep engine only. */
 int32_t mg_batch_size(const mg_batch *B);
 int32_t mg_batch_grid(const mg_batch *B);
 int32_t mg_batch_phases(const mg_batch *B, int32_t order);

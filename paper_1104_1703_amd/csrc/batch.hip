@@ -17,6 +17,15 @@
 // skip.  The host reads all per-patch norms once per cycle and takes each
 // patch's decisions with the single-grid solve loop's own code.
 //
+// A cycle's first finest pass runs ahead of those decisions, in a program of
+// its own that serves every unconverged patch in either order (the finest
+// level is the same in both): it reads the iterate from buffer 0, writes
+// buffer 1 and forms the residual norm of its input, bit for bit the
+// norm march's (patches solved whole in one workgroup or with one level get
+// the march there instead).  After the one synchronisation a patch that
+// stops keeps buffer 0; the others run the rest of the cycle in the order
+// their decision gives.
+//
 // The programs keep the finest iterate in buffer 0 between cycles.  Options
 // they do not cover (an odd number of finest-level passes per cycle, no
 // post-smoothing, a zero-pass relaxation from a zero start) run each patch's
@@ -80,6 +89,7 @@ enum : int {
     K_FIN,    // per-patch fixed-order sum of the partials
     K_FOLD,   // Dirichlet fold and guess load of the finest level
     K_STORE,  // finest iterate back to phi
+    K_SM0N,   // red-black pass, finest level, with the residual-norm partials of its input
 };
 
 // Block -> work item; false for grid padding and for patches this program
@@ -92,24 +102,30 @@ __device__ __forceinline__ bool take(const BRef *__restrict__ refs, int count, c
     return state[r.lev / MAXL] == order;
 }
 
-template <bool FINE, int SEGZ, bool PRO>
-__global__ __launch_bounds__(rb::NT, 5) void kb_smooth(const BRef *__restrict__ refs, int count,
+// NORMIN: the pass also writes its item's partial of the residual norm of
+// its input to part[poff + position] (the single-grid norm-forming pass).
+template <bool FINE, int SEGZ, bool PRO, bool NORMIN = false>
+__global__ __launch_bounds__(rb::NT, NORMIN ? 4 : 5) void kb_smooth(const BRef *__restrict__ refs, int count,
                                                        const BLev *__restrict__ lev, const int *__restrict__ state,
-                                                       int order) {
+                                                       int order, double *__restrict__ part = nullptr, int poff = 0) {
     __shared__ rb::RbgsLds<double, FINE, PRO> lds;
     BRef r;
     if (!take(refs, count, state, order, r)) return;
     const BLev &L = lev[r.lev];
     const int idx = r.w & IDX_MASK, sel = r.w >> WBITS, a = sel & 1;
-    rb::rbgs_item<double, FINE, SEGZ, PRO>(lds, (sel & 2) ? nullptr : L.x[a], L.x[a ^ 1], L.f, L.code, L.d, L.nx,
-                                           L.ny, L.nz, L.h2, L.segs[idx], L.pm + (size_t)idx * (SEGZ + 4),
-                                           PRO ? L.cx[(sel >> 2) & 1] : nullptr, L.cnx, L.cny, L.cnz);
+    const double sq = rb::rbgs_item<double, FINE, SEGZ, PRO, NORMIN>(
+        lds, (sel & 2) ? nullptr : L.x[a], L.x[a ^ 1], L.f, L.code, L.d, L.nx, L.ny, L.nz, L.h2, L.segs[idx],
+        L.pm + (size_t)idx * (SEGZ + 4), PRO ? L.cx[(sel >> 2) & 1] : nullptr, L.cnx, L.cny, L.cnz, L.ih2);
+    if constexpr (NORMIN) {
+        const double t = tr::block_sum(sq);
+        if (threadIdx.x == 0) part[poff + rb::xcd_item(blockIdx.x, gridDim.x)] = t;
+    }
 }
 
 template <int MODE>
 __global__ __launch_bounds__(tr::NT) void kb_residual(const BRef *__restrict__ refs, int count,
                                                       const BLev *__restrict__ lev, const int *__restrict__ state,
-                                                      int order, double *__restrict__ part) {
+                                                      int order, double *__restrict__ part, int poff = 0) {
     __shared__ tr::ResLds<double> lds;
     BRef r;
     if (!take(refs, count, state, order, r)) return;
@@ -122,7 +138,7 @@ __global__ __launch_bounds__(tr::NT) void kb_residual(const BRef *__restrict__ r
         RS ? L.cf : nullptr, nullptr, nullptr, nullptr);
     if constexpr (!RS) {
         const double t = tr::block_sum(sq);
-        if (threadIdx.x == 0) part[rb::xcd_item(blockIdx.x, gridDim.x)] = t;
+        if (threadIdx.x == 0) part[poff + rb::xcd_item(blockIdx.x, gridDim.x)] = t;
     }
 }
 
@@ -202,8 +218,10 @@ inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
 // One launch of a program.
 struct Launch {
     int kind, first, count;
-    size_t lds;  // dynamic LDS (K_SMALL)
-    int slot;    // K_FIN: norm slot
+    size_t lds;    // dynamic LDS (K_SMALL)
+    int slot;      // K_FIN: norm slot
+    int poff = 0;  // K_NORM, K_SM0N: offset of the launch's partials
+    int lay = 0;   // K_FIN: 0 = partials of every patch in patch order, 1 = the pre-cycle layout
 };
 
 }  // namespace
@@ -220,18 +238,22 @@ struct mg_batch {
     std::vector<void *> allocs;           // batch-owned device memory
     bool phased_ok = false;               // phase programs built
     bool use_phases = true;
-    // phase programs: begin (fold, reference norms), one cycle per order, end (store)
+    // phase programs: begin (fold, reference norms), pre (the next cycle's
+    // first finest pass with the norm of its input), the rest of one cycle per
+    // order, end (store)
     struct Prog {
         std::vector<mg::Launch> k;
         hipGraphExec_t exec = nullptr;
     };
-    Prog begin, end, cycle[3];
+    Prog begin, end, pre, cycle[3];
     mg::BRef *refs = nullptr;                    // device, all programs' work items
     mg::BLev *lev[3] = {};                       // device [n * MAXL] per order
     mg::small::SmallLevels<double> *sl[3] = {};  // device [n] per order
-    int *state[3] = {};                          // device [n]: [0] every patch 2, [o] this cycle's order-o patches
+    int *state[4] = {};                          // device [n]: [0] every patch 2, [o] this cycle's order-o patches,
+                                                 //   [3] the patches of the pre program
     int *pin_state = nullptr;                    // pinned [3n]
     int *nfirst = nullptr, *ncnt = nullptr;      // device [n]: each patch's norm partials within a norm phase
+    int *nfirst1 = nullptr, *ncnt1 = nullptr;    // ... within the pre program
     double *part = nullptr;
     double *norm2 = nullptr;       // device [2n]
     double *norm2_host = nullptr;  // pinned
@@ -288,6 +310,7 @@ struct Planner {
     std::vector<Launch> *out;
     std::vector<BRef> &refs;
     std::vector<std::array<int, MAXL>> cur;
+    std::vector<char> skip;  // patches whose first finest pass of a cycle runs in the pre program
 
     Planner(mg_batch *b, int order, std::vector<BRef> &r) : B(b), o(order), out(nullptr), refs(r) {
         cur.assign(b->n, std::array<int, MAXL>{});
@@ -344,7 +367,16 @@ struct Planner {
         }
         smooth(last, l, op.n_coarse_sweeps, zero);
         if (reg.empty()) return;
-        smooth(reg, l, op.n_pre, zero);
+        if (l == 0 && !skip.empty()) {
+            // the pre program ran the first pass of the patches marked in skip
+            std::vector<int> extra;
+            for (int p : reg)
+                if (!skip[p]) extra.push_back(p);
+            smooth(extra, 0, 1, zero);
+            smooth(reg, 0, op.n_pre - 1, zero);
+        } else {
+            smooth(reg, l, op.n_pre, zero);
+        }
         open(l == 0 ? K_RES0 : K_RESC);
         for (int p : reg) {
             const Level &C = B->patches[p]->lev[l + 1];
@@ -362,6 +394,36 @@ struct Planner {
         for (int p = 0; p < B->n; p++) add(p, 0, od(p, 0).nsegs, with_x ? cur[p][0] : 2);
         close();
         out->push_back(Launch{K_FIN, 0, B->n, 0, slot});
+    }
+    // pre program: the first finest pass of the next cycle, which also forms
+    // the norm partials of the current iterate (patches marked in skip), the
+    // residual-norm march of the others, and every patch's sum into slot 0;
+    // first/cnt: each patch's partials in this layout
+    void pre(std::vector<int> &first, std::vector<int> &cnt) {
+        int at = 0;
+        open(K_SM0N);
+        for (int p = 0; p < B->n; p++)
+            if (skip[p]) {
+                first[p] = at;
+                cnt[p] = od(p, 0).nsegs;
+                at += cnt[p];
+                add(p, 0, cnt[p], 0);
+            }
+        close();
+        open(K_NORM);
+        out->back().poff = at;
+        int bt = 0;
+        for (int p = 0; p < B->n; p++)
+            if (!skip[p]) {
+                first[p] = at + bt;
+                cnt[p] = od(p, 0).nsegs;
+                bt += cnt[p];
+                add(p, 0, cnt[p], 0);
+            }
+        close();
+        Launch fin{K_FIN, 0, B->n, 0, 0};
+        fin.lay = 1;
+        out->push_back(fin);
     }
     void tiles0(int kind) {
         open(kind);
@@ -436,16 +498,34 @@ std::vector<small::SmallLevels<double>> small_levels(mg_batch *B, int o) {
 bool build_programs(mg_batch *B) {
     const int n = B->n;
     std::vector<BRef> refs;
+    // patches whose finest level takes passes in both orders: the first of a
+    // cycle's passes runs in the pre program, which also forms the norm of
+    // the cycle's input; the others get the residual-norm march there
+    std::vector<char> skip(n, 0);
+    for (int p = 0; p < n; p++) {
+        const mg_hierarchy *H = B->patches[p];
+        skip[p] = B->opt.n_pre >= 1 && H->ls[1] != 0 && H->ls[2] != 0 && H->nlev[1] > 1 && H->nlev[2] > 1;
+    }
+    std::vector<int> first1(n), cnt1(n);
     try {
         for (int o = 1; o <= 2; o++) {
             Planner P(B, o, refs);
             P.out = &B->cycle[o].k;
+            P.skip = skip;
             std::vector<int> all(n);
-            for (int p = 0; p < n; p++) all[p] = p;
+            for (int p = 0; p < n; p++) {
+                all[p] = p;
+                P.cur[p][0] = skip[p] ? 1 : 0;
+            }
             P.mg(all, 0, false);
             for (int p = 0; p < n; p++)
                 if (P.cur[p][0] != 0) throw Unsupported{};  // odd number of finest-level passes
-            P.norm(true, 0);
+        }
+        {
+            Planner P(B, 2, refs);
+            P.out = &B->pre.k;
+            P.skip = skip;
+            P.pre(first1, cnt1);
         }
         Planner P(B, 2, refs);
         P.out = &B->begin.k;
@@ -455,7 +535,7 @@ bool build_programs(mg_batch *B) {
         P.out = &B->end.k;
         P.tiles0(K_STORE);
     } catch (const Unsupported &) {
-        for (auto *g : {&B->begin, &B->end, &B->cycle[1], &B->cycle[2]}) g->k.clear();
+        for (auto *g : {&B->begin, &B->end, &B->pre, &B->cycle[1], &B->cycle[2]}) g->k.clear();
         return false;
     }
     // each patch's partials within a norm phase (every norm phase lists all
@@ -471,13 +551,15 @@ bool build_programs(mg_batch *B) {
     B->refs = upload(B, refs);
     B->nfirst = upload(B, first);
     B->ncnt = upload(B, cnt);
+    B->nfirst1 = upload(B, first1);
+    B->ncnt1 = upload(B, cnt1);
     B->part = balloc<double>(B, (size_t)part_cap);
     for (int o = 1; o <= 2; o++) {
         B->lev[o] = upload(B, descriptors(B, o));
         B->sl[o] = upload(B, small_levels(B, o));
     }
     B->lev[0] = B->lev[2];
-    for (int s = 0; s < 3; s++) B->state[s] = balloc<int>(B, n);
+    for (int s = 0; s < 4; s++) B->state[s] = balloc<int>(B, n);
     std::vector<int> all2(n, 2);
     BHIP(hipMemcpyAsync(B->state[0], all2.data(), n * sizeof(int), hipMemcpyHostToDevice, B->stream));
     BHIP(hipStreamSynchronize(B->stream));
@@ -537,9 +619,15 @@ void launch(mg_batch *B, const Launch &k, int order, const int *state) {
             break;
         case K_RESC: kb_restrict<<<g, NT, 0, s>>>(r, k.count, lev, state, order); break;
         case K_SMALL: kb_small<<<k.count, NTS, k.lds, s>>>(r, k.count, lev, state, order, B->sl[order]); break;
-        case K_NORM: kb_residual<tr::RM_NORM><<<g, NT, 0, s>>>(r, k.count, lev, state, order, B->part); break;
+        case K_NORM:
+            kb_residual<tr::RM_NORM><<<g, NT, 0, s>>>(r, k.count, lev, state, order, B->part, k.poff);
+            break;
+        case K_SM0N:
+            kb_smooth<true, FINE_Z, false, true><<<g, NT, 0, s>>>(r, k.count, lev, state, order, B->part, k.poff);
+            break;
         case K_FIN:
-            kb_finalize<<<B->n, 1024, 0, s>>>(B->nfirst, B->ncnt, B->n, B->part, B->norm2, k.slot, state, order);
+            kb_finalize<<<B->n, 1024, 0, s>>>(k.lay ? B->nfirst1 : B->nfirst, k.lay ? B->ncnt1 : B->ncnt, B->n,
+                                              B->part, B->norm2, k.slot, state, order);
             break;
         case K_FOLD:
             kb_fold<<<g, NT, 0, s>>>(r, k.count, lev, state, order, B->in_rho, B->in_dir,
@@ -624,14 +712,37 @@ mg_status solve_batch_phased(mg_batch *B, const double *const *rho, double *cons
         const mg_status st = phase_start(H, S[p]);
         if (st != MG_OK) return st;
     }
+    // Every round: the pre program (the first finest pass of the next cycle,
+    // which also forms the residual norm of the current iterate; it reads
+    // buffer 0 and writes buffer 1, and the finest level is the same in both
+    // orders), one synchronisation, each patch's stop test and order switch
+    // on that norm, then the rest of the cycle for the patches that go on.  A
+    // patch that stops keeps its iterate in buffer 0.  The first round's norm
+    // is the initial one, already taken.
     std::vector<int> run;
-    while (true) {
+    for (int round = 0;; round++) {
         run.clear();
         for (int p = 0; p < n; p++)
             if (S[p].active) run.push_back(p);
         if (run.empty()) break;
+        int *sp = B->pin_state;  // slot 0 of the pinned staging: the pre program's patches
+        for (int p = 0; p < n; p++) sp[p] = S[p].active ? 2 : 0;
+        BHIP(hipMemcpyAsync(B->state[3], sp, n * sizeof(int), hipMemcpyHostToDevice, s));
+        run_program(B, B->pre, 2, B->state[3]);
+        BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+        BHIP(hipStreamSynchronize(s));
+        if (round > 0) {
+            for (int p : run) {
+                mg_hierarchy *H = B->patches[p];
+                H->norm_host[0] = B->norm2_host[2 * p];
+                S[p].host_slot = 0;
+                S[p].parity = 0;  // the finished cycle's iterate is in buffer 0
+                const mg_status st = phase_cycle_finish(H, S[p]);
+                if (st != MG_OK) return st;
+            }
+        }
         for (int o = 2; o >= 1; o--) {
-            int *sv = B->pin_state + o * n;  // the previous cycle's copies have finished
+            int *sv = B->pin_state + o * n;  // the previous round's copies have finished
             bool use = false;
             for (int p = 0; p < n; p++) {
                 sv[p] = (S[p].active && S[p].order == o) ? o : 0;
@@ -640,16 +751,6 @@ mg_status solve_batch_phased(mg_batch *B, const double *const *rho, double *cons
             if (!use) continue;
             BHIP(hipMemcpyAsync(B->state[o], sv, n * sizeof(int), hipMemcpyHostToDevice, s));
             run_program(B, B->cycle[o], o, B->state[o]);
-        }
-        BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
-        BHIP(hipStreamSynchronize(s));
-        for (int p : run) {
-            mg_hierarchy *H = B->patches[p];
-            H->norm_host[0] = B->norm2_host[2 * p];
-            S[p].host_slot = 0;
-            S[p].parity = 0;  // the programs end with the finest iterate in buffer 0
-            const mg_status st = phase_cycle_finish(H, S[p]);
-            if (st != MG_OK) return st;
         }
     }
     run_program(B, B->end, 2, B->state[0]);
@@ -706,7 +807,7 @@ extern "C" {
 void mg_destroy_batch(mg_batch *B) {
     if (!B) return;
     if (B->stream) (void)hipStreamSynchronize(B->stream);
-    for (auto *g : {&B->begin, &B->end, &B->cycle[1], &B->cycle[2]})
+    for (auto *g : {&B->begin, &B->end, &B->pre, &B->cycle[1], &B->cycle[2]})
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
     for (mg_hierarchy *H : B->patches) mg_destroy_hierarchy(H);
     for (void *p : B->allocs) {
@@ -812,12 +913,13 @@ int32_t mg_batch_grid(const mg_batch *B) {
     int m = 0;
     for (int o = 1; o <= 2; o++)
         for (const mg::Launch &k : B->cycle[o].k) m = std::max(m, k.count);
+    for (const mg::Launch &k : B->pre.k) m = std::max(m, k.count);
     return m;
 }
 
 int32_t mg_batch_phases(const mg_batch *B, int32_t order) {
     if (!B || !B->phased_ok || (order != 1 && order != 2)) return 0;
-    return (int32_t)B->cycle[order].k.size();
+    return (int32_t)(B->pre.k.size() + B->cycle[order].k.size());
 }
 
 }  // extern "C"
