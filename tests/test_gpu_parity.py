@@ -483,6 +483,32 @@ def test_batch_equals_single_solves_and_repeats(mg, engine):
     B.close()
 
 
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batch_mixes_whole_workgroup_patches(mg, graph):
+    """Patches whose whole hierarchy runs in one workgroup (sphere 16^3) or
+    that have a single level (6 x 10 x 10) get the residual-norm march in the
+    pre program while the others' first pass forms the norm: every patch
+    still equals its single-grid solve bit for bit."""
+    probs = gen.patch_problems(count=4, seed=12) + [gen.sphere_problem(16), gen.sphere_problem(32),
+                                                    gen.random_small_problem((6, 10, 10), 7, active_frac=0.8)]
+    for p in probs:
+        _print_case(p.name, p)
+    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], use_graph=graph)
+    assert B.phases(1) > 0 and B.phases(2) > 0
+    rhos = [dev(p.rho) for p in probs]
+    dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
+    got, infos, _ = B.solve(rhos, dirichlets=dirs, tol=1e-10, check=False)
+    for p, x, info, r, d in zip(probs, got, infos, rhos, dirs):
+        H = mg.Hierarchy(dev(p.mask), p.h)
+        ref, rinfo = H.solve(r, None, d, tol=1e-10, check=False)
+        assert info["status"] == rinfo["status"], p.name
+        assert (info["cycles"], info["switched_at"], info["r_final"]) == \
+            (rinfo["cycles"], rinfo["switched_at"], rinfo["r_final"]), p.name
+        assert np.array_equal(host(x), host(ref)), p.name
+        H.close()
+    B.close()
+
+
 def test_batch_guess_and_max_cycles(mg):
     """Phase engine with a non-zero guess (junk in inactive cells must not
     leak) and a cycle cap: the same iterate as single solves, MG_NOT_CONVERGED
