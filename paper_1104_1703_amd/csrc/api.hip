@@ -115,7 +115,30 @@ void build_lists(mg_hierarchy *H, int l, int order) {
         od.pmask2 = alloc_n<unsigned long long>(H, std::max<size_t>(1, segs.size() * npl2));
         launch_item_masks(L, l, order, od, npl2, od.pmask2, H->stream, 4);
     }
-    HIPCHK(hipStreamSynchronize(H->stream));
+    if (l == 1) {  // whole tiles for the FP64 prolongation pass
+        std::vector<Seg> s8;
+        for (int ty = 0; ty < L.nty; ty++)
+            for (int tx = 0; tx < L.ntx; tx++)
+                for (int tz = 0; tz < L.ntz; tz++)
+                    if (hf[(tz * L.nty + ty) * L.ntx + tx])
+                        s8.push_back(Seg{tx * TX, ty * TY, tz * TZ, std::min(L.nz, (tz + 1) * TZ)});
+        std::sort(s8.begin(), s8.end(), [](const Seg &a, const Seg &b) {
+            if (a.z0 != b.z0) return a.z0 < b.z0;
+            if (a.y0 != b.y0) return a.y0 < b.y0;
+            return a.x0 < b.x0;
+        });
+        od.nsegs8 = (int)s8.size();
+        od.segs8 = alloc_n<Seg>(H, std::max<size_t>(1, s8.size()));
+        if (!s8.empty())
+            HIPCHK(hipMemcpyAsync(od.segs8, s8.data(), s8.size() * sizeof(Seg), hipMemcpyHostToDevice, H->stream));
+        constexpr int npl8 = TZ + 4;
+        od.pmask8 = alloc_n<unsigned long long>(H, std::max<size_t>(1, s8.size() * npl8));
+        OrderData t = od;
+        t.segs = od.segs8;
+        t.nsegs = od.nsegs8;
+        launch_item_masks(L, l, order, t, npl8, od.pmask8, H->stream);
+        HIPCHK(hipStreamSynchronize(H->stream));
+    }
 }
 
 mg_status validate_options(const mg_options &o) {

@@ -45,6 +45,12 @@ struct OrderData {
     Seg *segs = nullptr;   // smoother work items (device)
     unsigned long long *pmask = nullptr;  // per item and plane activity masks (device)
     unsigned long long *pmask2 = nullptr; // the same for fused pairs of passes (4-cell halo; fuse_passes)
+    // level 1, FP64 pass with the prolongation on load: whole 8-plane tiles as
+    // work items and their masks (that pass fits 4 blocks per CU, not 5, and
+    // one round of tiles beats two rounds of 4-plane items)
+    Seg *segs8 = nullptr;
+    unsigned long long *pmask8 = nullptr;
+    int nsegs8 = 0;
     int ntiles = 0, nsegs = 0;
     int64_t nact = 0;
 };

@@ -131,6 +131,10 @@ void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const L
         k_rbgs<double, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
             xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx, C.ny,
             C.nz);
+    else if (level == 1 && od.nsegs8 > 0)  // whole tiles: one round at 4 blocks per CU
+        k_rbgs<double, false, TZ, true><<<grid8(od.nsegs8), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz,
+                                                                      h2, od.segs8, od.pmask8, od.nsegs8, L.halt, xc,
+                                                                      C.nx, C.ny, C.nz);
     else
         launch_coarse<double, true>(item_depth(level), xin, xout, f, od.d, L, od, h2, s, xc, &C);
 }
