@@ -134,15 +134,14 @@ __global__ __launch_bounds__(NT) void k_restrict(const int *__restrict__ ctiles,
                            x, f, fc);
 }
 
+// Eight blocks per CU put the 2048 finest items of 256^3 in one round (the
+// update-and-residual mode keeps seven: eight would spill).
 template <typename T, int SEGZ, int MODE>
-__global__ __launch_bounds__(NT) void k_residual_march(const T *__restrict__ x, const T *__restrict__ f,
-                                                       const uint8_t *__restrict__ code, int nx, int ny, int nz,
-                                                       T ih2, const Seg *__restrict__ segs,
-                                                       const unsigned long long *__restrict__ pm, int nsegs,
-                                                       const T *__restrict__ cd, int cnx, int cny,
-                                                       T *__restrict__ fc, double *__restrict__ part,
-                                                       float *__restrict__ r32, const float *__restrict__ ecor,
-                                                       T *__restrict__ xo, const int *__restrict__ halt) {
+__global__ __launch_bounds__(NT, MODE == RM_AXPY32 ? 7 : 8) void k_residual_march(
+    const T *__restrict__ x, const T *__restrict__ f, const uint8_t *__restrict__ code, int nx, int ny, int nz, T ih2,
+    const Seg *__restrict__ segs, const unsigned long long *__restrict__ pm, int nsegs, const T *__restrict__ cd,
+    int cnx, int cny, T *__restrict__ fc, double *__restrict__ part, float *__restrict__ r32,
+    const float *__restrict__ ecor, T *__restrict__ xo, const int *__restrict__ halt) {
     __shared__ ResLds<T> lds;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= nsegs || (halt && *halt)) return;
