@@ -367,6 +367,28 @@ mg_status mg_unet_train_step(mg_unet *U, int32_t n, const double *rho_dev, const
                              int32_t nz, float lr, float weight_decay, double *loss_out);
 
 /*
+ * Copy one tensor the network keeps between layers (BF16, channels-last, for
+ * the batch shape of the last mg_unet_loss_grad / mg_unet_train_step /
+ * mg_unet_infer call) into dst_dev, for per-layer checks of the chain rule
+ * that mg_unet_loss_grad applies layer by layer.  kind:
+ *   MG_UNET_ACT       index 0..13: layer output after ReLU (layer order above)
+ *   MG_UNET_ACT_GRAD  index 0..13: after a loss_grad, the loss gradient of the
+ *                     layer's output with the ReLU applied (zero where the
+ *                     output is not positive), i.e. of its pre-activation
+ *   MG_UNET_POOL      index 0..2: the pooled encoder outputs (levels 2..4)
+ *   MG_UNET_POOL_GRAD index 0..2: after a loss_grad, their loss gradients
+ *   MG_UNET_INPUT     index 0: the packed 16-channel input
+ *   MG_UNET_CAT_GRAD  index 0: after a loss_grad, the gradient of the last
+ *                     concatenated input differentiated (that of dec3a)
+ * count must equal the tensor's element count (MG_ERR_ARG otherwise, also
+ * when the tensor does not exist, e.g. a gradient after an inference).  The
+ * copy is enqueued on the network's stream and the call synchronises it.
+ */
+enum { MG_UNET_ACT = 0, MG_UNET_ACT_GRAD = 1, MG_UNET_POOL = 2, MG_UNET_POOL_GRAD = 3, MG_UNET_INPUT = 4,
+       MG_UNET_CAT_GRAD = 5 };
+mg_status mg_unet_tensor(mg_unet *U, int32_t kind, int32_t index, void *dst_dev, int64_t count);
+
+/*
  * First guess for one problem (nz, ny, nx), written to phi0_dev (float64,
  * every cell; 0 off the active set).  The network runs on the 1/stride grid
  * (stride 1, 2, 4 or 8; dims multiples of 8 * stride): each coarse cell takes

@@ -137,8 +137,10 @@ void build_lists(mg_hierarchy *H, int l, int order) {
         t.segs = od.segs8;
         t.nsegs = od.nsegs8;
         launch_item_masks(L, l, order, t, npl8, od.pmask8, H->stream);
-        HIPCHK(hipStreamSynchronize(H->stream));
     }
+    // the host vectors staged above (tiles, segs, s8) are the sources of
+    // asynchronous copies: wait for them before the vectors go away
+    HIPCHK(hipStreamSynchronize(H->stream));
 }
 
 mg_status validate_options(const mg_options &o) {

@@ -408,6 +408,38 @@ void mg_unet_destroy(mg_unet *U) {
     delete U;
 }
 
+mg_status mg_unet_tensor(mg_unet *U, int32_t kind, int32_t index, void *dst, int64_t count) {
+    if (!U || !dst || U->wn == 0) {
+        set_error("mg_unet_tensor: null argument or no workspace");
+        return MG_ERR_ARG;
+    }
+    const long long V1 = (long long)U->wn * U->wd * U->wh * U->ww;
+    auto vox = [&](int level) { return V1 >> (3 * (level - 1)); };
+    const void *src = nullptr;
+    long long n = 0;
+    if ((kind == MG_UNET_ACT || kind == MG_UNET_ACT_GRAD) && index >= 0 && index < NLAYER) {
+        src = kind == MG_UNET_ACT ? U->act[index] : U->gact[index];
+        n = kLayers[index].cout * vox(kLayers[index].level);
+    } else if ((kind == MG_UNET_POOL || kind == MG_UNET_POOL_GRAD) && index >= 0 && index < 3) {
+        src = kind == MG_UNET_POOL ? U->pool[index] : U->gpool[index];
+        n = (16LL << index) * vox(index + 2);
+    } else if (kind == MG_UNET_INPUT && index == 0) {
+        src = U->x0;
+        n = 16 * V1;
+    } else if (kind == MG_UNET_CAT_GRAD && index == 0) {
+        src = U->gcat;
+        n = (kLayers[D3A].ca + kLayers[D3A].cb) * vox(kLayers[D3A].level);
+    }
+    if (!src || count != n) {
+        set_error("mg_unet_tensor: no such tensor or wrong element count");
+        return MG_ERR_ARG;
+    }
+    const bool ok = hip_ok(hipMemcpyAsync(dst, src, (size_t)n * sizeof(bf16), hipMemcpyDeviceToDevice, U->stream),
+                           "tensor copy") &&
+                    hip_ok(hipStreamSynchronize(U->stream), "tensor copy sync");
+    return ok ? MG_OK : MG_ERR_HIP;
+}
+
 void *mg_unet_stream(const mg_unet *U) { return U ? (void *)U->stream : nullptr; }
 
 int32_t mg_unet_step(const mg_unet *U) { return U ? U->step : 0; }

@@ -90,6 +90,7 @@ SYMBOLS = [
     ("mg_unet_set_params", C.c_int, [_P, _P, C.c_int64]),
     ("mg_unet_get_params", C.c_int, [_P, _P, C.c_int64]),
     ("mg_unet_get_grads", C.c_int, [_P, _P, C.c_int64]),
+    ("mg_unet_tensor", C.c_int, [_P, _I, _I, _P, C.c_int64]),
     ("mg_unet_save", C.c_int, [_P, C.c_char_p]),
     ("mg_unet_load", C.c_int, [_P, C.c_char_p]),
     ("mg_unet_loss_grad", C.c_int, [_P, _I, _P, _P, _P, _P, _I, _I, _I, C.POINTER(_D)]),
@@ -462,6 +463,16 @@ class UNet:
         out = np.empty(self.num_params, np.float32)
         _check(self._call(load_library().mg_unet_get_grads, self._u, out.ctypes.data_as(C.c_void_p),
                           self.num_params), "mg_unet_get_grads")
+        return out
+
+    TENSOR_KINDS = {"act": 0, "act_grad": 1, "pool": 2, "pool_grad": 3, "input": 4, "cat_grad": 5}
+
+    def tensor(self, kind: str, index: int, shape):
+        """Copy of a tensor the network keeps between layers (BF16,
+        channels-last ``shape`` of the last batch); kinds as in mg.h."""
+        out = torch.empty(tuple(shape), dtype=torch.bfloat16, device=self.device)
+        _check(self._call(load_library().mg_unet_tensor, self._u, self.TENSOR_KINDS[kind], int(index), _ptr(out),
+                          out.numel()), "mg_unet_tensor")
         return out
 
     def set_params(self, p):
