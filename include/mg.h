@@ -129,6 +129,22 @@ mg_status mg_solve(mg_hierarchy *H, const double *rho_dev, double *phi_dev, cons
 mg_status mg_residual_norm(mg_hierarchy *H, const double *rho_dev, const double *phi_dev,
                            const double *dirichlet_dev, double *norm_out);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops): mg_residual_norm with its partial
+ * sums in a static per-device scratch array of the library (1 MiB, held by
+ * each device the library runs on until the process ends) instead of the
+ * hierarchy's buffer.  Calls no allocator and does not synchronise: the norm
+ * is written to norm_dev (device, one double) on the hierarchy's stream.
+ * The calling thread's current device must be the hierarchy's (MG_ERR_ARG
+ * otherwise).  MG_ERR_ARG when the finest level has more than 131008 work
+ * items (a 32 x 8 x 16 cell column each; a full 512^3 box has 32768).  Like
+ * mg_residual_norm it overwrites the hierarchy's finest right-hand side and
+ * iterate.  All calls on one device share the scratch array: calls that
+ * overlap on one device (on different streams or from several threads)
+ * race; calls ordered on one stream do not. */
+mg_status mg_residual_norm_noalloc(mg_hierarchy *H, const double *rho_dev, const double *phi_dev,
+                                   const double *dirichlet_dev, double *norm_dev);
+
 /* Static text of a status code. */
 const char *mg_status_string(mg_status s);
 

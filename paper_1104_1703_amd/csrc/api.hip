@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "mg_core.h"
@@ -920,6 +921,77 @@ mg_status mg_residual_norm(mg_hierarchy *H, const double *rho_dev, const double 
         launch_resnorm(L0, 0, od0, L0.x[0], L0.f, H->part, H->norm_dev, 0, H->stream);
         HIPCHK(hipMemcpyAsync(H->norm_host, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
         *norm_out = read_norm(H);
+        return MG_OK;
+    });
+}
+
+}  // extern "C"
+
+// Scratch of mg_residual_norm_noalloc: the per-item partial sums of squares
+// and their total, in a file-scope device array, so that the call allocates
+// nothing.  Host code must never pass `scratch` itself to a kernel (in host
+// code it names a host-side stand-in): its device address is taken once per
+// device with hipGetSymbolAddress and kept in g_scratch_dev.
+namespace {
+
+constexpr int NOALLOC_DOUBLES = 1 << 17;   // 1 MiB per device
+constexpr int NOALLOC_PART = 64;           // partials start here; [0] holds the total
+constexpr int NOALLOC_MAX_DEV = 64;
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+std::mutex g_scratch_mu;
+double *g_scratch_dev[NOALLOC_MAX_DEV] = {};
+
+// Device address of `scratch` on device `dev`, which must be current.
+double *scratch_on(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) {
+        set_error("device index out of range for the static scratch");
+        return nullptr;
+    }
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        if (!hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) return nullptr;
+        g_scratch_dev[dev] = (double *)p;
+    }
+    return g_scratch_dev[dev];
+}
+
+__global__ void k_sqrt_out(const double *__restrict__ sq, double *__restrict__ out) { out[0] = sqrt(sq[0]); }
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_residual_norm_noalloc(mg_hierarchy *H, const double *rho_dev, const double *phi_dev,
+                                   const double *dirichlet_dev, double *norm_dev) {
+    if (!H || !rho_dev || !phi_dev || !norm_dev) {
+        set_error("null argument");
+        return MG_ERR_ARG;
+    }
+    const OrderData &od0 = odata(H, 0, 2);
+    if (od0.nsegs > NOALLOC_DOUBLES - NOALLOC_PART) {
+        set_error("mg_residual_norm_noalloc: " + std::to_string(od0.nsegs) +
+                  " finest work items exceed the static scratch (" + std::to_string(NOALLOC_DOUBLES - NOALLOC_PART) +
+                  " partial sums)");
+        return MG_ERR_ARG;
+    }
+    int dev = -1;
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return MG_ERR_HIP;
+    if (dev != H->device) {
+        set_error("mg_residual_norm_noalloc: the current device is not the hierarchy's");
+        return MG_ERR_ARG;
+    }
+    double *sc = scratch_on(dev);
+    if (!sc) return MG_ERR_HIP;
+    return guarded([&]() {
+        Level &L0 = H->lev[0];
+        // the same kernels as mg_residual_norm; every partial the final sum
+        // reads is written by the march of this call, so nothing is cleared
+        launch_fold(L0, od0, rho_dev, dirichlet_dev, phi_dev, L0.f, L0.x[0], H->stream);
+        launch_resnorm(L0, 0, od0, L0.x[0], L0.f, sc + NOALLOC_PART, sc, 0, H->stream, nullptr);
+        k_sqrt_out<<<1, 1, 0, H->stream>>>(sc, norm_dev);
+        HIPCHK(hipGetLastError());
         return MG_OK;
     });
 }

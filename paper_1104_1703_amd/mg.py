@@ -57,6 +57,7 @@ SYMBOLS = [
     ("mg_destroy_hierarchy", None, [_P]),
     ("mg_solve", C.c_int, [_P, _P, _P, _P, _D, C.POINTER(SolveInfo)]),
     ("mg_residual_norm", C.c_int, [_P, _P, _P, _P, C.POINTER(_D)]),
+    ("mg_residual_norm_noalloc", C.c_int, [_P, _P, _P, _P, _P]),
     ("mg_status_string", C.c_char_p, [C.c_int]),
     ("mg_last_error", C.c_char_p, []),
     ("mg_num_levels", _I, [_P, _I]),
@@ -299,6 +300,15 @@ class Hierarchy:
                         C.byref(out))
         _check(st, "mg_residual_norm")
         return float(out.value)
+
+    def residual_norm_noalloc(self, rho, phi, dirichlet=None, out=None):
+        """The residual norm written to a one-element float64 device tensor,
+        with no allocation or synchronisation inside the library."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        _check(self._call(load_library().mg_residual_norm_noalloc, self._h, _ptr(rho), _ptr(phi), _ptr(dirichlet),
+                          _ptr(out)), "mg_residual_norm_noalloc")
+        return out
 
     # ---- single steps ----
     def fold(self, rho, dirichlet=None):
