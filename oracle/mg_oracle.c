@@ -165,7 +165,8 @@ void orc_destroy(orc_h *H) {
 /*
  * Build the hierarchy from the finest mask (values +1 / -1).
  * Coarsen while every dimension is even and the next level keeps every
- * dimension >= min_dim.  Returns NULL on invalid input.
+ * dimension >= min_dim.  Returns NULL on invalid input, including a mask
+ * without an active cell.
  */
 orc_h *orc_create(const int8_t *mask, int nx, int ny, int nz, double h, int min_dim) {
     if (!mask || nx < 1 || ny < 1 || nz < 1 || !(h > 0)) return NULL;
@@ -194,6 +195,15 @@ orc_h *orc_create(const int8_t *mask, int nx, int ny, int nz, double h, int min_
                         s += H->cnt[l - 1][idx(H, l - 1, 2 * i + (c & 1), 2 * j + ((c >> 1) & 1), 2 * k + (c >> 2))];
                     H->cnt[l][idx(H, l, i, j, k)] = s;
                 }
+    }
+    /* an empty domain has no unknowns: rejected, as the GPU library does */
+    {
+        size_t na0 = 0;
+        for (size_t p = 0; p < ncell(H, 0); p++) na0 += (size_t)H->cnt[0][p];
+        if (na0 == 0) {
+            orc_destroy(H);
+            return NULL;
+        }
     }
     /* active sets per order */
     for (int o = 1; o <= 2; o++) {

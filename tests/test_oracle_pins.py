@@ -448,3 +448,59 @@ def test_solve_stop_rule_and_zero_rhs():
     phi, info = orc.solve(p.rho, tol=1e-6)
     assert info["r_final"] <= 1e-6 * info["r_ref"]
     assert info["history"][-2] > 1e-6 * info["r_ref"]
+
+
+@pytest.mark.parametrize("transform", ["flip_x", "flip_z", "swap_xz", "flip_y_swap_xy"])
+def test_smoother_independent_of_the_order_within_a_colour(transform):
+    """T6: a red-black pass relaxes each colour in place, and no cell of a
+    colour neighbours another cell of that colour, so the order in which a
+    colour's cells are visited cannot matter.  The oracle always visits in
+    (k, j, i) order; on a mirrored or axis-permuted problem that order
+    visits the original cells in a different sequence.  With odd edges the
+    mirrors and permutations keep every cell's colour, so relaxing the
+    transformed problem must give the transformed result, on the finest
+    level and on a coarse level in both orders.  The only difference
+    allowed is the rounding of the operator's face sum, whose terms come in
+    another order (1e-13); a colour whose cells read each other's new
+    values, or an asymmetric stencil, differs at order one."""
+    rng = np.random.default_rng(7)
+    shape = (22, 26, 30)                              # level 1: 11 x 13 x 15 (odd edges)
+    mask = np.where(rng.random(shape) < 0.75, 1, -1).astype(np.int8)
+    mask[[0, -1]] = -1
+    mask[:, [0, -1]] = -1
+    mask[:, :, [0, -1]] = -1
+    B = rng.standard_normal(shape)
+    axes = {"flip_x": lambda a: a[:, :, ::-1], "flip_z": lambda a: a[::-1],
+            "swap_xz": lambda a: a.transpose(2, 1, 0),
+            "flip_y_swap_xy": lambda a: a[:, ::-1].transpose(0, 2, 1)}[transform]
+    T = lambda a: np.ascontiguousarray(axes(a))
+    h = 1.0 / 30
+    orc, orc_t = O.Oracle(mask, h), O.Oracle(T(mask), h)
+    # fine level 0 (even edges: a mirror flips colours) is checked through
+    # level 1 of the same hierarchy, and directly on an odd-edged box
+    odd = mask[:21, :25, :29].copy()
+    odd[-1] = -1
+    odd[:, -1] = -1
+    odd[:, :, -1] = -1
+    Bo = B[:21, :25, :29]
+    cases = [(O.Oracle(odd, h), O.Oracle(T(odd), h), 0, 2, odd.shape, Bo)]
+    cases += [(orc, orc_t, 1, order, orc.dims(1), None) for order in (1, 2)]
+    worst = 0.0
+    for o1, o2, level, order, shp, Bl in cases:
+        act = o1.active(level, order).astype(bool)
+        assert np.array_equal(T(act), o2.active(level, order).astype(bool))
+        x = np.where(act, rng.standard_normal(shp), 0.0)
+        f = np.where(act, rng.standard_normal(shp), 0.0)
+        a = o1.smooth(level, x, f, Bl, passes=2, order=order)
+        b = o2.smooth(level, T(x), T(f), None if Bl is None else T(Bl), passes=2, order=order)
+        err = float(np.abs(T(a) - b).max() / np.abs(a).max())
+        worst = max(worst, err)
+        assert err <= 1e-13, (transform, level, order, err)
+    print(f"{transform}: worst relative difference {worst:.1e}")
+
+
+def test_oracle_rejects_an_empty_domain():
+    """A mask without an active cell has no unknowns (the domain is {m > 0},
+    Sec. 3): the oracle rejects it, as the library does."""
+    with pytest.raises(ValueError):
+        O.Oracle(-np.ones((8, 8, 8), np.int8), 1 / 8)
