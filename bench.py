@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--cpu-solves", type=int, default=2, help="complete oracle solves timed for cpu_baseline")
     ap.add_argument("--profile-smoother", type=int, default=0, metavar="N",
                     help="counter runs: build the 256^3 hierarchy, launch only the finest smoother N times, exit")
+    ap.add_argument("--profile-workload", choices=("holes", "porous"), default="holes",
+                    help="workload of --profile-smoother: the --n holes box or the --large-n porous box")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="counter runs: 4 plain device copies of MIB MiB (known bytes), exit")
     ap.add_argument("--schedules", type=int, default=0, metavar="N",
@@ -106,12 +108,15 @@ def profile_smoother(args):
     import torch
 
     from paper_1104_1703_amd import gen, mg
-    p = gen.holes_problem(n=args.n, seed=args.seed)
+    if args.profile_workload == "porous":
+        p = gen.porous_problem(args.large_n, seed=4)
+    else:
+        p = gen.holes_problem(n=args.n, seed=args.seed)
     H = mg.Hierarchy(torch.from_numpy(p.mask).cuda(), p.h)
     n = args.profile_smoother + (args.profile_smoother % 2)
     H.time_smoother(n)
     torch.cuda.synchronize()
-    print(json.dumps({"mode": "profile-smoother", "launches": n, "active_cells": H.n_active(0),
+    print(json.dumps({"mode": "profile-smoother", "workload": p.name, "launches": n, "active_cells": H.n_active(0),
                       "algorithmic_bytes_per_launch": SMOOTH_BYTES_FP64 * H.n_active(0)}), flush=True)
     H.close()
 
@@ -292,9 +297,9 @@ def amr_study(args):
     rows = []
     for n in ns:
         levels, ms = amr.solve_nested(n, 3)
-        e = amr.composite_errors(levels)
+        e = composite_errors(levels)
         li, ms_i = amr.solve_nested(n, 3, guess="interp")
-        ei = amr.composite_errors(li)
+        ei = composite_errors(li)
         rows.append({"n": n, "finest_h": levels[-1].h, "ms": round(ms, 3),
                      "cycles": [L.info["cycles"] for L in levels], **e,
                      "interp_guess": {"ms": round(ms_i, 3), "cycles": [L.info["cycles"] for L in li],
@@ -303,6 +308,39 @@ def amr_study(args):
         b["orders"] = {k: round(float(np.log2(a[k] / b[k])), 3) for k in ("phi_linf", "phi_l2", "grad_linf", "grad_l2")}
     print(json.dumps({"mode": "amr", "workload": "ln profile r0 = 0.1, base n^3 box + 3 nested n^3 levels "
                       "(central 1/2, 1/4, 1/8), tol 1e-12", "rows": rows}), flush=True)
+
+
+def composite_errors(levels, r0: float = 0.1):
+    """Measurement of a nested solve against the closed form (not part of the
+    solve): over the composite grid (each point on the finest level that
+    covers it; level-0 cells whose 5-point stencil leaves the array left
+    out), the largest and the volume-weighted RMS error of the potential and
+    of the gradient's Euclidean length, the latter relative to the largest
+    exact gradient length."""
+    from paper_1104_1703_amd import gen
+    ep, eg, vol, gmax = [], [], [], 0.0
+    for k, L in enumerate(levels):
+        ctr = gen.level_centres(L.shape, L.h, L.origin)
+        phi_e, _, grad_e = gen.ln_profile(ctr, r0)
+        use = gen.frame_mask(L.shape) == 1
+        if k + 1 < len(levels):
+            N = levels[k + 1]
+            lo = np.array(N.origin) + N.h
+            hi = np.array(N.origin) + (np.array(N.shape[::-1]) - 1) * N.h
+            use &= ~np.all((ctr > lo) & (ctr < hi), axis=-1)
+        if k == 0:
+            core = np.zeros(L.shape, dtype=bool)
+            core[2:-2, 2:-2, 2:-2] = True
+            use &= core
+        phi = L.phi.cpu().numpy()
+        g = np.moveaxis(L.grad.cpu().numpy(), 0, -1)
+        ep.append(np.abs(phi - phi_e)[use])
+        eg.append(np.linalg.norm(g - grad_e, axis=-1)[use])
+        vol.append(np.full(int(use.sum()), L.h ** 3))
+        gmax = max(gmax, float(np.linalg.norm(grad_e, axis=-1)[use].max()))
+    ep, eg, vol = np.concatenate(ep), np.concatenate(eg), np.concatenate(vol)
+    return {"phi_linf": float(ep.max()), "phi_l2": float(np.sqrt((vol * ep ** 2).sum() / vol.sum())),
+            "grad_linf": float(eg.max() / gmax), "grad_l2": float(np.sqrt((vol * eg ** 2).sum() / vol.sum()) / gmax)}
 
 
 def schedules(args):

@@ -61,36 +61,3 @@ def solve_nested(n: int, depth: int, r0: float = 0.1, tol: float = 1e-12, guess:
     for H in hier:
         H.close()
     return levels, ms
-
-
-def composite_errors(levels, r0: float = 0.1):
-    """Measurement of a nested solve against the closed form (not part of the
-    solve): over the composite grid (each point on the finest level that
-    covers it; level-0 cells whose 5-point stencil leaves the array left
-    out), the largest and the volume-weighted RMS error of the potential and
-    of the gradient's Euclidean length, the latter relative to the largest
-    exact gradient length."""
-    import numpy as np
-    ep, eg, vol, gmax = [], [], [], 0.0
-    for k, L in enumerate(levels):
-        ctr = gen.level_centres(L.shape, L.h, L.origin)
-        phi_e, _, grad_e = gen.ln_profile(ctr, r0)
-        use = gen.frame_mask(L.shape) == 1
-        if k + 1 < len(levels):
-            N = levels[k + 1]
-            lo = np.array(N.origin) + N.h
-            hi = np.array(N.origin) + (np.array(N.shape[::-1]) - 1) * N.h
-            use &= ~np.all((ctr > lo) & (ctr < hi), axis=-1)
-        if k == 0:
-            core = np.zeros(L.shape, dtype=bool)
-            core[2:-2, 2:-2, 2:-2] = True
-            use &= core
-        phi = L.phi.cpu().numpy()
-        g = np.moveaxis(L.grad.cpu().numpy(), 0, -1)
-        ep.append(np.abs(phi - phi_e)[use])
-        eg.append(np.linalg.norm(g - grad_e, axis=-1)[use])
-        vol.append(np.full(int(use.sum()), L.h ** 3))
-        gmax = max(gmax, float(np.linalg.norm(grad_e, axis=-1)[use].max()))
-    ep, eg, vol = np.concatenate(ep), np.concatenate(eg), np.concatenate(vol)
-    return {"phi_linf": float(ep.max()), "phi_l2": float(np.sqrt((vol * ep ** 2).sum() / vol.sum())),
-            "grad_linf": float(eg.max() / gmax), "grad_l2": float(np.sqrt((vol * eg ** 2).sum() / vol.sum()) / gmax)}

@@ -73,7 +73,29 @@ struct RbgsLds {
     DT d[FS][DN];
     unsigned long long m[MAXPL];
     T c[PRO ? CS : 1][PRO ? CPN : 1];
+    T rcp[FINE ? 16 : 1];  // finest level: correctly rounded 1/d for the diagonals d = 1..12
 };
+
+// Correctly rounded reciprocals of 1..12 (constant-folded at compile time
+// with IEEE division in each precision).
+constexpr double RCP64[13] = {0.0,       1.0,       1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5, 1.0 / 6,
+                              1.0 / 7,   1.0 / 8,   1.0 / 9,  1.0 / 10, 1.0 / 11, 1.0 / 12};
+constexpr float RCP32[13] = {0.0f,      1.0f,      1.0f / 2, 1.0f / 3, 1.0f / 4,  1.0f / 5,  1.0f / 6,
+                             1.0f / 7,  1.0f / 8,  1.0f / 9, 1.0f / 10, 1.0f / 11, 1.0f / 12};
+
+// a / d for a diagonal d = 1..12 with y = RN(1/d): q0 = RN(a y) is within
+// one unit in the last place of a/d, the remainder a - q0 d is exact under
+// a fused multiply-add, and one correction step q0 + (a - q0 d) y rounds to
+// the correctly rounded quotient (Markstein's theorem), so the result is bit
+// for bit that of the division, except that a quotient in the subnormal
+// range may differ from it by one unit of that range.  The remainder is
+// formed as -(q0 d - a) so that a zero keeps its sign.
+template <typename T>
+__device__ __forceinline__ T div_small(T a, T d, T y) {
+    const T q0 = a * y;
+    const T r = -__builtin_fma(q0, d, -a);
+    return __builtin_fma(r, y, q0);
+}
 
 // One full red-black pass over one work item (see the file comment of
 // smooth.hip).  Called by all 256 threads of a block.  `pm`: the item's
@@ -111,6 +133,8 @@ __device__ __forceinline__ double rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *_
     const int z0 = max(sg.z0, 0), z1 = min(sg.z1, nz);  // a work item never leaves the box
 
     if (tid < SEGZ + 4) L.m[tid] = pm ? pm[tid] : ~0ull;
+    if constexpr (FINE && !NORMIN)
+        if (tid < 16) L.rcp[tid] = tid <= 12 ? T(sizeof(T) == 8 ? RCP64[tid] : RCP32[tid]) : T(0);
 
     // Per-thread element positions are the same for every plane: precompute
     // the in-plane byte offsets (OFF_NONE outside the box) and the mask bits
@@ -265,13 +289,21 @@ __device__ __forceinline__ double rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *_
             const int v = lo + e / half;
             const int u = lo + ((col + gy0 + v + k + gx0 + lo) & 1) + 2 * (e % half);
             const int qq = (v - 1) * QX + (u - 1);
-            T d;
-            if constexpr (FINE) d = T((int)dq[didx(u, v)]);
-            else d = dq[didx(u, v)];
-            if (d == T(0)) continue;
-            const int q = v * PX + u;
-            const T s = (c[q - 1] + c[q + 1]) + (c[q - PX] + c[q + PX]) + (dn[q] + up[q]);
-            c[q] = (s - h2 * fq[qq]) / d;
+            if constexpr (FINE && !NORMIN) {  // (the norm-forming pass has no registers to spare)
+                const int ci = (int)dq[didx(u, v)];
+                if (ci == 0) continue;
+                const int q = v * PX + u;
+                const T s = (c[q - 1] + c[q + 1]) + (c[q - PX] + c[q + PX]) + (dn[q] + up[q]);
+                c[q] = div_small<T>(s - h2 * fq[qq], T(ci), L.rcp[ci]);
+            } else {
+                T d;
+                if constexpr (FINE) d = T((int)dq[didx(u, v)]);
+                else d = dq[didx(u, v)];
+                if (d == T(0)) continue;
+                const int q = v * PX + u;
+                const T s = (c[q - 1] + c[q + 1]) + (c[q - PX] + c[q + PX]) + (dn[q] + up[q]);
+                c[q] = (s - h2 * fq[qq]) / d;
+            }
         }
     };
 
