@@ -73,6 +73,16 @@ typedef struct {
     int32_t fuse_passes;      /* 1 = run each pair of consecutive red-black passes on a level
                                  as one launch (two passes per march: x, f and the diagonal
                                  read once for both); same results bit for bit (default 0) */
+    int32_t tune;             /* 1 = pick the planes per smoother work item of every level and
+                                 boundary order by timing the compiled variants at creation
+                                 (cached in the file named by MG_TUNE_CACHE, if set); 0 = the
+                                 defaults below (default 0).  Every choice gives the same
+                                 iterates bit for bit; only the order in which the residual
+                                 norm's partial sums are added depends on it. */
+    int32_t item_depth_fine;  /* planes per finest-level work item: 8, 16 or 32; 0 = default
+                                 (16) or tuned.  A non-zero value is used as given. */
+    int32_t item_depth_l1;    /* level 1: 2, 4 or 8; 0 = default (4) or tuned */
+    int32_t item_depth_coarse;/* levels >= 2: 2, 4 or 8; 0 = default (2) or tuned */
     mg_allocator allocator;
 } mg_options;
 
@@ -162,6 +172,12 @@ mg_status mg_level_dims(const mg_hierarchy *H, int32_t level, int32_t *dims_out)
 
 /* Number of active cells of level l under boundary order `order`. */
 int64_t mg_level_active(const mg_hierarchy *H, int32_t level, int32_t order);
+
+/* Planes per smoother work item of level l in boundary order `order` (the
+ * default, the option's or the tuned value; work items are 32 x 8 cell
+ * columns); -1 for an invalid level or order.  Levels run by the
+ * one-workgroup small-level kernel keep their lists but use none. */
+int32_t mg_level_item_depth(const mg_hierarchy *H, int32_t level, int32_t order);
 
 /* Copy the integer mask counts of level l (active finest descendants per
  * cell, int32, dims of level l) into a device array (Sec. 3 R1 of the mask). */

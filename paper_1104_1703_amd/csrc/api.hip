@@ -2,6 +2,8 @@
 // multigrid iteration as a fixed kernel sequence (replayed as a hipGraph), the
 // solve loop with the runtime order switch, and single-step entry points.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -59,7 +61,23 @@ const OrderData &odata(const mg_hierarchy *H, int l, int order) { return H->lev[
 
 // ---------------------------------------------------------------- build --
 
-void build_lists(mg_hierarchy *H, int l, int order) {
+// Releases one allocation made through dev_alloc (after the stream is idle).
+void dev_free(mg_hierarchy *H, void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < H->allocs.size(); i++)
+        if (H->allocs[i] == p) {
+            if (H->opt.allocator.free) H->opt.allocator.free(p, H->opt.allocator.ctx);
+            else if (!H->opt.allocator.alloc) (void)hipFree(p);
+            H->allocs[i] = H->allocs.back();
+            H->allocs.pop_back();
+            return;
+        }
+}
+
+// Active tile list, smoother work items of `depth` planes and their activity
+// masks of level l in boundary order `order`, written to od (its diagonals
+// and active count are left as they are).
+void build_lists(mg_hierarchy *H, int l, int order, int depth, OrderData &od) {
     Level &L = H->lev[l];
     const int nt = L.ntx * L.nty * L.ntz;
     uint8_t *flags = alloc_n<uint8_t>(H, (size_t)nt);
@@ -67,10 +85,13 @@ void build_lists(mg_hierarchy *H, int l, int order) {
     std::vector<uint8_t> hf(nt);
     HIPCHK(hipMemcpyAsync(hf.data(), flags, nt, hipMemcpyDeviceToHost, H->stream));
     HIPCHK(hipStreamSynchronize(H->stream));
+    dev_free(H, flags);
     std::vector<int> tiles;
     for (int t = 0; t < nt; t++)
         if (hf[t]) tiles.push_back(t);
-    // smoother items: runs of active tiles along z, cut every SEG_TILES tiles
+    // smoother items: on the finest level runs of active tiles along z, cut
+    // every depth / TZ tiles; on coarse levels one active tile cut into
+    // depth-plane items
     std::vector<Seg> segs;
     for (int ty = 0; ty < L.nty; ty++)
         for (int tx = 0; tx < L.ntx; tx++) {
@@ -82,14 +103,13 @@ void build_lists(mg_hierarchy *H, int l, int order) {
                 }
                 int t1 = tz;
                 if (l == 0) {
-                    while (t1 < L.ntz && hf[(t1 * L.nty + ty) * L.ntx + tx] && t1 - tz < SEG_TILES_FINE) t1++;
+                    const int per = depth / TZ;
+                    while (t1 < L.ntz && hf[(t1 * L.nty + ty) * L.ntx + tx] && t1 - tz < per) t1++;
                     segs.push_back(Seg{tx * TX, ty * TY, tz * TZ, std::min(L.nz, t1 * TZ)});
                 } else {
-                    // coarse levels: one active tile cut into item_depth(l)-plane items
                     t1 = tz + 1;
-                    const int dz = item_depth(l);
-                    for (int z = tz * TZ; z < std::min(L.nz, t1 * TZ); z += dz)
-                        segs.push_back(Seg{tx * TX, ty * TY, z, std::min(std::min(L.nz, t1 * TZ), z + dz)});
+                    for (int z = tz * TZ; z < std::min(L.nz, t1 * TZ); z += depth)
+                        segs.push_back(Seg{tx * TX, ty * TY, z, std::min(std::min(L.nz, t1 * TZ), z + depth)});
                 }
                 tz = t1;
             }
@@ -99,7 +119,7 @@ void build_lists(mg_hierarchy *H, int l, int order) {
         if (a.y0 != b.y0) return a.y0 < b.y0;
         return a.x0 < b.x0;
     });
-    OrderData &od = L.od[order];
+    od.depth = depth;
     od.ntiles = (int)tiles.size();
     od.nsegs = (int)segs.size();
     od.tiles = alloc_n<int>(H, std::max<size_t>(1, tiles.size()));
@@ -108,16 +128,17 @@ void build_lists(mg_hierarchy *H, int l, int order) {
         HIPCHK(hipMemcpyAsync(od.tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, H->stream));
     if (!segs.empty())
         HIPCHK(hipMemcpyAsync(od.segs, segs.data(), segs.size() * sizeof(Seg), hipMemcpyHostToDevice, H->stream));
-    const int npl = item_planes(l);
+    const int npl = depth + 4;
     od.pmask = alloc_n<unsigned long long>(H, std::max<size_t>(1, segs.size() * npl));
     launch_item_masks(L, l, order, od, npl, od.pmask, H->stream);
+    od.pmask2 = nullptr;
     if (H->opt.fuse_passes) {
-        const int npl2 = item_planes2(l);
+        const int npl2 = depth + 8;
         od.pmask2 = alloc_n<unsigned long long>(H, std::max<size_t>(1, segs.size() * npl2));
         launch_item_masks(L, l, order, od, npl2, od.pmask2, H->stream, 4);
     }
+    std::vector<Seg> s8;
     if (l == 1) {  // whole tiles for the FP64 prolongation pass
-        std::vector<Seg> s8;
         for (int ty = 0; ty < L.nty; ty++)
             for (int tx = 0; tx < L.ntx; tx++)
                 for (int tz = 0; tz < L.ntz; tz++)
@@ -144,6 +165,17 @@ void build_lists(mg_hierarchy *H, int l, int order) {
     HIPCHK(hipStreamSynchronize(H->stream));
 }
 
+// Frees the lists build_lists made (the stream must be idle).
+void free_lists(mg_hierarchy *H, OrderData &od) {
+    for (void *p : {(void *)od.tiles, (void *)od.segs, (void *)od.pmask, (void *)od.pmask2, (void *)od.segs8,
+                    (void *)od.pmask8})
+        dev_free(H, p);
+    od.tiles = nullptr;
+    od.segs = nullptr;
+    od.pmask = od.pmask2 = od.pmask8 = nullptr;
+    od.segs8 = nullptr;
+}
+
 mg_status validate_options(const mg_options &o) {
     if (o.n_pre < 0 || o.n_post < 0 || o.n_cycles < 1 || o.n_coarse_sweeps < 0 || o.min_coarse_dim < 1 ||
         o.max_cycles < 0 || (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.bc_order < 0 ||
@@ -155,7 +187,147 @@ mg_status validate_options(const mg_options &o) {
         set_error("n_cycles above 4 is not supported");
         return MG_ERR_ARG;
     }
+    if (o.tune < 0 || o.tune > 1 || (o.item_depth_fine && !depth_supported(0, o.item_depth_fine)) ||
+        (o.item_depth_l1 && !depth_supported(1, o.item_depth_l1)) ||
+        (o.item_depth_coarse && !depth_supported(2, o.item_depth_coarse))) {
+        set_error("invalid tune or item depth (finest: 8, 16, 32; coarse: 2, 4, 8)");
+        return MG_ERR_ARG;
+    }
+    if (o.fuse_passes && o.item_depth_fine && o.item_depth_fine != SEG_TILES_FINE * TZ) {
+        set_error("fuse_passes runs 16-plane finest work items only");
+        return MG_ERR_ARG;
+    }
     return MG_OK;
+}
+
+// ------------------------------------------------------------- tuning --
+
+// Item depth of level l fixed by the options (0: default or tuned).
+int forced_depth(const mg_options &o, int l) {
+    return l == 0 ? o.item_depth_fine : l == 1 ? o.item_depth_l1 : o.item_depth_coarse;
+}
+
+int start_depth(const mg_options &o, int l) {
+    const int f = forced_depth(o, l);
+    return f ? f : item_depth(l);
+}
+
+// The tuning cache: lines "<key> <depth>" in the file MG_TUNE_CACHE names.
+std::string tune_key(const mg_hierarchy *H, int l, int order, bool f32) {
+    const Level &L = H->lev[l];
+    char b[160];
+    snprintf(b, sizeof b, "gfx950:%dx%dx%d:l%d:o%d:%s:a%lld", H->lev[0].nx, H->lev[0].ny, H->lev[0].nz, l, order,
+             f32 ? "fp32" : "fp64", (long long)L.od[l == 0 ? 2 : order].nact);
+    return b;
+}
+
+int tune_cache_get(const std::string &key) {
+    const char *path = getenv("MG_TUNE_CACHE");
+    if (!path || !*path) return 0;
+    FILE *fp = fopen(path, "r");
+    if (!fp) return 0;
+    char k[200];
+    int d = 0, found = 0;
+    while (fscanf(fp, "%199s %d", k, &d) == 2)
+        if (key == k) found = d;  // the last entry wins
+    fclose(fp);
+    return found;
+}
+
+void tune_cache_put(const std::string &key, int depth) {
+    const char *path = getenv("MG_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *fp = fopen(path, "a");
+    if (!fp) return;
+    fprintf(fp, "%s %d\n", key.c_str(), depth);
+    fclose(fp);
+}
+
+// Average time of the work a cycle runs over the work items of od on
+// level l, with HIP events on the hierarchy's stream (best of three runs):
+// on coarse levels one smoother pass; on the finest level, which runs
+// several kernels over the same items, two passes, the residual with its
+// restriction and the pass forming its input's norm (FP64) or the update
+// with the outer residual (mixed).  At creation every iterate and
+// right-hand side buffer holds zeros, which this work keeps; it costs the
+// same on any values.
+float time_pass(mg_hierarchy *H, int l, const OrderData &od, bool f32) {
+    Level &L = H->lev[l];
+    const bool coarse = H->nlev[2] > 1;
+    auto pass = [&](int p) {
+        if (f32) launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream);
+        else launch_rbgs(L, l, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, H->stream);
+        if (l != 0 || (p & 1) == 0) return;
+        if (f32) {
+            if (coarse) launch_restrict32(L, H->lev[1], 0, 2, L.x32[0], L.f32, H->lev[1].f32, H->stream);
+            launch_axpy_resnorm32(L, od, L.x[0], L.x32[0], L.x[1], L.f, L.f32, H->part, H->norm_dev, 0, H->stream,
+                                  nullptr);
+        } else {
+            if (coarse) launch_restrict(L, H->lev[1], 0, 2, L.x[0], L.f, H->lev[1].f, H->stream);
+            launch_rbgs_norm(L, od, L.x[0], L.x[1], L.f, H->part, H->stream);
+        }
+    };
+    // the restriction march reads the finest lists from the level itself
+    const OrderData saved = L.od[2];
+    if (l == 0) L.od[2] = od;
+    const int n = l == 0 ? 10 : 20;
+    for (int p = 0; p < 4; p++) pass(p);
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; rep++) {
+        HIPCHK(hipEventRecord(H->ev0, H->stream));
+        for (int p = 0; p < n; p++) pass(p);
+        HIPCHK(hipEventRecord(H->ev1, H->stream));
+        HIPCHK(hipEventSynchronize(H->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, H->ev0, H->ev1));
+        best = std::min(best, ms);
+    }
+    L.od[2] = saved;
+    return best / n;
+}
+
+// Picks the planes per work item of every level and order that its
+// smoother passes run fastest with (each candidate timed on this
+// hierarchy), unless the options fix it; levels run by the one-workgroup
+// kernel take no work items.  The precision timed is the one the level's
+// passes run in (FP32 for a mixed-precision hierarchy).
+void tune_depths(mg_hierarchy *H) {
+    const bool f32 = H->opt.precision == MG_MIXED;
+    for (int l = 0; l < std::max(H->nlev[1], H->nlev[2]); l++)
+        for (int o = 2; o >= 1; o--) {
+            if (l == 0 && o == 1) continue;  // the finest level is the same in both orders
+            if (l >= H->nlev[o] || (H->ls[o] >= 0 && l >= H->ls[o])) continue;
+            if (forced_depth(H->opt, l) || (l == 0 && H->opt.fuse_passes)) continue;
+            OrderData &od = H->lev[l].od[o];
+            if (od.nsegs == 0) continue;
+            const std::string key = tune_key(H, l, o, f32);
+            int best = tune_cache_get(key);
+            if (!depth_supported(l, best)) {
+                const int cand0[3] = {8, 16, 32}, cand1[3] = {2, 4, 8};
+                const int *cand = l == 0 ? cand0 : cand1;
+                float tbest = time_pass(H, l, od, f32);
+                best = od.depth;
+                for (int c = 0; c < 3; c++) {
+                    if (cand[c] == od.depth) continue;
+                    OrderData t = od;
+                    build_lists(H, l, o, cand[c], t);
+                    const float tc = time_pass(H, l, t, f32);
+                    HIPCHK(hipStreamSynchronize(H->stream));
+                    if (tc < tbest) {
+                        tbest = tc;
+                        best = cand[c];
+                    }
+                    free_lists(H, t);
+                }
+                tune_cache_put(key, best);
+            }
+            if (best != od.depth) {
+                HIPCHK(hipStreamSynchronize(H->stream));
+                free_lists(H, od);
+                build_lists(H, l, o, best, od);
+            }
+        }
+    H->lev[0].od[1] = H->lev[0].od[2];
 }
 
 void create(mg_hierarchy *H, const int8_t *mask, int nx, int ny, int nz, double h) {
@@ -223,11 +395,11 @@ void create(mg_hierarchy *H, const int8_t *mask, int nx, int ny, int nz, double 
             if (lev[l].od[o].nact > 0 && H->nlev[o] == l) H->nlev[o] = l + 1;
         }
     }
-    // active tile lists
-    build_lists(H, 0, 2);
+    // active tile lists and work items (default or fixed depths; tuned below)
+    build_lists(H, 0, 2, start_depth(H->opt, 0), lev[0].od[2]);
     lev[0].od[1] = lev[0].od[2];
     for (int o = 1; o <= 2; o++)
-        for (int l = 1; l < H->nlev[o]; l++) build_lists(H, l, o);
+        for (int l = 1; l < H->nlev[o]; l++) build_lists(H, l, o, start_depth(H->opt, l), lev[l].od[o]);
     // level buffers
     const int nl = std::max(H->nlev[1], H->nlev[2]);
     const bool mixed = H->opt.precision == MG_MIXED;
@@ -283,6 +455,8 @@ void create(mg_hierarchy *H, const int8_t *mask, int nx, int ny, int nz, double 
     HIPCHK(hipEventCreate(&H->ev0));
     HIPCHK(hipEventCreate(&H->ev1));
     for (int q = 0; q < 2; q++) HIPCHK(hipEventCreateWithFlags(&H->evq[q], hipEventDisableTiming));
+    HIPCHK(hipStreamSynchronize(s));
+    if (H->opt.tune) tune_depths(H);
     HIPCHK(hipStreamSynchronize(s));
     H->coarse_order_state = 0;
 }
@@ -1011,6 +1185,11 @@ mg_status mg_level_dims(const mg_hierarchy *H, int32_t level, int32_t *dims_out)
     dims_out[1] = H->lev[level].ny;
     dims_out[2] = H->lev[level].nz;
     return MG_OK;
+}
+
+int32_t mg_level_item_depth(const mg_hierarchy *H, int32_t level, int32_t order) {
+    if (!H || level < 0 || (order != 1 && order != 2) || level >= H->nlev[order]) return -1;
+    return H->lev[level].od[level == 0 ? 2 : order].depth;
 }
 
 int64_t mg_level_active(const mg_hierarchy *H, int32_t level, int32_t order) {

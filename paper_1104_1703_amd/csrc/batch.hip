@@ -579,6 +579,9 @@ void build_batch(mg_batch *B, const int8_t *const *masks, const int32_t *dims, c
     for (int p = 0; p < n; p++) {
         mg_options o = B->opt;
         o.use_graph = 1;  // the lockstep engine replays each patch's captured cycle
+        // the phase kernels are instances for the default work-item depths
+        o.tune = 0;
+        o.item_depth_fine = o.item_depth_l1 = o.item_depth_coarse = 0;
         mg_hierarchy *H = nullptr;
         const mg_status st =
             mg_create_hierarchy(masks[p], dims[3 * p], dims[3 * p + 1], dims[3 * p + 2], h[p], &o, B->stream, &H);
@@ -838,6 +841,11 @@ mg_status mg_create_batch(int32_t n, const int8_t *const *masks_dev, const int32
     else mg_default_options(&B->opt);
     if (B->opt.precision != MG_FP64) {
         set_error("the batched solver runs in FP64");
+        delete B;
+        return MG_ERR_ARG;
+    }
+    if (B->opt.tune || B->opt.item_depth_fine || B->opt.item_depth_l1 || B->opt.item_depth_coarse) {
+        set_error("the batched solver runs the default work-item depths (no tuning)");
         delete B;
         return MG_ERR_ARG;
     }

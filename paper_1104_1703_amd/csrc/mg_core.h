@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mg.h"
@@ -22,12 +23,23 @@ constexpr int MAXS = 8;                    // levels handled by the one-workgrou
 constexpr size_t SMALL_MAX_CELLS = 4096;   // first level handled there has at most this many cells
 constexpr int SMALL_LDS_MAX = 160 * 1024;  // LDS of one gfx950 workgroup
 
-// Planes per smoother work item (its z range plus the two-plane halo on each side).
+// Default planes per smoother work item of a level (a hierarchy may use other
+// depths with kernel instances: 8, 16, 32 on the finest level, 2, 4, 8 on
+// coarse levels; OrderData::depth holds the one in use).
 constexpr int item_depth(int level) {
     return level == 0 ? SEG_TILES_FINE * TZ : level == 1 ? SEGZ_COARSE1 : SEGZ_COARSE;
 }
-constexpr int item_planes(int level) { return item_depth(level) + 4; }
-constexpr int item_planes2(int level) { return item_depth(level) + 8; }  // fused pairs of passes
+constexpr bool depth_supported(int level, int depth) {
+    return level == 0 ? (depth == 8 || depth == 16 || depth == 32) : (depth == 2 || depth == 4 || depth == 8);
+}
+// Calls f(std::integral_constant<int, D>()) with D the finest-level item depth
+// in use (the kernel instance to launch).
+template <typename F>
+inline void with_fine_depth(int depth, F &&f) {
+    if (depth == 8) f(std::integral_constant<int, 8>());
+    else if (depth == 32) f(std::integral_constant<int, 32>());
+    else f(std::integral_constant<int, 16>());
+}
 
 // Stop test of the solve loop evaluated on the device by the norm's final
 // sum (the same FP64 comparisons as the host's): halt when sqrt(sum) <= thresh,
@@ -52,6 +64,7 @@ struct OrderData {
     unsigned long long *pmask8 = nullptr;
     int nsegs8 = 0;
     int ntiles = 0, nsegs = 0;
+    int depth = 0;  // planes per work item of segs (its masks hold depth + 4 words per item)
     int64_t nact = 0;
 };
 

@@ -154,7 +154,7 @@ __global__ void k_item_masks(const int32_t *__restrict__ cnt, int nx, int ny, in
                              const Seg *__restrict__ segs, int npl, unsigned long long *__restrict__ pm) {
     constexpr int RY = TY + 2 * HH, RX = TX + 2 * HH;
     static_assert(4 * RY <= 64, "one 64-bit word per plane");
-    __shared__ unsigned rowbits[(SEG_TILES_FINE * TZ + 2 * HH) * RY];
+    __shared__ unsigned rowbits[(SEGZ_FINE_MAX + 2 * HH) * RY];
     const Seg sg = segs[blockIdx.x];
     for (int r = threadIdx.x; r < npl * RY; r += blockDim.x) {
         const int pi = r / RY, v = r % RY;

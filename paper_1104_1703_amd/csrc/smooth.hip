@@ -49,6 +49,7 @@ __global__ __launch_bounds__(NT, 5) void k_rbgs(const T *__restrict__ xin, T *__
 
 // The finest pass that also forms the residual-norm partials of its input,
 // one per work item, as the residual-norm march does.
+template <int SZ>
 __global__ __launch_bounds__(NT, 5) void k_rbgs_norm(const double *__restrict__ xin, double *__restrict__ xout,
                                                    const double *__restrict__ f, const uint8_t *__restrict__ code,
                                                    int nx, int ny, int nz, double h2, double ih2,
@@ -58,7 +59,6 @@ __global__ __launch_bounds__(NT, 5) void k_rbgs_norm(const double *__restrict__ 
     __shared__ RbgsLds<double, true, false> lds;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= nsegs || (halt && *halt)) return;
-    constexpr int SZ = SEG_TILES_FINE * TZ;
     const double sq = rbgs_item<double, true, SZ, false, true>(lds, xin, xout, f, code, nullptr, nx, ny, nz, h2,
                                                                segs[item], pm + (size_t)item * (SZ + 4), nullptr, 0,
                                                                0, 0, ih2);
@@ -110,17 +110,22 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
     if (od.nsegs == 0) return;
     const double h2 = L.h * L.h;
     if (level == 0)
-        k_rbgs<double, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
-            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
+        with_fine_depth(od.depth, [&](auto Z) {
+            k_rbgs<double, true, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(
+                xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
+        });
     else
-        launch_coarse<double>(item_depth(level), xin, xout, f, od.d, L, od, h2, s);
+        launch_coarse<double>(od.depth, xin, xout, f, od.d, L, od, h2, s);
 }
 
 void launch_rbgs_norm(const Level &L, const OrderData &od, const double *xin, double *xout, const double *f,
                       double *part, hipStream_t s) {
     if (od.nsegs == 0) return;
-    k_rbgs_norm<<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, L.nx, L.ny, L.nz, L.h * L.h, 1.0 / (L.h * L.h),
-                                               od.segs, od.pmask, od.nsegs, L.halt, part);
+    with_fine_depth(od.depth, [&](auto Z) {
+        k_rbgs_norm<decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, L.nx, L.ny, L.nz, L.h * L.h,
+                                                                       1.0 / (L.h * L.h), od.segs, od.pmask, od.nsegs,
+                                                                       L.halt, part);
+    });
 }
 
 void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const Level &C, const double *xc,
@@ -128,15 +133,17 @@ void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const L
     if (od.nsegs == 0) return;
     const double h2 = L.h * L.h;
     if (level == 0)
-        k_rbgs<double, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
-            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx, C.ny,
-            C.nz);
+        with_fine_depth(od.depth, [&](auto Z) {
+            k_rbgs<double, true, decltype(Z)::value, true><<<grid8(od.nsegs), NT, 0, s>>>(
+                xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx,
+                C.ny, C.nz);
+        });
     else if (level == 1 && od.nsegs8 > 0)  // whole tiles: one round at 4 blocks per CU
         k_rbgs<double, false, TZ, true><<<grid8(od.nsegs8), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz,
                                                                       h2, od.segs8, od.pmask8, od.nsegs8, L.halt, xc,
                                                                       C.nx, C.ny, C.nz);
     else
-        launch_coarse<double, true>(item_depth(level), xin, xout, f, od.d, L, od, h2, s, xc, &C);
+        launch_coarse<double, true>(od.depth, xin, xout, f, od.d, L, od, h2, s, xc, &C);
 }
 
 void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const Level &C, const float *xc,
@@ -144,11 +151,13 @@ void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const
     if (od.nsegs == 0) return;
     const float h2 = (float)(L.h * L.h);
     if (level == 0)
-        k_rbgs<float, true, SEG_TILES_FINE * TZ, true><<<grid8(od.nsegs), NT, 0, s>>>(
-            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx, C.ny,
-            C.nz);
+        with_fine_depth(od.depth, [&](auto Z) {
+            k_rbgs<float, true, decltype(Z)::value, true><<<grid8(od.nsegs), NT, 0, s>>>(
+                xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx,
+                C.ny, C.nz);
+        });
     else
-        launch_coarse<float, true>(item_depth(level), xin, xout, f, od.d32, L, od, h2, s, xc, &C);
+        launch_coarse<float, true>(od.depth, xin, xout, f, od.d32, L, od, h2, s, xc, &C);
 }
 
 template <typename T>
@@ -159,10 +168,10 @@ void launch_fused(const Level &L, int level, const OrderData &od, const T *xin, 
     if (level == 0)
         k_rbgs2<T, true, SEG_TILES_FINE * TZ><<<g, NT, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2,
                                                                od.segs, od.pmask2, od.nsegs, L.halt);
-    else if (item_depth(level) == 8)
+    else if (od.depth == 8)
         k_rbgs2<T, false, 8><<<g, NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs, od.pmask2,
                                               od.nsegs, L.halt);
-    else if (item_depth(level) == 4)
+    else if (od.depth == 4)
         k_rbgs2<T, false, 4><<<g, NT, 0, s>>>(xin, xout, f, nullptr, d, L.nx, L.ny, L.nz, h2, od.segs, od.pmask2,
                                               od.nsegs, L.halt);
     else
@@ -201,10 +210,12 @@ void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *
     if (od.nsegs == 0) return;
     const float h2 = (float)(L.h * L.h);
     if (level == 0)
-        k_rbgs<float, true, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
-            xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
+        with_fine_depth(od.depth, [&](auto Z) {
+            k_rbgs<float, true, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(
+                xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
+        });
     else
-        launch_coarse<float>(item_depth(level), xin, xout, f, od.d32, L, od, h2, s);
+        launch_coarse<float>(od.depth, xin, xout, f, od.d32, L, od, h2, s);
 }
 
 }  // namespace mg

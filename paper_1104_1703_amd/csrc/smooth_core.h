@@ -62,7 +62,7 @@ struct Rings {
 };
 constexpr int CX = BX / 2 + 4, CY = BY / 2 + 4, CPN = CX * CY;
 static_assert(CPN <= NT, "one coarse element per thread");
-constexpr int MAXPL = SEG_TILES_FINE * TZ + 4;  // planes touched by the longest work item
+constexpr int MAXPL = SEGZ_FINE_MAX + 4;  // planes touched by the longest work item
 template <typename T, bool FINE, bool PRO = false>
 struct RbgsLds {
     using DT = typename std::conditional<FINE, uint8_t, T>::type;

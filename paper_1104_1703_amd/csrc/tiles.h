@@ -10,9 +10,10 @@ namespace mg {
 constexpr int TX = 32;  // tile width along x (one 256-byte row of doubles)
 constexpr int TY = 8;
 constexpr int TZ = 8;
-constexpr int SEG_TILES_FINE = 2;    // z-tiles per smoother work item on the finest level
-constexpr int SEGZ_COARSE1 = 4;      // planes per smoother work item on level 1
-constexpr int SEGZ_COARSE = 2;       // planes per smoother work item on coarser levels (latency-bound: short marches)
+constexpr int SEG_TILES_FINE = 2;    // default z-tiles per smoother work item on the finest level
+constexpr int SEGZ_COARSE1 = 4;      // default planes per smoother work item on level 1
+constexpr int SEGZ_COARSE = 2;       // default planes per smoother work item on coarser levels (latency-bound: short marches)
+constexpr int SEGZ_FINE_MAX = 32;    // longest finest-level work item with kernel instances (8, 16, 32 planes)
 // Finest-level cell code: the diagonal of the cell's equation, 12 - (number
 // of active face neighbours) = 6..12 for an active cell, CODE_OFF if inactive.
 constexpr uint8_t CODE_OFF = 0;

@@ -278,9 +278,11 @@ void launch_resnorm(const Level &L, int level, const OrderData &od, const double
     const double ih2 = 1.0 / (L.h * L.h);
     if (level == 0) {
         if (od.nsegs)
-            k_residual_march<double, SEG_TILES_FINE * TZ, RM_NORM><<<grid8(od.nsegs), NT, 0, s>>>(
-                x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part,
-                nullptr, nullptr, nullptr, L.halt);
+            with_fine_depth(od.depth, [&](auto Z) {
+                k_residual_march<double, decltype(Z)::value, RM_NORM><<<grid8(od.nsegs), NT, 0, s>>>(
+                    x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part,
+                    nullptr, nullptr, nullptr, L.halt);
+            });
         k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
         return;
     }
@@ -305,9 +307,11 @@ void launch_resnorm32(const Level &L, const OrderData &od, const double *x, cons
                       double *out, int slot, hipStream_t s) {
     const double ih2 = 1.0 / (L.h * L.h);
     if (od.nsegs)
-        k_residual_march<double, SEG_TILES_FINE * TZ, RM_NORM32><<<grid8(od.nsegs), NT, 0, s>>>(
-            x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32,
-            nullptr, nullptr, L.halt);
+        with_fine_depth(od.depth, [&](auto Z) {
+            k_residual_march<double, decltype(Z)::value, RM_NORM32><<<grid8(od.nsegs), NT, 0, s>>>(
+                x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32,
+                nullptr, nullptr, L.halt);
+        });
     k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, nullptr, halt_rw(L));
 }
 
@@ -316,9 +320,11 @@ void launch_axpy_resnorm32(const Level &L, const OrderData &od, const double *x,
                            const StopTest *stop) {
     const double ih2 = 1.0 / (L.h * L.h);
     if (od.nsegs)
-        k_residual_march<double, SEG_TILES_FINE * TZ, RM_AXPY32><<<grid8(od.nsegs), NT, 0, s>>>(
-            x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32, e,
-            xo, L.halt);
+        with_fine_depth(od.depth, [&](auto Z) {
+            k_residual_march<double, decltype(Z)::value, RM_AXPY32><<<grid8(od.nsegs), NT, 0, s>>>(
+                x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32, e,
+                xo, L.halt);
+        });
     k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
 }
 
@@ -342,9 +348,11 @@ void launch_restrict(const Level &L, const Level &C, int level, int order, const
     if (level == 0) {
         const OrderData &fo = L.od[2];
         if (fo.nsegs)
-            k_residual_march<double, SEG_TILES_FINE * TZ, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
-                x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d, C.nx, C.ny, fc, nullptr,
-                nullptr, nullptr, nullptr, L.halt);
+            with_fine_depth(fo.depth, [&](auto Z) {
+                k_residual_march<double, decltype(Z)::value, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
+                    x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d, C.nx, C.ny, fc, nullptr,
+                    nullptr, nullptr, nullptr, L.halt);
+            });
     } else
         k_restrict<double, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny,
                                                                   C.nz, co.d, L.nx, L.ny, L.nz, ih2, nullptr,
@@ -359,9 +367,11 @@ void launch_restrict32(const Level &L, const Level &C, int level, int order, con
     if (level == 0) {
         const OrderData &fo = L.od[2];
         if (fo.nsegs)
-            k_residual_march<float, SEG_TILES_FINE * TZ, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
-                x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d32, C.nx, C.ny, fc, nullptr,
-                nullptr, nullptr, nullptr, L.halt);
+            with_fine_depth(fo.depth, [&](auto Z) {
+                k_residual_march<float, decltype(Z)::value, RM_RESTRICT><<<grid8(fo.nsegs), NT, 0, s>>>(
+                    x, f, L.code, L.nx, L.ny, L.nz, ih2, fo.segs, fo.pmask, fo.nsegs, co.d32, C.nx, C.ny, fc, nullptr,
+                    nullptr, nullptr, nullptr, L.halt);
+            });
     } else
         k_restrict<float, false><<<gridt(co.ntiles), NT, 0, s>>>(co.tiles, co.ntiles, C.ntx, C.nty, C.nx, C.ny, C.nz,
                                                                  co.d32, L.nx, L.ny, L.nz, ih2, nullptr,
@@ -374,8 +384,10 @@ void launch_prolong(const Level &L, const Level &C, int level, int order, const 
     if (!od.ntiles) return;
     if (level == 0) {
         if (od.nsegs)
-            k_prolong_march<double, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
-                L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs, L.halt);
+            with_fine_depth(od.depth, [&](auto Z) {
+                k_prolong_march<double, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(
+                    L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs, L.halt);
+            });
     } else
         k_prolong<double, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
                                                                  nullptr, od.d, xc, C.nx, C.ny, C.nz, x, L.halt);
@@ -387,8 +399,10 @@ void launch_prolong32(const Level &L, const Level &C, int level, int order, cons
     if (!od.ntiles) return;
     if (level == 0) {
         if (od.nsegs)
-            k_prolong_march<float, SEG_TILES_FINE * TZ><<<grid8(od.nsegs), NT, 0, s>>>(
-                L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs, L.halt);
+            with_fine_depth(od.depth, [&](auto Z) {
+                k_prolong_march<float, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(
+                    L.code, xc, C.nx, C.ny, C.nz, x, L.nx, L.ny, L.nz, od.segs, od.pmask, od.nsegs, L.halt);
+            });
     } else
         k_prolong<float, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny, L.nz,
                                                                 nullptr, od.d32, xc, C.nx, C.ny, C.nz, x, L.halt);

@@ -32,7 +32,9 @@ class Options(C.Structure):
     _fields_ = [("n_pre", C.c_int32), ("n_post", C.c_int32), ("n_cycles", C.c_int32), ("n_coarse_sweeps", C.c_int32),
                 ("min_coarse_dim", C.c_int32), ("max_cycles", C.c_int32), ("precision", C.c_int32),
                 ("bc_order", C.c_int32), ("eta", C.c_double), ("first_order_hold", C.c_int32),
-                ("use_graph", C.c_int32), ("fuse_passes", C.c_int32), ("allocator", Allocator)]
+                ("use_graph", C.c_int32), ("fuse_passes", C.c_int32), ("tune", C.c_int32),
+                ("item_depth_fine", C.c_int32), ("item_depth_l1", C.c_int32), ("item_depth_coarse", C.c_int32),
+                ("allocator", Allocator)]
 
 
 class SolveInfo(C.Structure):
@@ -63,6 +65,7 @@ SYMBOLS = [
     ("mg_num_levels", _I, [_P, _I]),
     ("mg_level_dims", C.c_int, [_P, _I, C.POINTER(_I)]),
     ("mg_level_active", C.c_int64, [_P, _I, _I]),
+    ("mg_level_item_depth", C.c_int32, [_P, _I, _I]),
     ("mg_level_counts", C.c_int, [_P, _I, _P]),
     ("mg_level_diag", C.c_int, [_P, _I, _I, _P]),
     ("mg_fold", C.c_int, [_P, _P, _P, _P]),
@@ -271,6 +274,14 @@ class Hierarchy:
 
     def n_active(self, level: int = 0, order: int = 2) -> int:
         return int(load_library().mg_level_active(self._h, level, order))
+
+    def item_depth(self, level: int = 0, order: int = 2) -> int:
+        """Planes per smoother work item of a level (default, given or tuned)."""
+        return int(load_library().mg_level_item_depth(self._h, level, order))
+
+    def item_depths(self):
+        """{order: [depth of each level]} for both boundary orders."""
+        return {o: [self.item_depth(l, o) for l in range(self.nlevels(o))] for o in (1, 2)}
 
     def counts(self, level: int) -> torch.Tensor:
         out = torch.empty(self.dims(level), dtype=torch.int32, device=self.device)
