@@ -68,10 +68,13 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--variants", default="mixed,interp,learned,learned_mixed",
+    ap.add_argument("--variants", default="mixed,interp,learned,learned_s1,learned_s2,learned_mixed",
                     help="comma list of extra variants timed beside fp64: mixed (FP32 inner / FP64 outer), "
-                         "interp (coarse-solve guess), learned (U-Net guess), learned_mixed")
+                         "interp (coarse-solve guess), learned (U-Net guess at --learned-stride), learned_sK "
+                         "(U-Net at stride K), learned_mixed")
     ap.add_argument("--learned-stride", type=int, default=4, help="U-Net runs on the 1/stride grid")
+    ap.add_argument("--no-learned-eval", dest="learned_eval", action="store_false",
+                    help="skip the sphere-geometry evaluation of the learned guess at strides 1, 2, 4")
     ap.add_argument("--batch-patches", type=int, default=512,
                     help="patches of the batched workload timed beside the main line (0: skip)")
     ap.add_argument("--large-n", type=int, default=512,
@@ -89,6 +92,8 @@ def parse():
     ap.add_argument("--schedules", type=int, default=0, metavar="N",
                     help="study: the sphere at N^3 to 1e-10 with N_cycles 1, 2, 3 in each boundary order "
                          "(cycles, mean rate, ms), exit")
+    ap.add_argument("--schedules-workload", choices=("sphere", "holes"), default="sphere",
+                    help="domain of --schedules: the sphere or the holes workload (adds AUTO order)")
     ap.add_argument("--amr", default="", metavar="N,N,...",
                     help="study: one-way nested levels (3 refinements) of the ln profile at these base sizes: "
                          "errors, orders and time, exit")
@@ -245,7 +250,7 @@ def large_measurement(args):
     phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
     res, phi64 = {}, None
     for prec in ("fp64", "mixed"):
-        H = mg.Hierarchy(mask, p.h, precision=prec)
+        H = mg.Hierarchy(mask, p.h, precision=prec, tune=1)
         walls, info = [], None
         for rep in range(4):
             phi.zero_()
@@ -256,7 +261,8 @@ def large_measurement(args):
             if rep:
                 walls.append(time.perf_counter() - t0)
         r = {"ms": round(float(np.median(walls)) * 1e3, 3), "cycles": info["cycles"],
-             "switched_at": info["switched_at"], "final_rel_residual": info["r_final"] / info["r_ref"]}
+             "switched_at": info["switched_at"], "final_rel_residual": info["r_final"] / info["r_ref"],
+             "item_depths": H.item_depths()}
         if prec == "fp64":
             n_act = H.n_active(0)
             H.time_smoother(4)
@@ -350,31 +356,36 @@ def schedules(args):
     import torch
 
     from paper_1104_1703_amd import gen, mg
-    p = gen.sphere_problem(args.schedules)
+    p = gen.holes_problem(args.schedules, seed=2) if args.schedules_workload == "holes" else \
+        gen.sphere_problem(args.schedules)
     dev = torch.device("cuda:0")
     mask = torch.from_numpy(p.mask).to(dev)
     rho = torch.from_numpy(p.rho).to(dev)
     phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
     rows = []
+    orders = ("second", "first", "auto") if args.schedules_workload == "holes" else ("second", "first")
     for nc in (1, 2, 3):
-        for bo in ("second", "first"):
-            H = mg.Hierarchy(mask, p.h, n_cycles=nc, bc_order=bo)
+        for bo in orders:
+            H = mg.Hierarchy(mask, p.h, n_cycles=nc, bc_order=bo, tune=1)
             walls, info = [], None
             for rep in range(4):
                 phi.zero_()
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                info = H.solve(rho, phi, None, tol=args.tol)[1]
+                info = H.solve(rho, phi, None, tol=args.tol, check=False)[1]
                 torch.cuda.synchronize()
                 if rep:
                     walls.append(time.perf_counter() - t0)
             h = info["history"]
-            rows.append({"n_cycles": nc, "order": bo, "cycles": info["cycles"],
+            rows.append({"n_cycles": nc, "order": bo, "status": info["status"], "cycles": info["cycles"],
                          "mean_rate": (h[-1] / h[0]) ** (1.0 / max(1, info["cycles"])),
                          "ms": round(float(np.median(walls)) * 1e3, 3)})
             H.close()
-    print(json.dumps({"mode": "schedules", "workload": f"sphere{args.schedules}: R = 0.4 Dirichlet 0, "
-                      f"rho = 1 inside r = 0.2, tol {args.tol:g}", "rows": rows}), flush=True)
+    what = (f"holes{args.schedules} (seed 2; AUTO: the untimed first solve switches order, the timed ones "
+            f"start held in first order)"
+            if args.schedules_workload == "holes" else
+            f"sphere{args.schedules}: R = 0.4 Dirichlet 0, rho = 1 inside r = 0.2")
+    print(json.dumps({"mode": "schedules", "workload": f"{what}, tol {args.tol:g}", "rows": rows}), flush=True)
 
 
 def profile_batch(args):
@@ -495,7 +506,7 @@ def main():
     rho = torch.from_numpy(p.rho).to(dev)
     phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
 
-    def time_solves(H, make_guess=None):
+    def time_solves(H, make_guess=None, prho=None, pphi=None):
         """W warm-up then K timed solves on one fresh hierarchy, each solve
         timed alone (wall clock, synchronised) and recorded with its regime:
         a solve that starts in second order and switches, or one that starts
@@ -503,12 +514,15 @@ def main():
         cycle counts, so both the mean over the K solves (`value`) and the
         per-regime figures are reported.  Every variant runs the same
         schedule on its own fresh hierarchy."""
+        prho = rho if prho is None else prho
+        pphi = phi if pphi is None else pphi
+
         def step():
             if make_guess is None:
-                phi.zero_()
+                pphi.zero_()
             else:
-                make_guess(phi)
-            return H.solve(rho, phi, None, tol=args.tol)[1]
+                make_guess(pphi)
+            return H.solve(prho, pphi, None, tol=args.tol)[1]
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -538,8 +552,9 @@ def main():
             r["switched_at"] = sorted(set(r["switched_at"]))
         return out
 
-    H = mg.Hierarchy(mask, p.h, precision="fp64")
+    H = mg.Hierarchy(mask, p.h, precision="fp64", tune=1)
     n_act = H.n_active(0)
+    depths64 = H.item_depths()
     ms_wall, infos64, walls64 = time_solves(H)
     last = infos64[-1]
     reg64 = regimes(infos64, walls64)
@@ -561,53 +576,86 @@ def main():
     phi64 = phi.clone()
     H.close()
 
-    variants = {}
-    net = None
-    for v in [x for x in args.variants.split(",") if x]:
-        precision = "mixed" if v in ("mixed", "learned_mixed") else "fp64"
-        make_guess, extra, ig = None, {}, None
-        if v == "interp":
-            from paper_1104_1703_amd import guess
-            ig = guess.InterpolatedGuess(mask, p.h)
-            make_guess = lambda out: ig(rho, out=out)
-            extra["guess"] = "problem coarsened by 2 per axis, FP64 multigrid to 1e-4, linear up-sampling"
-        elif v in ("learned", "learned_mixed"):
-            from paper_1104_1703_amd import guess
-            if net is None:
+    net_box = {}
+
+    def network():
+        from paper_1104_1703_amd import guess
+        if "net" not in net_box:
+            net_box["net"] = guess.load_network(args.weights or guess.WEIGHTS)
+        return net_box["net"]
+
+    def measure_variants(names, prob, pmask, prho, base_reg, base_ms, base_phi):
+        """Each variant on its own fresh (tuned) hierarchy with the same
+        schedule as the FP64 zero-guess line, guess included in the time."""
+        out_v = {}
+        for v in names:
+            precision = "mixed" if v in ("mixed", "learned_mixed") else "fp64"
+            make_guess, extra, ig = None, {}, None
+            if v == "interp":
+                from paper_1104_1703_amd import guess
+                ig = guess.InterpolatedGuess(pmask, prob.h, tune=1)
+                make_guess = lambda out: ig(prho, out=out)
+                extra["guess"] = "problem coarsened by 2 per axis, FP64 multigrid to 1e-4, linear up-sampling"
+            elif v.startswith("learned"):
                 try:
-                    net = guess.load_network(args.weights or guess.WEIGHTS)
+                    net = network()
                 except FileNotFoundError as e:
-                    variants[v] = {"skipped": str(e)}
+                    out_v[v] = {"skipped": str(e)}
                     continue
-            stride = args.learned_stride
-            make_guess = lambda out: net.infer(rho, mask, stride=stride, out=out)
-            for _ in range(3):
-                make_guess(phi)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(10):
-                make_guess(phi)
-            torch.cuda.synchronize()
-            extra["guess"] = f"U-Net at 1/{stride} resolution, linear up-sampling"
-            extra["guess_ms"] = round((time.perf_counter() - t0) / 10 * 1e3, 4)
-        elif v != "mixed":
-            raise SystemExit(f"unknown variant {v}")
-        Hv = mg.Hierarchy(mask, p.h, precision=precision)
-        v_wall, v_infos, v_walls = time_solves(Hv, make_guess)
-        v_last = v_infos[-1]
-        v_reg = regimes(v_infos, v_walls)
-        for k, r in v_reg.items():
-            if k in reg64:
-                r["speedup_vs_fp64"] = round(reg64[k]["ms_mean"] / r["ms_mean"], 3)
-        diff = float((phi - phi64).abs().max() / phi64.abs().max())
-        variants[v] = {"ms": round(v_wall, 4), "speedup_vs_fp64": round(ms_wall / v_wall, 3),
-                       "regimes": v_reg, "cycles_mean": float(np.mean([i["cycles"] for i in v_infos])),
-                       "final_rel_residual": v_last["r_final"] / v_last["r_ref"],
-                       "initial_rel_residual": v_last["r0"] / v_last["r_ref"],
-                       "max_rel_diff_vs_fp64_solution": diff, **extra}
-        Hv.close()
-        if ig is not None:
-            ig.close()
+                stride = int(v[len("learned_s"):]) if v.startswith("learned_s") else args.learned_stride
+                make_guess = lambda out, stride=stride: net.infer(prho, pmask, stride=stride, out=out)
+                for _ in range(3):
+                    make_guess(phi_v)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(10):
+                    make_guess(phi_v)
+                torch.cuda.synchronize()
+                extra["guess"] = f"U-Net at 1/{stride} resolution, linear up-sampling"
+                extra["guess_ms"] = round((time.perf_counter() - t0) / 10 * 1e3, 4)
+            elif v != "mixed":
+                raise SystemExit(f"unknown variant {v}")
+            Hv = mg.Hierarchy(pmask, prob.h, precision=precision, tune=1)
+            v_wall, v_infos, v_walls = time_solves(Hv, make_guess, prho, phi_v)
+            v_last = v_infos[-1]
+            v_reg = regimes(v_infos, v_walls)
+            for k, r in v_reg.items():
+                if k in base_reg:
+                    r["speedup_vs_fp64"] = round(base_reg[k]["ms_mean"] / r["ms_mean"], 3)
+            diff = float((phi_v - base_phi).abs().max() / base_phi.abs().max())
+            out_v[v] = {"ms": round(v_wall, 4), "speedup_vs_fp64": round(base_ms / v_wall, 3),
+                        "regimes": v_reg, "cycles_mean": float(np.mean([i["cycles"] for i in v_infos])),
+                        "final_rel_residual": v_last["r_final"] / v_last["r_ref"],
+                        "initial_rel_residual": v_last["r0"] / v_last["r_ref"],
+                        "max_rel_diff_vs_fp64_solution": diff, "item_depths": Hv.item_depths(), **extra}
+            Hv.close()
+            if ig is not None:
+                ig.close()
+        return out_v
+
+    phi_v = phi
+    variants = measure_variants([x for x in args.variants.split(",") if x], p, mask, rho, reg64, ms_wall, phi64)
+
+    # Learned guess on both readings of "applied at 256^3 like config 1":
+    # the 256^3 sphere geometry (config 1's domain) next to the zero and
+    # interpolated starts, at network strides 1, 2 and 4
+    learned_eval = None
+    if args.learned_eval:
+        ps = gen.sphere_problem(args.n)
+        smask = torch.from_numpy(ps.mask).to(dev)
+        srho = torch.from_numpy(ps.rho).to(dev)
+        phi_v = torch.zeros(ps.shape, dtype=torch.float64, device=dev)
+        Hs = mg.Hierarchy(smask, ps.h, precision="fp64", tune=1)
+        s_wall, s_infos, s_walls = time_solves(Hs, None, srho, phi_v)
+        s_reg = regimes(s_infos, s_walls)
+        s_phi = phi_v.clone()
+        Hs.close()
+        learned_eval = {
+            "workload": f"sphere{args.n}: R = 0.4 Dirichlet 0, rho = 1 inside r = 0.2, tol {args.tol:g}",
+            "zero": {"ms": round(s_wall, 4), "regimes": s_reg},
+            **measure_variants(["interp", "learned_s1", "learned_s2", "learned_s4"], ps, smask, srho, s_reg,
+                               s_wall, s_phi)}
+        phi_v = phi
 
     traffic = measured_traffic() if args.n == 256 and args.seed == 2 else None
     out = {
@@ -630,10 +678,12 @@ def main():
             "precision": "fp64",
             "cycles_mean": cycles_mean,
             "regimes": reg64,
+            "item_depths": depths64,
             "final_rel_residual": last["r_final"] / last["r_ref"],
             "ms_events_median": round(ms_events, 4),
         },
         "variants": variants,
+        "learned_eval": learned_eval,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_rbgs<double,true> (finest-level red-black pass)",

@@ -284,6 +284,14 @@ int32_t mg_batch_size(const mg_batch *B);
 int32_t mg_batch_grid(const mg_batch *B);
 int32_t mg_batch_phases(const mg_batch *B, int32_t order);
 
+/* Re-run the host-side validation of the phase programs' tables (run once at
+ * creation, before any phase kernel): every work item's patch, level, item
+ * index and selector against the hierarchy it refers to, launch ranges,
+ * partial-sum offsets and small-level LDS sizes.  Returns the number of
+ * violations (0 for a valid batch; -1 for NULL) and copies a description
+ * of the first ones into msg (capacity len, may be NULL). */
+int32_t mg_batch_validate(const mg_batch *B, char *msg, int32_t len);
+
 /* Select the engine of later solves: phased != 0 the phase programs (the
  * default where they exist; MG_ERR_ARG if they do not), 0 the per-patch
  * lockstep cycles.  Both give the same results. */

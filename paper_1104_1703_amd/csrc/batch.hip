@@ -262,6 +262,10 @@ struct mg_batch {
     const double **pin_ptrs = nullptr;  // pinned [3n]: rho, dirichlet, phi
     int small_lim = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // host copies of the tables the programs read, for their validation
+    std::vector<mg::BRef> refs_host;
+    std::vector<int> nfirst_h, ncnt_h, nfirst1_h, ncnt1_h;
+    int part_cap = 0;
 };
 
 namespace mg {
@@ -493,6 +497,114 @@ std::vector<small::SmallLevels<double>> small_levels(mg_batch *B, int o) {
     return sl;
 }
 
+// Host-side check of every table the phase kernels read, before any of them
+// runs: each work item's patch, level, item index and selector against the
+// patch hierarchy it refers to (the level exists in the program's order and
+// holds the buffers the kernel dereferences; the item index is below that
+// level's item or tile count; the level's items have the depth the kernel
+// instance marches, so its masks lie inside the mask array), each launch's
+// item range inside the item table, each norm partial offset inside the
+// partial buffer, and each small-level launch's LDS at least what its
+// patches' levels need.  Returns the number of violations (the first few
+// are written to *msg).
+int validate_tables(const mg_batch *B, std::string *msg) {
+    int bad = 0;
+    auto fail = [&](const std::string &s) {
+        if (bad++ < 8 && msg) *msg += s + "; ";
+    };
+    const int n = B->n;
+    const int nref = (int)B->refs_host.size();
+    struct ProgRef {
+        const mg_batch::Prog *g;
+        int order;
+        const char *name;
+    };
+    const ProgRef progs[] = {{&B->begin, 2, "begin"}, {&B->end, 2, "end"}, {&B->pre, 2, "pre"},
+                             {&B->cycle[1], 1, "cycle1"}, {&B->cycle[2], 2, "cycle2"}};
+    for (const ProgRef &pr : progs) {
+        const int o = pr.order;
+        for (const Launch &k : pr.g->k) {
+            const std::string where = std::string(pr.name) + " kind " + std::to_string(k.kind);
+            if (k.kind == K_FIN) {
+                const std::vector<int> &fi = k.lay ? B->nfirst1_h : B->nfirst_h;
+                const std::vector<int> &cn = k.lay ? B->ncnt1_h : B->ncnt_h;
+                if (k.count != n || (int)fi.size() != n || (int)cn.size() != n) fail(where + ": patch count");
+                else
+                    for (int p = 0; p < n; p++)
+                        if (fi[p] < 0 || cn[p] < 0 || fi[p] + cn[p] > B->part_cap) fail(where + ": partial range");
+                continue;
+            }
+            if (k.first < 0 || k.count < 0 || k.first + k.count > nref) {
+                fail(where + ": item range outside the table");
+                continue;
+            }
+            if ((k.kind == K_NORM || k.kind == K_SM0N) && (k.poff < 0 || k.poff + k.count > B->part_cap))
+                fail(where + ": partials outside the buffer");
+            for (int i = k.first; i < k.first + k.count; i++) {
+                const BRef r = B->refs_host[i];
+                const int p = r.lev / MAXL, l = r.lev % MAXL, idx = r.w & IDX_MASK, sel = r.w >> WBITS;
+                if (r.lev < 0 || p >= n) {
+                    fail(where + ": patch out of range");
+                    continue;
+                }
+                const mg_hierarchy *H = B->patches[p];
+                if (l >= H->nlev[o] || sel < 0 || sel > 7) {
+                    fail(where + ": level or selector out of range");
+                    continue;
+                }
+                const Level &L = H->lev[l];
+                const OrderData &od = L.od[l == 0 ? 2 : o];
+                const bool bufs = L.x[0] && L.x[1] && L.f;
+                const bool has_c = l + 1 < H->nlev[o];
+                switch (k.kind) {
+                    case K_SM0:
+                    case K_SM0P:
+                    case K_SM0N:
+                    case K_SM1:
+                    case K_SM1P:
+                    case K_SM2:
+                    case K_SM2P: {
+                        const int want_l = (k.kind == K_SM1 || k.kind == K_SM1P) ? 1 : (k.kind == K_SM2 || k.kind == K_SM2P) ? 2 : 0;
+                        const int depth = want_l == 0 ? FINE_Z : want_l == 1 ? SEGZ_COARSE1 : SEGZ_COARSE;
+                        const bool pro = k.kind == K_SM0P || k.kind == K_SM1P || k.kind == K_SM2P;
+                        if ((want_l < 2 ? l != want_l : l < 2) || idx >= od.nsegs || od.depth != depth || !bufs ||
+                            !od.segs || !od.pmask || (l == 0 ? !L.code : !od.d))
+                            fail(where + ": smoother item");
+                        if (pro && (!has_c || !H->lev[l + 1].x[(sel >> 2) & 1])) fail(where + ": prolongation source");
+                        break;
+                    }
+                    case K_RES0:
+                        if (l != 0 || idx >= od.nsegs || od.depth != FINE_Z || !has_c || !bufs || !L.code ||
+                            !H->lev[1].f || !H->lev[1].od[o].d)
+                            fail(where + ": finest residual item");
+                        break;
+                    case K_RESC:
+                        if (l < 1 || !has_c || !bufs || !od.d || idx >= H->lev[l + 1].od[o].ntiles * TZ ||
+                            !H->lev[l + 1].od[o].tiles || !H->lev[l + 1].f)
+                            fail(where + ": coarse restriction item");
+                        break;
+                    case K_SMALL:
+                        if (l != H->ls[o] || !bufs || k.lds < small_lds_bytes(H, o, l, false) ||
+                            k.lds > (size_t)B->small_lim)
+                            fail(where + ": small-level item");
+                        break;
+                    case K_NORM:
+                        if (l != 0 || idx >= od.nsegs || od.depth != FINE_Z || !L.f || !L.code)
+                            fail(where + ": norm item");
+                        break;
+                    case K_FOLD:
+                    case K_STORE:
+                        if (l != 0 || idx >= od.ntiles * TZ || !od.tiles || !bufs) fail(where + ": tile-plane item");
+                        break;
+                    default:
+                        fail(where + ": unknown kind");
+                }
+            }
+        }
+    }
+    return bad;
+}
+
 // Builds the phase programs; false (and the lockstep engine) when the
 // options or a patch need a step the programs do not have.
 bool build_programs(mg_batch *B) {
@@ -548,6 +660,19 @@ bool build_programs(mg_batch *B) {
         acc += cnt[p];
     }
     part_cap = std::max(part_cap, acc);
+    B->refs_host = refs;
+    B->nfirst_h = first;
+    B->ncnt_h = cnt;
+    B->nfirst1_h = first1;
+    B->ncnt1_h = cnt1;
+    B->part_cap = part_cap;
+    {
+        std::string why;
+        if (validate_tables(B, &why) != 0) {
+            set_error("batch tables failed validation: " + why);
+            throw BFail{MG_ERR_HIP};
+        }
+    }
     B->refs = upload(B, refs);
     B->nfirst = upload(B, first);
     B->ncnt = upload(B, cnt);
@@ -923,6 +1048,17 @@ int32_t mg_batch_grid(const mg_batch *B) {
         for (const mg::Launch &k : B->cycle[o].k) m = std::max(m, k.count);
     for (const mg::Launch &k : B->pre.k) m = std::max(m, k.count);
     return m;
+}
+
+int32_t mg_batch_validate(const mg_batch *B, char *msg, int32_t len) {
+    if (!B) return -1;
+    std::string why;
+    const int bad = B->phased_ok ? mg::validate_tables(B, &why) : 0;
+    if (msg && len > 0) {
+        strncpy(msg, why.c_str(), (size_t)len - 1);
+        msg[len - 1] = 0;
+    }
+    return bad;
 }
 
 int32_t mg_batch_phases(const mg_batch *B, int32_t order) {

@@ -82,6 +82,7 @@ SYMBOLS = [
     ("mg_batch_size", _I, [_P]),
     ("mg_batch_grid", _I, [_P]),
     ("mg_batch_phases", _I, [_P, _I]),
+    ("mg_batch_validate", _I, [_P, C.c_char_p, _I]),
     ("mg_batch_set_engine", C.c_int, [_P, _I]),
     ("mg_amr_dirichlet", C.c_int, [_P, _I, _I, _I, _D, _P, _I, _I, _I, _D, _P, _P, _P]),
     ("mg_amr_grad5", C.c_int, [_P, _P, _I, _I, _I, _D, _P, _P, _I, _I, _I, _D, _P, _P, _P, _P]),
@@ -398,6 +399,12 @@ class Batch:
 
     def phases(self, order: int = 2) -> int:
         return int(load_library().mg_batch_phases(self._b, order))
+
+    def validate(self):
+        """(violations, description) of the host-side check of the phase tables."""
+        buf = C.create_string_buffer(1024)
+        n = int(load_library().mg_batch_validate(self._b, buf, len(buf)))
+        return n, buf.value.decode()
 
     def set_engine(self, phased: bool):
         """Phase programs (True) or per-patch lockstep cycles (False)."""

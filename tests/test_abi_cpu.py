@@ -62,3 +62,5 @@ def test_create_rejects_null_arguments_without_gpu():
     assert lib.mg_create_hierarchy(None, 8, 8, 8, 0.1, None, None, C.byref(out)) == mg.MG_ERR_ARG
     assert lib.mg_create_hierarchy(C.c_void_p(1), 8, 8, 8, -1.0, None, None, C.byref(out)) == mg.MG_ERR_ARG
     assert lib.mg_solve(None, None, None, None, 1e-10, None) == mg.MG_ERR_ARG
+    assert lib.mg_batch_validate(None, None, 0) == -1
+    assert lib.mg_level_item_depth(None, 0, 2) == -1
