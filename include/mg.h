@@ -81,8 +81,10 @@ typedef struct {
                                  norm's partial sums are added depends on it. */
     int32_t item_depth_fine;  /* planes per finest-level work item: 8, 16 or 32; 0 = default
                                  (16) or tuned.  A non-zero value is used as given. */
-    int32_t item_depth_l1;    /* level 1: 2, 4 or 8; 0 = default (4) or tuned */
-    int32_t item_depth_coarse;/* levels >= 2: 2, 4 or 8; 0 = default (2) or tuned */
+    int32_t item_depth_l1;    /* level 1: 2, 4 or 8; 0 = default (4) or tuned; 1 = plain passes
+                                 over 8 x 8 x 8 cubes loaded whole (no z march; not with
+                                 fuse_passes), the prolongation pass keeping the default */
+    int32_t item_depth_coarse;/* levels >= 2: as item_depth_l1 (default 2) */
     mg_allocator allocator;
 } mg_options;
 
@@ -175,7 +177,8 @@ int64_t mg_level_active(const mg_hierarchy *H, int32_t level, int32_t order);
 
 /* Planes per smoother work item of level l in boundary order `order` (the
  * default, the option's or the tuned value; work items are 32 x 8 cell
- * columns); -1 for an invalid level or order.  Levels run by the
+ * columns), 1 when its plain passes run over whole 8 x 8 x 8 cubes; -1 for
+ * an invalid level or order.  Levels run by the
  * one-workgroup small-level kernel keep their lists but use none. */
 int32_t mg_level_item_depth(const mg_hierarchy *H, int32_t level, int32_t order);
 

@@ -187,10 +187,11 @@ mg_status validate_options(const mg_options &o) {
         set_error("n_cycles above 4 is not supported");
         return MG_ERR_ARG;
     }
+    auto coarse_ok = [&](int v) { return !v || depth_supported(2, v) || (v == DEPTH_CUBE && !o.fuse_passes); };
     if (o.tune < 0 || o.tune > 1 || (o.item_depth_fine && !depth_supported(0, o.item_depth_fine)) ||
-        (o.item_depth_l1 && !depth_supported(1, o.item_depth_l1)) ||
-        (o.item_depth_coarse && !depth_supported(2, o.item_depth_coarse))) {
-        set_error("invalid tune or item depth (finest: 8, 16, 32; coarse: 2, 4, 8)");
+        !coarse_ok(o.item_depth_l1) || !coarse_ok(o.item_depth_coarse)) {
+        set_error("invalid tune or item depth (finest: 8, 16, 32; coarse: 2, 4, 8, or 1 for cubes "
+                  "without fuse_passes)");
         return MG_ERR_ARG;
     }
     if (o.fuse_passes && o.item_depth_fine && o.item_depth_fine != SEG_TILES_FINE * TZ) {
@@ -207,9 +208,11 @@ int forced_depth(const mg_options &o, int l) {
     return l == 0 ? o.item_depth_fine : l == 1 ? o.item_depth_l1 : o.item_depth_coarse;
 }
 
+// March depth a level's lists start with (cube items keep the default march
+// for the passes that apply the prolongation).
 int start_depth(const mg_options &o, int l) {
     const int f = forced_depth(o, l);
-    return f ? f : item_depth(l);
+    return (f && f != DEPTH_CUBE) ? f : item_depth(l);
 }
 
 // The tuning cache: lines "<key> <depth>" in the file MG_TUNE_CACHE names.
@@ -302,7 +305,7 @@ void tune_depths(mg_hierarchy *H) {
             if (od.nsegs == 0) continue;
             const std::string key = tune_key(H, l, o, f32);
             int best = tune_cache_get(key);
-            if (!depth_supported(l, best)) {
+            if (!depth_supported(l, best) && !(l > 0 && best == DEPTH_CUBE && !H->opt.fuse_passes)) {
                 const int cand0[3] = {8, 16, 32}, cand1[3] = {2, 4, 8};
                 const int *cand = l == 0 ? cand0 : cand1;
                 float tbest = time_pass(H, l, od, f32);
@@ -319,13 +322,20 @@ void tune_depths(mg_hierarchy *H) {
                     }
                     free_lists(H, t);
                 }
+                if (l > 0 && !H->opt.fuse_passes) {  // whole 8^3 cubes instead of a march
+                    OrderData t = od;
+                    t.cube = true;
+                    if (time_pass(H, l, t, f32) < tbest) best = DEPTH_CUBE;
+                }
                 tune_cache_put(key, best);
             }
-            if (best != od.depth) {
+            const int march = best == DEPTH_CUBE ? od.depth : best;
+            if (march != od.depth) {
                 HIPCHK(hipStreamSynchronize(H->stream));
                 free_lists(H, od);
-                build_lists(H, l, o, best, od);
+                build_lists(H, l, o, march, od);
             }
+            od.cube = best == DEPTH_CUBE;
         }
     H->lev[0].od[1] = H->lev[0].od[2];
 }
@@ -399,7 +409,10 @@ void create(mg_hierarchy *H, const int8_t *mask, int nx, int ny, int nz, double 
     build_lists(H, 0, 2, start_depth(H->opt, 0), lev[0].od[2]);
     lev[0].od[1] = lev[0].od[2];
     for (int o = 1; o <= 2; o++)
-        for (int l = 1; l < H->nlev[o]; l++) build_lists(H, l, o, start_depth(H->opt, l), lev[l].od[o]);
+        for (int l = 1; l < H->nlev[o]; l++) {
+            build_lists(H, l, o, start_depth(H->opt, l), lev[l].od[o]);
+            lev[l].od[o].cube = forced_depth(H->opt, l) == DEPTH_CUBE;
+        }
     // level buffers
     const int nl = std::max(H->nlev[1], H->nlev[2]);
     const bool mixed = H->opt.precision == MG_MIXED;
@@ -1189,7 +1202,8 @@ mg_status mg_level_dims(const mg_hierarchy *H, int32_t level, int32_t *dims_out)
 
 int32_t mg_level_item_depth(const mg_hierarchy *H, int32_t level, int32_t order) {
     if (!H || level < 0 || (order != 1 && order != 2) || level >= H->nlev[order]) return -1;
-    return H->lev[level].od[level == 0 ? 2 : order].depth;
+    const OrderData &od = H->lev[level].od[level == 0 ? 2 : order];
+    return od.cube ? DEPTH_CUBE : od.depth;
 }
 
 int64_t mg_level_active(const mg_hierarchy *H, int32_t level, int32_t order) {

@@ -32,6 +32,9 @@ constexpr int item_depth(int level) {
 constexpr bool depth_supported(int level, int depth) {
     return level == 0 ? (depth == 8 || depth == 16 || depth == 32) : (depth == 2 || depth == 4 || depth == 8);
 }
+// Coarse-level option value selecting 8^3 cube items for plain passes (the
+// passes that apply the prolongation keep the default march).
+constexpr int DEPTH_CUBE = 1;
 // Calls f(std::integral_constant<int, D>()) with D the finest-level item depth
 // in use (the kernel instance to launch).
 template <typename F>
@@ -65,6 +68,7 @@ struct OrderData {
     int nsegs8 = 0;
     int ntiles = 0, nsegs = 0;
     int depth = 0;  // planes per work item of segs (its masks hold depth + 4 words per item)
+    bool cube = false;  // coarse levels: plain passes over 8^3 cubes loaded whole (no z march)
     int64_t nact = 0;
 };
 

@@ -22,6 +22,7 @@
 // of inactive neighbours) are never fetched, and inactive cells are never
 // stored.  Net HBM traffic per pass: one read of x, f and the code/diagonal
 // and one write of x, on granules holding active cells.
+#include "cube_core.h"
 #include "mg_core.h"
 #include "smooth2_core.h"
 #include "transfer_core.h"
@@ -82,9 +83,35 @@ __global__ __launch_bounds__(NT, 2) void k_rbgs2(const T *__restrict__ xin, T *_
                                         pm + (size_t)item * (SEGZ + 2 * rb2::H), xc, cnx, cny, cnz);
 }
 
+// Coarse-level pass over 8 x 8 x 8 cubes (four per active 32 x 8 x 8 tile),
+// each loaded whole: cube_core.h.
+template <typename T>
+__global__ __launch_bounds__(cube::NT) void k_rbgs_cube(const T *__restrict__ xin, T *__restrict__ xout,
+                                                      const T *__restrict__ f, const T *__restrict__ d, int nx, int ny,
+                                                      int nz, int ntx, int nty, T h2, const int *__restrict__ tiles,
+                                                      int ntiles, const int *__restrict__ halt) {
+    __shared__ cube::Lds<T> lds;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= 4 * ntiles || (halt && *halt)) return;
+    const int tile = tiles[item >> 2];
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int x0 = tx * TX + (item & 3) * cube::C;
+    if (x0 >= nx) return;  // a tile wider than the level
+    cube::rbgs_cube<T>(lds, xin, xout, f, d, nx, ny, nz, h2, x0, ty * TY, tz * TZ);
+}
+
 inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
 
 }  // namespace
+
+template <typename T>
+void launch_cube(const T *xin, T *xout, const T *f, const T *d, const Level &L, const OrderData &od, T h2,
+                 hipStream_t s) {
+    static_assert(TX == 4 * cube::C && TY == cube::C && TZ == cube::C, "a tile holds four cubes");
+    if (od.ntiles == 0) return;
+    k_rbgs_cube<T><<<grid8(4 * od.ntiles), cube::NT, 0, s>>>(xin, xout, f, d, L.nx, L.ny, L.nz, L.ntx, L.nty, h2,
+                                                            od.tiles, od.ntiles, L.halt);
+}
 
 // Coarse levels: the kernel instance for the level's item depth.
 template <typename T, bool PRO = false>
@@ -114,6 +141,8 @@ void launch_rbgs(const Level &L, int level, const OrderData &od, const double *x
             k_rbgs<double, true, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(
                 xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
         });
+    else if (od.cube)
+        launch_cube<double>(xin, xout, f, od.d, L, od, h2, s);
     else
         launch_coarse<double>(od.depth, xin, xout, f, od.d, L, od, h2, s);
 }
@@ -214,6 +243,8 @@ void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *
             k_rbgs<float, true, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(
                 xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
         });
+    else if (od.cube)
+        launch_cube<float>(xin, xout, f, od.d32, L, od, h2, s);
     else
         launch_coarse<float>(od.depth, xin, xout, f, od.d32, L, od, h2, s);
 }

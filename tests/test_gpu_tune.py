@@ -1,8 +1,9 @@
-"""Work-item depths of the smoother marches (default, given, or picked by
-the autotuner at hierarchy creation): every depth runs the same arithmetic
-on every cell, so iterates are bit for bit those of the default depths;
-only the grouping of the residual norm's partial sums (one per work item)
-changes, so norms agree to rounding."""
+"""Work-item shapes of the smoother (default, given, or picked by the
+autotuner at hierarchy creation): z marches of 8/16/32 planes on the finest
+level and 2/4/8 planes or whole 8^3 cubes on coarse levels.  Every shape
+runs the same arithmetic on every cell, so iterates are bit for bit those
+of the default shapes; only the grouping of the residual norm's partial
+sums (one per finest work item) changes, so norms agree to rounding."""
 import os
 import tempfile
 
@@ -43,7 +44,8 @@ PROBLEMS = {
 }
 VARIANTS = [dict(item_depth_fine=8), dict(item_depth_fine=32), dict(item_depth_l1=2), dict(item_depth_l1=8),
             dict(item_depth_coarse=4), dict(item_depth_coarse=8),
-            dict(item_depth_fine=32, item_depth_l1=8, item_depth_coarse=8)]
+            dict(item_depth_fine=32, item_depth_l1=8, item_depth_coarse=8),
+            dict(item_depth_l1=1), dict(item_depth_coarse=1), dict(item_depth_fine=8, item_depth_l1=1, item_depth_coarse=1)]
 
 
 def _same_solve(a, ia, b, ib, what):
@@ -108,7 +110,7 @@ def test_tuned_hierarchy_solves_as_the_default_and_caches_its_choice(mg, precisi
             assert sum(1 for ln in lines if ln.strip()) >= 2
             for o in (1, 2):
                 for l, dz in enumerate(depths[o]):
-                    assert dz in ((8, 16, 32) if l == 0 else (2, 4, 8))
+                    assert dz in ((8, 16, 32) if l == 0 else (1, 2, 4, 8))
             ref, rinfo = H0.solve(rho, tol=1e-10)
             got, info = Ht.solve(rho, tol=1e-10)
             _same_solve(host(got), info, host(ref), rinfo, "tuned")
@@ -127,8 +129,8 @@ def test_tuned_hierarchy_solves_as_the_default_and_caches_its_choice(mg, precisi
 
 def test_invalid_depths_are_rejected(mg):
     p = gen.sphere_problem(16)
-    for opts in (dict(item_depth_fine=12), dict(item_depth_l1=16), dict(tune=2),
-                 dict(fuse_passes=1, item_depth_fine=8)):
+    for opts in (dict(item_depth_fine=12), dict(item_depth_l1=16), dict(tune=2), dict(item_depth_fine=1),
+                 dict(fuse_passes=1, item_depth_fine=8), dict(fuse_passes=1, item_depth_coarse=1)):
         with pytest.raises(mg.MGError) as e:
             mg.Hierarchy(dev(p.mask), p.h, **opts)
         assert e.value.status == mg.MG_ERR_ARG
