@@ -295,9 +295,13 @@ int32_t mg_batch_phases(const mg_batch *B, int32_t order);
  * of the first ones into msg (capacity len, may be NULL). */
 int32_t mg_batch_validate(const mg_batch *B, char *msg, int32_t len);
 
-/* Select the engine of later solves: phased != 0 the phase programs (the
- * default where they exist; MG_ERR_ARG if they do not), 0 the per-patch
- * lockstep cycles.  Both give the same results. */
+/* Select the engine of later solves: 1 the phase programs, one launch per
+ * phase (the default where they exist; MG_ERR_ARG if they do not); 2 the
+ * same programs as phases of one persistent cooperative launch per V-cycle
+ * (the cycle in each boundary order in use, then the next cycle's first
+ * finest pass with the norm of its input; grid-wide barriers between
+ * phases; MG_ERR_ARG where the device cannot run it); 0 the per-patch
+ * lockstep cycles.  All give the same results bit for bit. */
 mg_status mg_batch_set_engine(mg_batch *B, int32_t phased);
 
 /* ---------------- one-way nested levels (AMR) ----------------

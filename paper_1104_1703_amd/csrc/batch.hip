@@ -213,7 +213,7 @@ __global__ __launch_bounds__(tr::NT) void kb_store(const BRef *__restrict__ refs
                    L.x[sel & 1], phi[p]);
 }
 
-inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
+__host__ __device__ inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
 
 // One launch of a program.
 struct Launch {
@@ -223,6 +223,224 @@ struct Launch {
     int poff = 0;  // K_NORM, K_SM0N: offset of the launch's partials
     int lay = 0;   // K_FIN: 0 = partials of every patch in patch order, 1 = the pre-cycle layout
 };
+
+// ------------------------------------------------------------ persistent
+// The persistent engine runs whole programs in one cooperative launch: the
+// launches of the per-phase engine become phases separated by a grid-wide
+// barrier, and every block walks the phase's work items in the order the
+// per-phase kernel's blocks take them (virtual block vb -> item
+// xcd_item(vb, grid)), so each item runs the same device code on the same
+// data and partial sums land in the same slots: results are bit for bit
+// those of the per-phase engine.  Blocks are 256 threads; the small-level
+// call runs with 256 threads (its sweeps are in place per colour and its
+// transfers per cell, so the thread count does not change a result) with
+// its levels in LDS: a block's dynamic LDS is the largest of the phases'
+// needs (at least PERSIST_LDS), which sets how many blocks share a CU.
+constexpr int PERSIST_LDS = 40 * 1024;               // smallest dynamic LDS of a block
+constexpr unsigned PERSIST_SPIN_LIMIT = 1u << 22;    // barrier wait bound (about 0.2 s), then err
+static_assert(sizeof(rb::RbgsLds<double, true, true>) <= PERSIST_LDS &&
+                  sizeof(rb::RbgsLds<double, false, true>) <= PERSIST_LDS &&
+                  sizeof(tr::ResLds<double>) <= PERSIST_LDS && 1024 * sizeof(double) <= PERSIST_LDS,
+              "every phase's LDS fits a persistent block");
+
+struct PSeg {
+    const Launch *k;    // device copy of a program's launches
+    int nk;
+    int order;
+    const int *state;
+};
+
+struct PArgs {
+    PSeg seg[3];
+    int nseg;
+    const BRef *refs;
+    const BLev *lev[3];
+    const small::SmallLevels<double> *sl[3];
+    double *part, *norm2;
+    const int *nfirst, *ncnt, *nfirst1, *ncnt1;
+    int npatch;
+    const double *const *rho;
+    const double *const *dir;
+    double *const *phi;
+    unsigned *bar;  // [2]: arrivals, generation
+    int *err;       // set when a barrier wait exceeds its bound
+};
+
+// Grid-wide barrier of a co-resident launch.  Every thread's global writes
+// are made visible at device scope before the block arrives, and every
+// thread's view is refreshed after it leaves.  The wait is bounded: past
+// the bound it raises err and goes on, so every wave reaches the kernel's
+// end (the host then reports the error).
+__device__ void persist_sync(unsigned *bar, int *err) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (arrived == gridDim.x) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > PERSIST_SPIN_LIMIT) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+// Work item of virtual block vb of a phase with `grid` virtual blocks, as
+// the per-phase kernel's block vb takes it.
+__device__ __forceinline__ bool ptake(const BRef *refs, const Launch &k, int vb, int grid, const int *state,
+                                      int order, BRef &r, int &w) {
+    w = rb::xcd_item(vb, grid);
+    if (w >= k.count) return false;
+    r = refs[k.first + w];
+    return state[r.lev / MAXL] == order;
+}
+
+template <bool FINE, int SEGZ, bool PRO, bool NORMIN = false>
+__device__ __attribute__((noinline)) void p_smooth(unsigned char *smem, const BRef r, int w, const BLev *lev, double *part, int poff) {
+    auto &lds = *reinterpret_cast<rb::RbgsLds<double, FINE, PRO> *>(smem);
+    const BLev &L = lev[r.lev];
+    const int idx = r.w & IDX_MASK, sel = r.w >> WBITS, a = sel & 1;
+    const double sq = rb::rbgs_item<double, FINE, SEGZ, PRO, NORMIN>(
+        lds, (sel & 2) ? nullptr : L.x[a], L.x[a ^ 1], L.f, L.code, L.d, L.nx, L.ny, L.nz, L.h2, L.segs[idx],
+        L.pm + (size_t)idx * (SEGZ + 4), PRO ? L.cx[(sel >> 2) & 1] : nullptr, L.cnx, L.cny, L.cnz, L.ih2);
+    if constexpr (NORMIN) {
+        const double t = tr::block_sum(sq);
+        if (threadIdx.x == 0) part[poff + w] = t;
+    }
+}
+
+template <int MODE>
+__device__ __attribute__((noinline)) void p_residual(unsigned char *smem, const BRef r, int w, const BLev *lev, double *part, int poff) {
+    auto &lds = *reinterpret_cast<tr::ResLds<double> *>(smem);
+    const BLev &L = lev[r.lev];
+    const int idx = r.w & IDX_MASK, sel = r.w >> WBITS;
+    constexpr bool RS = MODE == tr::RM_RESTRICT;
+    const double sq = tr::residual_item<double, FINE_Z, MODE>(
+        lds, (sel & 2) ? nullptr : L.x[sel & 1], L.f, L.code, L.nx, L.ny, L.nz, L.ih2, L.segs[idx],
+        L.pm + (size_t)idx * (FINE_Z + 4), RS ? L.cd : nullptr, RS ? L.cnx : 0, RS ? L.cny : 0,
+        RS ? L.cf : nullptr, nullptr, nullptr, nullptr);
+    if constexpr (!RS) {
+        const double t = tr::block_sum(sq);
+        if (threadIdx.x == 0) part[poff + w] = t;
+    }
+}
+
+__device__ __attribute__((noinline)) void p_small(unsigned char *smem, const small::SmallLevels<double> &S,
+                                                  const double *f0, double *x0, bool load_x) {
+    small::small_tail<double, rb::NT>(reinterpret_cast<double *>(smem), S, f0, x0, load_x);
+}
+
+__device__ __attribute__((noinline)) void p_cell(int kind, const BLev &L, int idx, int sel, const double *rho,
+                                                 const double *dir, double *phi) {
+    switch (kind) {
+        case K_RESC: {
+            const tr::TileCoord t = tr::tile_cell(L.ctiles[idx / TZ], idx % TZ, L.cntx, L.cnty, L.cnx, L.cny, L.cnz);
+            tr::restrict_cell<double, false>(t, L.cnx, L.cny, L.cd, L.nx, L.ny, L.nz, L.ih2, nullptr, L.d,
+                                             L.x[sel & 1], L.f, L.cf);
+            break;
+        }
+        case K_FOLD:
+            tr::fold_cell(tr::tile_cell(L.tiles[idx / TZ], idx % TZ, L.ntx, L.nty, L.nx, L.ny, L.nz), L.nx, L.ny,
+                          L.ih2, L.code, rho, dir, phi, L.f, L.x[0]);
+            break;
+        case K_STORE:
+            tr::store_cell(tr::tile_cell(L.tiles[idx / TZ], idx % TZ, L.ntx, L.nty, L.nx, L.ny, L.nz), L.nx, L.ny,
+                           L.code, L.x[sel & 1], phi);
+            break;
+        default: break;
+    }
+}
+
+__global__ __launch_bounds__(rb::NT, 4) void kb_persist(PArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    bool first = true;
+    for (int si = 0; si < A.nseg; si++) {
+        const PSeg S = A.seg[si];
+        const int order = S.order;
+        const BLev *lev = A.lev[order];
+        for (int i = 0; i < S.nk; i++) {
+            if (!first) persist_sync(A.bar, A.err);
+            first = false;
+            const Launch k = S.k[i];
+            if (k.kind == K_FIN) {
+                // per patch: the per-phase kernel's 1024-lane fixed-order sum, four lanes per thread
+                const int *fi = k.lay ? A.nfirst1 : A.nfirst;
+                const int *cn = k.lay ? A.ncnt1 : A.ncnt;
+                double *sm = reinterpret_cast<double *>(smem);
+                for (int p = blockIdx.x; p < A.npatch; p += gridDim.x) {
+                    if (S.state[p] != order) continue;
+                    const double *pp = A.part + fi[p];
+                    const int n = cn[p];
+                    for (int lane = threadIdx.x; lane < 1024; lane += rb::NT) {
+                        double v = 0.0;
+                        for (int q = lane; q < n; q += 1024) v += pp[q];
+                        sm[lane] = v;
+                    }
+                    __syncthreads();
+                    for (int o = 512; o > 0; o >>= 1) {
+                        for (int lane = threadIdx.x; lane < o; lane += rb::NT) sm[lane] += sm[lane + o];
+                        __syncthreads();
+                    }
+                    if (threadIdx.x == 0) A.norm2[2 * p + k.slot] = sm[0];
+                    __syncthreads();
+                }
+                continue;
+            }
+            if (k.kind == K_SMALL) {
+                for (int vb = blockIdx.x; vb < k.count; vb += gridDim.x) {
+                    const BRef r = A.refs[k.first + vb];
+                    const int p = r.lev / MAXL;
+                    if (S.state[p] != order) continue;
+                    const BLev &L = lev[r.lev];
+                    const int sel = r.w >> WBITS;
+                    p_small(smem, A.sl[order][p], L.f, L.x[sel & 1], (sel & 2) == 0);
+                    __syncthreads();
+                }
+                continue;
+            }
+            const int grid = (int)grid8(k.count);
+            for (int vb = blockIdx.x; vb < grid; vb += gridDim.x) {
+                BRef r;
+                int w;
+                if (!ptake(A.refs, k, vb, grid, S.state, order, r, w)) continue;
+                const BLev &L = lev[r.lev];
+                const int idx = r.w & IDX_MASK, sel = r.w >> WBITS, p = r.lev / MAXL;
+                switch (k.kind) {
+                    case K_SM0: p_smooth<true, FINE_Z, false>(smem, r, w, lev, nullptr, 0); break;
+                    case K_SM0P: p_smooth<true, FINE_Z, true>(smem, r, w, lev, nullptr, 0); break;
+                    case K_SM1: p_smooth<false, SEGZ_COARSE1, false>(smem, r, w, lev, nullptr, 0); break;
+                    case K_SM1P: p_smooth<false, SEGZ_COARSE1, true>(smem, r, w, lev, nullptr, 0); break;
+                    case K_SM2: p_smooth<false, SEGZ_COARSE, false>(smem, r, w, lev, nullptr, 0); break;
+                    case K_SM2P: p_smooth<false, SEGZ_COARSE, true>(smem, r, w, lev, nullptr, 0); break;
+                    case K_SM0N: p_smooth<true, FINE_Z, false, true>(smem, r, w, lev, A.part, k.poff); break;
+                    case K_RES0: p_residual<tr::RM_RESTRICT>(smem, r, w, lev, nullptr, 0); break;
+                    case K_NORM: p_residual<tr::RM_NORM>(smem, r, w, lev, A.part, k.poff); break;
+                    case K_RESC:
+                    case K_FOLD:
+                    case K_STORE: p_cell(k.kind, L, idx, sel, A.rho[p], A.dir[p], A.phi[p]); break;
+                    default: break;
+                }
+                __syncthreads();  // the next item reuses the block's LDS
+            }
+        }
+    }
+}
+
+__global__ void kb_zero_bar(unsigned *bar, int *err) {
+    if (threadIdx.x < 2) bar[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) *err = 0;
+}
 
 }  // namespace
 }  // namespace mg
@@ -262,6 +480,17 @@ struct mg_batch {
     const double **pin_ptrs = nullptr;  // pinned [3n]: rho, dirichlet, phi
     int small_lim = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // persistent engine: device copies of the programs' launches (begin,
+    // end, pre, cycle 1, cycle 2), the block's LDS, the grid barrier, the
+    // co-resident grid size
+    bool persist_ok = false;
+    bool use_persist = false;
+    mg::Launch *dk[5] = {};
+    int plds = 0;  // dynamic LDS of a persistent block
+    unsigned *pbar = nullptr;
+    int *perr = nullptr;
+    int *perr_host = nullptr;  // pinned
+    int pgrid = 0;
     // host copies of the tables the programs read, for their validation
     std::vector<mg::BRef> refs_host;
     std::vector<int> nfirst_h, ncnt_h, nfirst1_h, ncnt1_h;
@@ -696,6 +925,42 @@ bool build_programs(mg_batch *B) {
     return true;
 }
 
+// Device copies of the programs for the persistent engine and its
+// co-resident grid; false when the device cannot run it.
+bool build_persistent(mg_batch *B) {
+    int dev = 0, ncu = 0, coop = 0, per = 0;
+    BHIP(hipGetDevice(&dev));
+    BHIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) {
+        (void)hipGetLastError();
+        return false;
+    }
+    // LDS: the largest small-level call of either order (every other phase
+    // needs at most PERSIST_LDS)
+    size_t lds = PERSIST_LDS;
+    for (int o = 1; o <= 2; o++)
+        for (const mg::Launch &k : B->cycle[o].k)
+            if (k.kind == K_SMALL) lds = std::max(lds, k.lds);
+    lds = (lds + 1023) / 1024 * 1024;
+    if (lds > (size_t)B->small_lim) return false;
+    B->plds = (int)lds;
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void *)kb_persist, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kb_persist, rb::NT, lds));
+    B->pgrid = (per * ncu) / 8 * 8;
+    if (B->pgrid < 8) return false;
+    const mg_batch::Prog *progs[5] = {&B->begin, &B->end, &B->pre, &B->cycle[1], &B->cycle[2]};
+    for (int i = 0; i < 5; i++) B->dk[i] = upload(B, progs[i]->k);
+    B->pbar = balloc<unsigned>(B, 2);
+    B->perr = balloc<int>(B, 1);
+    BHIP(hipHostMalloc((void **)&B->perr_host, sizeof(int), hipHostMallocDefault));
+    return true;
+}
+
 void build_batch(mg_batch *B, const int8_t *const *masks, const int32_t *dims, const double *h) {
     const int n = B->n;
     BHIP(hipEventCreate(&B->ev0));
@@ -726,6 +991,7 @@ void build_batch(mg_batch *B, const int8_t *const *masks, const int32_t *dims, c
     }
     B->phased_ok = lds_ok && build_programs(B);
     B->use_phases = B->phased_ok;
+    B->persist_ok = B->phased_ok && build_persistent(B);
     BHIP(hipStreamSynchronize(B->stream));
 }
 
@@ -786,6 +1052,152 @@ void run_program(mg_batch *B, mg_batch::Prog &g, int order, const int *state) {
         BHIP(ie);
     }
     BHIP(hipGraphLaunch(g.exec, B->stream));
+}
+
+// Programs run back to back in one cooperative launch (a grid barrier
+// between consecutive phases).  prog: 0 begin, 1 end, 2 pre, 3 cycle 1,
+// 4 cycle 2.
+struct PRun {
+    int prog, order;
+    const int *state;
+};
+
+void run_persist(mg_batch *B, std::initializer_list<PRun> runs) {
+    const mg_batch::Prog *progs[5] = {&B->begin, &B->end, &B->pre, &B->cycle[1], &B->cycle[2]};
+    PArgs A;
+    memset(&A, 0, sizeof(A));
+    for (const PRun &r : runs) {
+        if (progs[r.prog]->k.empty()) continue;
+        PSeg &s = A.seg[A.nseg++];
+        s.k = B->dk[r.prog];
+        s.nk = (int)progs[r.prog]->k.size();
+        s.order = r.order;
+        s.state = r.state;
+    }
+    if (A.nseg == 0) return;
+    A.refs = B->refs;
+    for (int o = 0; o < 3; o++) A.lev[o] = B->lev[o];
+    for (int o = 1; o <= 2; o++) A.sl[o] = B->sl[o];
+    A.sl[0] = A.sl[2];
+    A.part = B->part;
+    A.norm2 = B->norm2;
+    A.nfirst = B->nfirst;
+    A.ncnt = B->ncnt;
+    A.nfirst1 = B->nfirst1;
+    A.ncnt1 = B->ncnt1;
+    A.npatch = B->n;
+    A.rho = B->in_rho;
+    A.dir = B->in_dir;
+    A.phi = B->in_phi;
+    A.bar = B->pbar;
+    A.err = B->perr;
+    kb_zero_bar<<<1, 64, 0, B->stream>>>(B->pbar, B->perr);
+    void *args[] = {&A};
+    BHIP(hipLaunchCooperativeKernel((const void *)kb_persist, dim3(B->pgrid), dim3(rb::NT), args, (size_t)B->plds,
+                                    B->stream));
+}
+
+// Waits for the batch stream (the norms were queued for copy) and checks
+// the persistent launches' barrier flag.
+void persist_wait(mg_batch *B) {
+    BHIP(hipMemcpyAsync(B->perr_host, B->perr, sizeof(int), hipMemcpyDeviceToHost, B->stream));
+    BHIP(hipStreamSynchronize(B->stream));
+    if (*B->perr_host) {
+        set_error("persistent batch launch: a grid barrier wait exceeded its bound");
+        throw BFail{MG_ERR_HIP};
+    }
+}
+
+mg_status first_error(const std::vector<SolveState> &S);
+mg_status finish_batch(mg_batch *B, std::vector<SolveState> &S, mg_solve_info *infos, double *ms_out);
+
+// The persistent engine: the steps of the per-phase engine, each program
+// run as phases of one cooperative launch; per V-cycle one launch runs the
+// cycle in each boundary order in use and then the next cycle's first
+// finest pass with the norm of its input, followed by one copy of all
+// per-patch norms and one synchronisation.
+mg_status solve_batch_persistent(mg_batch *B, const double *const *rho, double *const *phi,
+                                 const double *const *dir, double tol, mg_solve_info *infos, double *ms_out) {
+    const int n = B->n;
+    hipStream_t s = B->stream;
+    std::vector<SolveState> S(n);
+    BHIP(hipStreamSynchronize(s));  // no copy of an earlier solve still reads the staging
+    BHIP(hipEventRecord(B->ev0, s));
+    for (int p = 0; p < n; p++) {
+        const mg_status st = phase_init(B->patches[p], phi[p], tol, &infos[p], S[p]);
+        if (st != MG_OK) return st;
+    }
+    const double **pr = B->pin_ptrs, **pd = B->pin_ptrs + n, **pp = B->pin_ptrs + 2 * n;
+    for (int p = 0; p < n; p++) {
+        pr[p] = rho[p];
+        pd[p] = dir ? dir[p] : nullptr;
+        pp[p] = phi[p];
+    }
+    BHIP(hipMemcpyAsync((void *)B->in_rho, pr, n * sizeof(double *), hipMemcpyHostToDevice, s));
+    BHIP(hipMemcpyAsync((void *)B->in_dir, pd, n * sizeof(double *), hipMemcpyHostToDevice, s));
+    BHIP(hipMemcpyAsync((void *)B->in_phi, pp, n * sizeof(double *), hipMemcpyHostToDevice, s));
+    run_persist(B, {{0, 2, B->state[0]}});
+    BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+    persist_wait(B);
+    for (int p = 0; p < n; p++) {
+        mg_hierarchy *H = B->patches[p];
+        H->norm_host[0] = B->norm2_host[2 * p];
+        H->norm_host[1] = B->norm2_host[2 * p + 1];
+        const mg_status st = phase_start(H, S[p]);
+        if (st != MG_OK) return st;
+    }
+    // the first cycle's first finest pass with the norm of the initial iterate
+    int *sp = B->pin_state;  // slot 0 of the pinned staging: the pre program's patches
+    bool any = false;
+    for (int p = 0; p < n; p++) {
+        sp[p] = S[p].active ? 2 : 0;
+        any |= S[p].active;
+    }
+    if (any) {
+        BHIP(hipMemcpyAsync(B->state[3], sp, n * sizeof(int), hipMemcpyHostToDevice, s));
+        run_persist(B, {{2, 2, B->state[3]}});
+        BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+        persist_wait(B);
+    }
+    std::vector<int> run;
+    while (true) {
+        run.clear();
+        for (int p = 0; p < n; p++)
+            if (S[p].active) run.push_back(p);
+        if (run.empty()) break;
+        // the rest of this cycle in each order, then the next cycle's first
+        // pass (forming this cycle's norm) for the same patches
+        bool use[3] = {false, false, false};
+        for (int o = 1; o <= 2; o++) {
+            int *sv = B->pin_state + o * n;  // the previous round's copies have finished
+            for (int p = 0; p < n; p++) {
+                sv[p] = (S[p].active && S[p].order == o) ? o : 0;
+                use[o] |= sv[p] != 0;
+            }
+            if (use[o]) BHIP(hipMemcpyAsync(B->state[o], sv, n * sizeof(int), hipMemcpyHostToDevice, s));
+        }
+        for (int p = 0; p < n; p++) sp[p] = S[p].active ? 2 : 0;
+        BHIP(hipMemcpyAsync(B->state[3], sp, n * sizeof(int), hipMemcpyHostToDevice, s));
+        if (use[2] && use[1])
+            run_persist(B, {{4, 2, B->state[2]}, {3, 1, B->state[1]}, {2, 2, B->state[3]}});
+        else if (use[2])
+            run_persist(B, {{4, 2, B->state[2]}, {2, 2, B->state[3]}});
+        else
+            run_persist(B, {{3, 1, B->state[1]}, {2, 2, B->state[3]}});
+        BHIP(hipMemcpyAsync(B->norm2_host, B->norm2, 2 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+        persist_wait(B);
+        for (int p : run) {
+            mg_hierarchy *H = B->patches[p];
+            H->norm_host[0] = B->norm2_host[2 * p];
+            S[p].host_slot = 0;
+            S[p].parity = 0;  // the finished cycle's iterate is in buffer 0
+            const mg_status st = phase_cycle_finish(H, S[p]);
+            if (st != MG_OK) return st;
+        }
+    }
+    run_persist(B, {{1, 2, B->state[0]}});
+    persist_wait(B);
+    return finish_batch(B, S, infos, ms_out);
 }
 
 mg_status first_error(const std::vector<SolveState> &S) {
@@ -945,6 +1357,7 @@ void mg_destroy_batch(mg_batch *B) {
     if (B->norm2_host) (void)hipHostFree(B->norm2_host);
     if (B->pin_ptrs) (void)hipHostFree((void *)B->pin_ptrs);
     if (B->pin_state) (void)hipHostFree(B->pin_state);
+    if (B->perr_host) (void)hipHostFree(B->perr_host);
     if (B->ev0) (void)hipEventDestroy(B->ev0);
     if (B->ev1) (void)hipEventDestroy(B->ev1);
     if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
@@ -1013,6 +1426,8 @@ mg_status mg_solve_batch(mg_batch *B, const double *const *rho_dev, double *cons
             tmp.resize(B->n);
             infos = tmp.data();
         }
+        if (B->use_phases && B->use_persist)
+            return solve_batch_persistent(B, rho_dev, phi_dev, dirichlet_dev, tol, infos, ms_out);
         if (B->use_phases) return solve_batch_phased(B, rho_dev, phi_dev, dirichlet_dev, tol, infos, ms_out);
         return solve_batch_lockstep(B, rho_dev, phi_dev, dirichlet_dev, tol, infos, ms_out);
     } catch (const BFail &f) {
@@ -1031,11 +1446,16 @@ mg_status mg_batch_set_engine(mg_batch *B, int32_t phased) {
         set_error("null batch");
         return MG_ERR_ARG;
     }
-    if (phased && !B->phased_ok) {
+    if (phased < 0 || phased > 2 || (phased && !B->phased_ok)) {
         set_error("the phase programs do not cover these options; the batch runs per patch");
         return MG_ERR_ARG;
     }
+    if (phased == 2 && !B->persist_ok) {
+        set_error("this device cannot run the persistent batch engine");
+        return MG_ERR_ARG;
+    }
     B->use_phases = phased != 0;
+    B->use_persist = phased == 2;
     return MG_OK;
 }
 

@@ -63,10 +63,17 @@ __device__ __forceinline__ T nb_sum(const T *x, int i, int j, int k, int nx, int
     return (xm + xp) + (ym + yp) + (zm + zp);
 }
 
+// The three relaxation paths below (one wave, cells in registers, slots in
+// turn) are chosen by level size and thread count; each evaluates
+// ((x-neighbour pair) + (y pair) + (z pair) - h^2 f) / d with h^2 f rounded
+// on its own (no fused multiply-add), so every path, for any thread count,
+// gives the same value bit for bit.
+
 // Red-black half-sweep of colour `col` over slots first, first + step, ...
 // (slot m of row (j, k) is cell i = 2m + ((col + j + k) mod 2)).
 template <typename T>
 __device__ __forceinline__ void half_sweep(const Lv<T> &L, int col, int first, int step) {
+#pragma clang fp contract(off)
     const int slots = L.hx * L.ny * L.nz;
     for (int s = first; s < slots; s += step) {
         const int k = qdiv(s, L.mhy);
@@ -90,6 +97,7 @@ constexpr int WAVE_SLOTS = 64;
 
 template <typename T>
 __device__ __forceinline__ void smooth_wave(const Lv<T> &L, int passes) {
+#pragma clang fp contract(off)
     const int lane = threadIdx.x;
     const int nxy = L.nx * L.ny;
     int e[2] = {-1, -1};
@@ -138,6 +146,7 @@ __device__ __forceinline__ void smooth_wave(const Lv<T> &L, int passes) {
 // passes of the call (the same expression as half_sweep).
 template <typename T, int NTH>
 __device__ void smooth_regs(const Lv<T> &L, int passes) {
+#pragma clang fp contract(off)
     const int slots = L.hx * L.ny * L.nz;
     const int nxy = L.nx * L.ny;
     int e[2][2];
@@ -259,8 +268,8 @@ __device__ void prolong_from(const Lv<T> &L, const Lv<T> &C) {
     __syncthreads();
 }
 
-// One call MG(ls) for the levels held in S, all resident in the memory at
-// `sm` (LDS, or global memory for levels too large for LDS); f0 is level ls's
+// One call MG(ls) for the levels held in S, all resident in LDS at `sm`
+// (the one-wave path relies on a wave's in-order LDS accesses); f0 is level ls's
 // right-hand side and x0 its iterate (in/out), started from zero unless
 // load_x.  Called by all NTH threads of a block.
 template <typename T, int NTH>

@@ -406,9 +406,12 @@ class Batch:
         n = int(load_library().mg_batch_validate(self._b, buf, len(buf)))
         return n, buf.value.decode()
 
-    def set_engine(self, phased: bool):
-        """Phase programs (True) or per-patch lockstep cycles (False)."""
-        _check(load_library().mg_batch_set_engine(self._b, 1 if phased else 0), "mg_batch_set_engine")
+    def set_engine(self, phased):
+        """Phase programs (True or "phased"), the same programs as one
+        cooperative launch per V-cycle ("persistent"), or per-patch lockstep
+        cycles (False or "lockstep")."""
+        v = {"lockstep": 0, "phased": 1, "persistent": 2}[phased] if isinstance(phased, str) else (1 if phased else 0)
+        _check(load_library().mg_batch_set_engine(self._b, v), "mg_batch_set_engine")
 
     def solve(self, rhos, phis=None, dirichlets=None, tol: float = 1e-10, check: bool = True):
         """Solve every patch in place; returns (phis, list of info dicts, ms)."""

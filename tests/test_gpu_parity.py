@@ -476,15 +476,18 @@ def test_mixed_precision_matches_converged_oracle(mg, name):
 
 
 # ---------------------------------------------------------------- batched solver
-def _batch_case(mg, probs, **opts):
+def _batch_case(mg, probs, engine=None, **opts):
     B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], **opts)
+    if engine is not None:
+        B.set_engine(engine)
     rhos = [dev(p.rho) for p in probs]
     dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
     phis, infos, ms = B.solve(rhos, None, dirs, tol=1e-10, check=False)
     return B, [host(x) for x in phis], infos, ms
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(bc_order="second"), dict(n_cycles=2)])
+@pytest.mark.parametrize("opts", [dict(), dict(bc_order="second"), dict(n_cycles=2), dict(engine="persistent"),
+                                  dict(engine="persistent", bc_order="second")])
 def test_batch_matches_oracle_per_patch(mg, opts):
     """Uneven patches in one batch on the phase programs: every patch takes
     the same cycles, switch and solution as the oracle's own solve of it.  In
@@ -537,6 +540,16 @@ def test_batch_patches512_matches_oracle_per_patch(mg):
     # the phase kernels read (run at creation too, before any phase kernel)
     assert B.validate() == (0, "")
     B.close()
+    # the same programs as one persistent launch per V-cycle, bit for bit.  A
+    # fresh batch: a patch that switched order above starts its next solve on
+    # the same hierarchy in first order (the hold of Sec. 4).
+    B2, got_p, infos_p, ms_p = _batch_case(mg, probs, engine="persistent")
+    print(f"  phase programs {ms:.1f} ms, persistent {ms_p:.1f} ms", flush=True)
+    for p, x, xp, info, ip in zip(probs, got, got_p, infos, infos_p):
+        assert (ip["status"], ip["cycles"], ip["switched_at"], ip["r_final"]) == \
+            (info["status"], info["cycles"], info["switched_at"], info["r_final"]), p.name
+        assert np.array_equal(xp, x), p.name
+    B2.close()
     refs = _oracle_solves(probs)
     worst = 0.0
     for p, x, info, (ref, rinfo) in zip(probs, got, infos, refs):
@@ -550,14 +563,14 @@ def test_batch_patches512_matches_oracle_per_patch(mg):
           f"{min(i['cycles'] for i in infos)}..{max(i['cycles'] for i in infos)}", flush=True)
 
 
-@pytest.mark.parametrize("engine", ["phased", "phased_graph", "lockstep"])
+@pytest.mark.parametrize("engine", ["phased", "phased_graph", "lockstep", "persistent"])
 def test_batch_equals_single_solves_and_repeats(mg, engine):
     """24 patches solved twice (the second solve starts in first order where
     the first switched): on either engine every patch equals its own
     single-grid solve bit for bit, with the same cycles and switch."""
     probs = gen.patch_problems(count=22, seed=12) + [gen.porous_problem(n=64, seed=4), gen.sphere_problem(32)]
     B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], use_graph=int(engine == "phased_graph"))
-    B.set_engine(engine != "lockstep")
+    B.set_engine("persistent" if engine == "persistent" else engine != "lockstep")
     singles = [mg.Hierarchy(dev(p.mask), p.h) for p in probs]
     rhos = [dev(p.rho) for p in probs]
     dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
@@ -581,7 +594,7 @@ def test_batch_equals_single_solves_and_repeats(mg, engine):
     B.close()
 
 
-@pytest.mark.parametrize("graph", [0, 1])
+@pytest.mark.parametrize("graph", [0, 1, "persistent"])
 def test_batch_mixes_whole_workgroup_patches(mg, graph):
     """Patches whose whole hierarchy runs in one workgroup (sphere 16^3) or
     that have a single level (6 x 10 x 10) get the residual-norm march in the
@@ -591,7 +604,9 @@ def test_batch_mixes_whole_workgroup_patches(mg, graph):
                                                     gen.random_small_problem((6, 10, 10), 7, active_frac=0.8)]
     for p in probs:
         _print_case(p.name, p)
-    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], use_graph=graph)
+    B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], use_graph=int(graph == 1))
+    if graph == "persistent":
+        B.set_engine("persistent")
     assert B.phases(1) > 0 and B.phases(2) > 0
     rhos = [dev(p.rho) for p in probs]
     dirs = [None if p.dirichlet is None else dev(p.dirichlet) for p in probs]
@@ -607,12 +622,14 @@ def test_batch_mixes_whole_workgroup_patches(mg, graph):
     B.close()
 
 
-def test_batch_guess_and_max_cycles(mg):
-    """Phase engine with a non-zero guess (junk in inactive cells must not
+@pytest.mark.parametrize("engine", ["phased", "persistent"])
+def test_batch_guess_and_max_cycles(mg, engine):
+    """Phase engines with a non-zero guess (junk in inactive cells must not
     leak) and a cycle cap: the same iterate as single solves, MG_NOT_CONVERGED
     reported per patch."""
     probs = gen.patch_problems(count=5, seed=21)
     B = mg.Batch([dev(p.mask) for p in probs], [p.h for p in probs], max_cycles=3)
+    B.set_engine(engine)
     assert B.phases(2) > 0
     rng = np.random.default_rng(5)
     guesses = [rng.standard_normal(p.mask.shape) for p in probs]
