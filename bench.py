@@ -397,9 +397,9 @@ def profile_batch(args):
 def batch_measurement(args, solves=3):
     """The batched workload: `--batch-patches` masked patches (edges log-uniform
     in 16..128, multiples of 8, seed 3), FP64, V(2,2), each to 1e-10; the
-    wall time of one mg_solve_batch call (inputs resident), median of 3
-    after one warm-up (`solves` timed solves); the patch hierarchies are
-    built once, untimed."""
+    wall time of one mg_solve_batch call (inputs resident), median of
+    `solves` timed solves after one warm-up, on each engine; the patch
+    hierarchies are built untimed."""
     import torch
 
     from paper_1104_1703_amd import gen, mg
@@ -410,25 +410,37 @@ def batch_measurement(args, solves=3):
     rhos = [torch.from_numpy(p.rho).cuda() for p in probs]
     dirs = [torch.from_numpy(p.dirichlet).cuda() for p in probs]
     phis = [torch.zeros(p.shape, dtype=torch.float64, device="cuda") for p in probs]
-    t0 = time.perf_counter()
-    B = mg.Batch(masks, [p.h for p in probs])
-    torch.cuda.synchronize()
-    t_build = time.perf_counter() - t0
-    B_phases = B.phases(2)
-    if B_phases == 0:
-        raise RuntimeError("the batch has no phase programs for the default options")
-    walls, infos = [], None
-    for rep in range(solves + 1):
-        for x in phis:
-            x.zero_()
-        torch.cuda.synchronize()
+
+    def timed(engine):
+        """A fresh batch on `engine`: its build time, the median wall of the
+        timed solves, their infos and the warm-up solve's.  Patches that
+        switch order in the warm-up solve keep first order in the timed ones
+        (the hold of Sec. 4), on either engine alike."""
         t0 = time.perf_counter()
-        _, infos, _ = B.solve(rhos, phis, dirs, tol=1e-10)
+        B = mg.Batch(masks, [p.h for p in probs])
         torch.cuda.synchronize()
-        if rep > 0:
-            walls.append(time.perf_counter() - t0)
-    B.close()
-    ms = float(np.median(walls)) * 1e3
+        t_build = time.perf_counter() - t0
+        if B.phases(2) == 0:
+            raise RuntimeError("the batch has no phase programs for the default options")
+        B.set_engine(engine)
+        walls, infos, first = [], None, None
+        for rep in range(solves + 1):
+            for x in phis:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, infos, _ = B.solve(rhos, phis, dirs, tol=1e-10)
+            torch.cuda.synchronize()
+            if rep > 0:
+                walls.append(time.perf_counter() - t0)
+            else:
+                first = infos
+        B_phases = B.phases(2)
+        B.close()
+        return float(np.median(walls)) * 1e3, infos, first, t_build, B_phases
+
+    ms, infos, first, t_build, B_phases = timed("phased")
+    ms_p, infos_p, _, _, _ = timed("persistent")
     active = sum(p.n_active for p in probs)
     cycles = [i["cycles"] for i in infos]
     return {"workload": f"{len(probs)} masked patches (seed 3), {sum(p.mask.size for p in probs)} cells, "
@@ -437,7 +449,13 @@ def batch_measurement(args, solves=3):
                       f"({B_phases} launches per cycle); the first finest pass also forms the norm of its "
                       f"input, then one norm copy and synchronisation per cycle",
             "ms": round(ms, 3), "active_cells_per_s": round(active / (ms * 1e-3), 1),
+            "persistent_ms": round(ms_p, 3),
+            "persistent_engine": "the same programs as phases of one cooperative launch per V-cycle (grid-wide "
+                                 "barriers between phases), same results bit for bit",
+            "persistent_all_converged": all(i["status"] == 0 for i in infos_p),
             "cycles_min": min(cycles), "cycles_max": max(cycles), "cycles_total": int(sum(cycles)),
+            "warmup_cycles_total": int(sum(i["cycles"] for i in first)),
+            "warmup_switched": int(sum(i["switched_at"] > 0 for i in first)),
             "all_converged": all(i["status"] == 0 for i in infos),
             "build_s": round(t_build, 2), "generate_s": round(t_gen, 2)}
 
@@ -561,16 +579,23 @@ def main():
     ms_events = float(np.median([i["ms"] for i in infos64]))
     cycles_mean = float(np.mean([i["cycles"] for i in infos64]))
 
-    # dominant kernel: finest-level smoother, HIP events on the solver's stream
-    launches = args.smoother_launches - (args.smoother_launches % 2)
+    # dominant kernel: finest-level smoother, HIP events on the solver's
+    # stream, in batches of 20 back-to-back launches (a solve interleaves the
+    # finest passes with lighter kernels; one unbroken run of a few hundred
+    # passes has shown a stretch of 10-15% slower launches, which the solves
+    # themselves do not show)
+    launches = args.smoother_launches - (args.smoother_launches % 20)
     H.time_smoother(8)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(H.stream)
-    H.time_smoother(launches)
-    e1.record(H.stream)
-    e1.synchronize()
-    smooth_ms = e0.elapsed_time(e1) / launches
+    total_ms = 0.0
+    for _ in range(launches // 20):
+        e0.record(H.stream)
+        H.time_smoother(20)
+        e1.record(H.stream)
+        e1.synchronize()
+        total_ms += e0.elapsed_time(e1)
+    smooth_ms = total_ms / launches
     bytes_per = SMOOTH_BYTES_FP64 * n_act
     achieved = bytes_per / (smooth_ms * 1e-3) / 1e9
     phi64 = phi.clone()
