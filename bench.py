@@ -6,8 +6,9 @@ and the residual norm after every cycle, until ||r|| <= 1e-10 ||f||.  Inputs
 are resident in HBM before the timed region.
 
 Also measured here, for the dominant kernel (the finest-level smoother):
-its average launch duration with HIP events on the solver's stream, and the
-oracle (plain FP64 C, host cores) on a bounded sample of the same workload.
+its average launch duration inside the timed solves, from HIP event pairs on
+the solver's stream, and the oracle (plain FP64 C, host cores) on a bounded
+sample of the same workload.
 
 Beside it (not part of `value`): the same solve with FP32 inner cycles in
 FP64 iterative refinement, from an interpolated (coarse-solve) guess and from
@@ -524,14 +525,16 @@ def main():
     rho = torch.from_numpy(p.rho).to(dev)
     phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
 
-    def time_solves(H, make_guess=None, prho=None, pphi=None):
+    def time_solves(H, make_guess=None, prho=None, pphi=None, kernel_timing=False):
         """W warm-up then K timed solves on one fresh hierarchy, each solve
         timed alone (wall clock, synchronised) and recorded with its regime:
         a solve that starts in second order and switches, or one that starts
         held in first order by an earlier switch (Sec. 4), take different
         cycle counts, so both the mean over the K solves (`value`) and the
         per-regime figures are reported.  Every variant runs the same
-        schedule on its own fresh hierarchy."""
+        schedule on its own fresh hierarchy.  kernel_timing: HIP events on
+        the solver's stream also bracket every plain finest-level red-black
+        launch of the timed solves."""
         prho = rho if prho is None else prho
         pphi = phi if pphi is None else pphi
 
@@ -544,6 +547,8 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        if kernel_timing:
+            H.kernel_timing(True)
         infos, walls = [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -552,6 +557,8 @@ def main():
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t1)
         wall = time.perf_counter() - t0
+        if kernel_timing:
+            H.kernel_timing(False)
         return wall / max(1, args.steps) * 1e3, infos, walls
 
     def regimes(infos, walls):
@@ -573,17 +580,23 @@ def main():
     H = mg.Hierarchy(mask, p.h, precision="fp64", tune=1)
     n_act = H.n_active(0)
     depths64 = H.item_depths()
-    ms_wall, infos64, walls64 = time_solves(H)
+    ms_wall, infos64, walls64 = time_solves(H, kernel_timing=True)
+    k_ms, k_launches = H.kernel_timing_read()
     last = infos64[-1]
     reg64 = regimes(infos64, walls64)
     ms_events = float(np.median([i["ms"] for i in infos64]))
     cycles_mean = float(np.mean([i["cycles"] for i in infos64]))
 
-    # dominant kernel: finest-level smoother, HIP events on the solver's
-    # stream, in batches of 20 back-to-back launches (a solve interleaves the
-    # finest passes with lighter kernels; one unbroken run of a few hundred
-    # passes has shown a stretch of 10-15% slower launches, which the solves
-    # themselves do not show)
+    # dominant kernel: the finest-level plain red-black pass, its average
+    # launch duration from the HIP event pairs that the library's launches of
+    # it in the timed solves record (the kernel's own start and end, on the
+    # solver's stream)
+    if k_launches == 0:
+        raise RuntimeError("no finest-level smoother launch was timed")
+    smooth_ms = k_ms / k_launches
+    # beside it: the same kernel back to back, in batches of 20 launches (an
+    # unbroken run of a few hundred passes shows a stretch of launches 10-15%
+    # slower than inside the solves, where lighter kernels come between them)
     launches = args.smoother_launches - (args.smoother_launches % 20)
     H.time_smoother(8)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -595,7 +608,7 @@ def main():
         e1.record(H.stream)
         e1.synchronize()
         total_ms += e0.elapsed_time(e1)
-    smooth_ms = total_ms / launches
+    b2b_ms = total_ms / max(1, launches)
     bytes_per = SMOOTH_BYTES_FP64 * n_act
     achieved = bytes_per / (smooth_ms * 1e-3) / 1e9
     phi64 = phi.clone()
@@ -720,7 +733,12 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "traffic_gbs": round(traffic / (smooth_ms * 1e-3) / 1e9, 1) if traffic else None,
             "avg_launch_us": round(smooth_ms * 1e3, 3),
+            "launches_timed": k_launches,
+            "timing": "HIP event pair (the kernel's start and end, hipExtLaunchKernel) on each plain "
+                      "finest-level pass of the timed solves",
             "algorithmic_bytes_per_launch": bytes_per,
+            "back_to_back_us": round(b2b_ms * 1e3, 3),
+            "back_to_back_frac": round(bytes_per / (b2b_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         },
         "vcycle": vcycle_rate(n_act, ms_wall, cycles_mean),
     }

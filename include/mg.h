@@ -232,6 +232,23 @@ mg_status mg_vcycle(mg_hierarchy *H, int32_t order, double *x_dev, const double 
  */
 mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches);
 
+/*
+ * Duration of the finest level's plain red-black passes inside later solves
+ * (the passes that neither form the input norm nor apply the prolongation;
+ * FP64, or FP32 in a mixed solve): enable = 1 clears the record and launches
+ * each such pass with a pair of HIP events that take the kernel's own start
+ * and end times (hipExtLaunchKernel), up to 1024 launches; a launch of a
+ * cycle that the device stop test halted is dropped from the record; enable
+ * = 0 stops recording.  Both synchronise the stream first.  MG_ERR_ARG for
+ * another enable value or with use_graph set (a captured cycle records no
+ * events).
+ */
+mg_status mg_kernel_timing(mg_hierarchy *H, int32_t enable);
+
+/* Synchronise the stream; *ms_total = the summed durations of the recorded
+ * launches, *launches = their count. */
+mg_status mg_kernel_timing_read(mg_hierarchy *H, double *ms_total, int32_t *launches);
+
 /* The stream the hierarchy enqueues on (as void*). */
 void *mg_stream(const mg_hierarchy *H);
 

@@ -520,8 +520,13 @@ void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur 
             else launch_rbgs2(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream);
             p += 2;
         } else {
-            if (f32) launch_rbgs32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream);
-            else launch_rbgs(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream);
+            // optional timing: the kernel's own start and end on a pair of events
+            const bool timed = l == 0 && H->kt_on && od.nsegs > 0 && H->kt_used * 2 < (int)H->kt_ev.size();
+            hipEvent_t e0 = timed ? H->kt_ev[2 * H->kt_used] : nullptr;
+            hipEvent_t e1 = timed ? H->kt_ev[2 * H->kt_used + 1] : nullptr;
+            if (f32) HIPCHK(launch_rbgs32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream, e0, e1));
+            else HIPCHK(launch_rbgs(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream, e0, e1));
+            if (timed) H->kt_used++;
             p += 1;
         }
         cur.c[l] = b;
@@ -824,6 +829,7 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
         // allowed cycle's norm comes from the residual-norm march.
         bool launched = false;  // cycle S.n + 1 is in the stream
         int par_next = S.parity;  // buffer of the iterate of cycle S.n + 1
+        int kt_mark = 0;          // timing records before the cycle after S.n + 1
         while (S.active) {
             if (!launched) {
                 enqueue_cycle(H, S.order, S.parity, false, &par_next, false, NORM_NONE);
@@ -832,6 +838,7 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
             const int k = S.n + 1;
             const int slot = 4 + (k & 1);
             int par_after = par_next;
+            kt_mark = H->kt_used;
             if (k + 1 <= o.max_cycles) {
                 const InputNorm in{H->stop_dev, H->norm_host + slot, H->evq[k & 1]};
                 enqueue_cycle(H, S.order, par_next, false, &par_after, true, NORM_INPUT, &in);
@@ -848,8 +855,10 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
             solve_cycle_finish(H, S);
             S.parity = par_next;
             if (!S.active || S.order != order_before) {
-                // the device stop test halted the rest of cycle k + 1
+                // the device stop test halted the rest of cycle k + 1 (its
+                // launches returned at once: drop their timing records)
                 launched = false;
+                H->kt_used = kt_mark;
                 if (S.active) {
                     launch_set_halt(H->halt_dev, 0, s);
                     set_device_stop(H, S);
@@ -867,15 +876,16 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
         return S.st;
     }
     struct Flight {
-        int parity_out, slot, ev;
+        int parity_out, slot, ev, kt_mark;
     } fl[2];
     int nf = 0, enq = 0, par = S.parity;
     auto launch = [&]() {
         const int k = enq & 1;
         int np = par;
+        const int kt_mark = H->kt_used;
         run_cycle(H, S.order, par, S.mixed, &np, true, 4 + k);
         HIPCHK(hipEventRecord(H->evq[k], s));
-        fl[nf++] = Flight{np, 4 + k, k};
+        fl[nf++] = Flight{np, 4 + k, k, kt_mark};
         par = np;
         enq++;
     };
@@ -891,7 +901,10 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
         nf--;
         if (!S.active || S.order != order_before) {
             // the cycle in flight found the halt flag set and did nothing
-            if (nf) HIPCHK(hipEventSynchronize(H->evq[fl[0].ev]));
+            if (nf) {
+                HIPCHK(hipEventSynchronize(H->evq[fl[0].ev]));
+                H->kt_used = fl[0].kt_mark;
+            }
             nf = 0;
             par = S.parity;
             if (S.active) {
@@ -1034,6 +1047,7 @@ void mg_destroy_hierarchy(mg_hierarchy *H) {
     }
     if (H->norm_host) (void)hipHostFree(H->norm_host);
     if (H->own_stream && H->stream) (void)hipStreamDestroy(H->stream);
+    for (hipEvent_t e : H->kt_ev) (void)hipEventDestroy(e);
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
     for (int q = 0; q < 2; q++)
@@ -1394,6 +1408,47 @@ mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches) {
         }
         if (launches & 1)
             HIPCHK(hipMemcpyAsync(L0.x[0], L0.x[1], L0.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
+        return MG_OK;
+    });
+}
+
+mg_status mg_kernel_timing(mg_hierarchy *H, int32_t enable) {
+    if (!H || (enable != 0 && enable != 1)) {
+        set_error("invalid argument");
+        return MG_ERR_ARG;
+    }
+    if (enable && H->opt.use_graph) {
+        set_error("mg_kernel_timing: a captured cycle records no events (use_graph is set)");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        HIPCHK(hipSetDevice(H->device));
+        HIPCHK(hipStreamSynchronize(H->stream));  // no recorded pair is still pending
+        if (enable && H->kt_ev.empty()) {
+            H->kt_ev.assign(2 * KT_MAX_LAUNCHES, nullptr);
+            for (hipEvent_t &e : H->kt_ev) HIPCHK(hipEventCreate(&e));
+        }
+        H->kt_on = enable != 0;
+        if (enable) H->kt_used = 0;
+        return MG_OK;
+    });
+}
+
+mg_status mg_kernel_timing_read(mg_hierarchy *H, double *ms_total, int32_t *launches) {
+    if (!H || !ms_total || !launches) {
+        set_error("invalid argument");
+        return MG_ERR_ARG;
+    }
+    return guarded([&]() {
+        HIPCHK(hipStreamSynchronize(H->stream));
+        double total = 0.0;
+        for (int i = 0; i < H->kt_used; i++) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, H->kt_ev[2 * i], H->kt_ev[2 * i + 1]));
+            total += ms;
+        }
+        *ms_total = total;
+        *launches = H->kt_used;
         return MG_OK;
     });
 }

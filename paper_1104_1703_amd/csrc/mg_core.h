@@ -95,6 +95,10 @@ struct Graph {
 
 }  // namespace mg
 
+namespace mg {
+constexpr int KT_MAX_LAUNCHES = 1024;  // launches one kernel-timing record holds
+}
+
 struct mg_hierarchy {
     mg_options opt;
     hipStream_t stream = nullptr;
@@ -118,6 +122,12 @@ struct mg_hierarchy {
     std::vector<mg::Graph> graphs;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evq[2] = {nullptr, nullptr};  // ends of the (at most two) cycles in flight
+    // optional timing of the finest level's plain red-black launches inside
+    // solves: an event pair per launch (the kernel's own start and end), up
+    // to kt_ev.size() / 2 launches
+    bool kt_on = false;
+    std::vector<hipEvent_t> kt_ev;
+    int kt_used = 0;
 };
 
 namespace mg {
@@ -173,10 +183,12 @@ void launch_item_masks(const Level &L, int level, int order, const OrderData &od
 
 // -------- smoother (smooth.hip) --------
 // One red-black pass over the segments of `od`; xin == nullptr reads zero.
-void launch_rbgs(const Level &L, int level, const OrderData &od, const double *xin, double *xout,
-                 const double *f, hipStream_t s);
-void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
-                   hipStream_t s);
+// On the finest level, events e0 / e1 (if given) take the kernel's own start
+// and end times (hipExtLaunchKernel); the launch status is returned.
+hipError_t launch_rbgs(const Level &L, int level, const OrderData &od, const double *xin, double *xout,
+                       const double *f, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout,
+                         const float *f, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // A finest-level FP64 pass (xin != nullptr) that also writes the residual
 // norm partials of its input xin, one per work item, to part[0 .. od.nsegs):
 // the same values, bit for bit, as launch_resnorm's partials of xin.

@@ -22,6 +22,8 @@
 // of inactive neighbours) are never fetched, and inactive cells are never
 // stored.  Net HBM traffic per pass: one read of x, f and the code/diagonal
 // and one write of x, on granules holding active cells.
+#include <hip/hip_ext.h>
+
 #include "cube_core.h"
 #include "mg_core.h"
 #include "smooth2_core.h"
@@ -132,19 +134,43 @@ static_assert((SEGZ_COARSE1 == 2 || SEGZ_COARSE1 == 4 || SEGZ_COARSE1 == 8) &&
                   (SEGZ_COARSE == 2 || SEGZ_COARSE == 4 || SEGZ_COARSE == 8),
               "coarse item depths have kernel instances for 2, 4 and 8 planes");
 
-void launch_rbgs(const Level &L, int level, const OrderData &od, const double *xin, double *xout, const double *f,
-                 hipStream_t s) {
-    if (od.nsegs == 0) return;
+// A finest-level pass; with events, launched so that e0 and e1 take the
+// kernel's own start and end times.
+template <typename T>
+hipError_t launch_fine(const Level &L, const OrderData &od, const T *xin, T *xout, const T *f, T h2, hipStream_t s,
+                       hipEvent_t e0, hipEvent_t e1) {
+    hipError_t err = hipSuccess;
+    with_fine_depth(od.depth, [&](auto Z) {
+        auto kern = k_rbgs<T, true, decltype(Z)::value>;
+        const dim3 grid(grid8(od.nsegs)), block(NT);
+        if (!e0 && !e1) {
+            k_rbgs<T, true, decltype(Z)::value><<<grid, block, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny,
+                                                                       L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
+            return;
+        }
+        const uint8_t *code = L.code;
+        const T *dco = nullptr, *xc = nullptr;
+        int nx = L.nx, ny = L.ny, nz = L.nz, nsegs = od.nsegs, c0 = 0;
+        const Seg *segs = od.segs;
+        const unsigned long long *pm = od.pmask;
+        const int *halt = L.halt;
+        void *args[] = {&xin, &xout, &f, &code, &dco, &nx, &ny, &nz, &h2, &segs, &pm, &nsegs, &halt, &xc, &c0, &c0, &c0};
+        err = hipExtLaunchKernel((const void *)kern, grid, block, args, 0, s, e0, e1, 0);
+    });
+    return err;
+}
+
+hipError_t launch_rbgs(const Level &L, int level, const OrderData &od, const double *xin, double *xout,
+                       const double *f, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (od.nsegs == 0) return hipSuccess;
     const double h2 = L.h * L.h;
     if (level == 0)
-        with_fine_depth(od.depth, [&](auto Z) {
-            k_rbgs<double, true, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(
-                xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
-        });
+        return launch_fine<double>(L, od, xin, xout, f, h2, s, e0, e1);
     else if (od.cube)
         launch_cube<double>(xin, xout, f, od.d, L, od, h2, s);
     else
         launch_coarse<double>(od.depth, xin, xout, f, od.d, L, od, h2, s);
+    return hipSuccess;
 }
 
 void launch_rbgs_norm(const Level &L, const OrderData &od, const double *xin, double *xout, const double *f,
@@ -234,19 +260,17 @@ void launch_rbgs2_prolong32(const Level &L, const OrderData &od, const Level &C,
         xc, C.nx, C.ny, C.nz);
 }
 
-void launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout, const float *f,
-                   hipStream_t s) {
-    if (od.nsegs == 0) return;
+hipError_t launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout,
+                         const float *f, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (od.nsegs == 0) return hipSuccess;
     const float h2 = (float)(L.h * L.h);
     if (level == 0)
-        with_fine_depth(od.depth, [&](auto Z) {
-            k_rbgs<float, true, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(
-                xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
-        });
+        return launch_fine<float>(L, od, xin, xout, f, h2, s, e0, e1);
     else if (od.cube)
         launch_cube<float>(xin, xout, f, od.d32, L, od, h2, s);
     else
         launch_coarse<float>(od.depth, xin, xout, f, od.d32, L, od, h2, s);
+    return hipSuccess;
 }
 
 }  // namespace mg

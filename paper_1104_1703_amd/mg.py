@@ -75,6 +75,8 @@ SYMBOLS = [
     ("mg_prolong", C.c_int, [_P, _I, _I, _P, _P]),
     ("mg_vcycle", C.c_int, [_P, _I, _P, _P]),
     ("mg_time_smoother", C.c_int, [_P, _I, _I]),
+    ("mg_kernel_timing", C.c_int, [_P, _I]),
+    ("mg_kernel_timing_read", C.c_int, [_P, C.POINTER(_D), C.POINTER(_I)]),
     ("mg_stream", _P, [_P]),
     ("mg_create_batch", C.c_int, [_I, _P, _P, _P, C.POINTER(Options), _P, C.POINTER(_P)]),
     ("mg_solve_batch", C.c_int, [_P, _P, _P, _P, _D, _P, C.POINTER(_D)]),
@@ -356,6 +358,18 @@ class Hierarchy:
 
     def time_smoother(self, launches: int, order: int = 2):
         _check(self._call(load_library().mg_time_smoother, self._h, order, launches), "mg_time_smoother")
+
+    def kernel_timing(self, enable: bool):
+        """Start (clearing the record) or stop HIP-event timing of the finest
+        level's plain red-black launches inside later solves."""
+        _check(self._call(load_library().mg_kernel_timing, self._h, int(bool(enable))), "mg_kernel_timing")
+
+    def kernel_timing_read(self):
+        """(summed milliseconds, launches) of the recorded launches."""
+        ms, n = C.c_double(0.0), C.c_int32(0)
+        _check(self._call(load_library().mg_kernel_timing_read, self._h, C.byref(ms), C.byref(n)),
+               "mg_kernel_timing_read")
+        return ms.value, n.value
 
 
 class Batch:

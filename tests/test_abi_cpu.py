@@ -64,3 +64,6 @@ def test_create_rejects_null_arguments_without_gpu():
     assert lib.mg_solve(None, None, None, None, 1e-10, None) == mg.MG_ERR_ARG
     assert lib.mg_batch_validate(None, None, 0) == -1
     assert lib.mg_level_item_depth(None, 0, 2) == -1
+    ms, n = C.c_double(0.0), C.c_int32(0)
+    assert lib.mg_kernel_timing(None, 1) == mg.MG_ERR_ARG
+    assert lib.mg_kernel_timing_read(None, C.byref(ms), C.byref(n)) == mg.MG_ERR_ARG

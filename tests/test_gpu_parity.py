@@ -339,6 +339,40 @@ def test_max_cycles_status(mg):
     H.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_kernel_timing_leaves_the_solve_unchanged(mg, precision):
+    """Event pairs around the finest plain passes of a solve (the benchmark's
+    in-solve kernel timing): the same solution bit for bit.  With n_pre =
+    n_post = 2 a cycle has three plain passes (the one that applies the
+    prolongation is not plain); in FP64 the first pass of every cycle after
+    the first also forms the input norm, except right after an order switch,
+    and a halted speculative cycle leaves no record."""
+    p = gen.holes_problem(n=64, seed=2)
+    ref_H = mg.Hierarchy(dev(p.mask), p.h, precision=precision)
+    ref, rinfo = ref_H.solve(dev(p.rho), tol=1e-10)
+    H = mg.Hierarchy(dev(p.mask), p.h, precision=precision)
+    H.kernel_timing(True)
+    got, info = H.solve(dev(p.rho), tol=1e-10)
+    ms, n = H.kernel_timing_read()
+    print(f"[case] holes64 {precision}: {n} launches, {ms / max(n, 1) * 1e3:.2f} us each", flush=True)
+    assert info["cycles"] == rinfo["cycles"] and np.array_equal(host(got), host(ref))
+    if precision == "fp64":
+        assert n == 2 * info["cycles"] + 1 + (info["switched_at"] >= 0)
+    else:
+        assert n == 3 * info["cycles"]
+    assert ms > 0
+    H.kernel_timing(False)
+    H.solve(dev(p.rho), tol=1e-10)
+    assert H.kernel_timing_read()[1] == n          # stopped: the record is kept
+    H.kernel_timing(True)
+    assert H.kernel_timing_read() == (0.0, 0)      # restarted: cleared
+    G = mg.Hierarchy(dev(p.mask), p.h, use_graph=1)
+    with pytest.raises(RuntimeError):
+        G.kernel_timing(True)
+    for X in (ref_H, H, G):
+        X.close()
+
+
 # ---------------------------------------------------------------- full size
 def _check_solve_pair(info, rinfo, got, ref, act, what):
     assert info["status"] == rinfo["status"] == 0, what
