@@ -231,13 +231,14 @@ struct Launch {
 // per-phase kernel's blocks take them (virtual block vb -> item
 // xcd_item(vb, grid)), so each item runs the same device code on the same
 // data and partial sums land in the same slots: results are bit for bit
-// those of the per-phase engine.  Blocks are 256 threads; the small-level
-// call runs with 256 threads (its sweeps are in place per colour and its
-// transfers per cell, so the thread count does not change a result) with
-// its levels in LDS: a block's dynamic LDS is the largest of the phases'
-// needs (at least PERSIST_LDS), which sets how many blocks share a CU.
-constexpr int PERSIST_LDS = 40 * 1024;               // smallest dynamic LDS of a block
-constexpr unsigned PERSIST_SPIN_LIMIT = 1u << 22;    // barrier wait bound (about 0.2 s), then err
+// those of the per-phase engine.  Blocks are 256 threads with PERSIST_LDS
+// of dynamic LDS (four blocks per CU).  The small-level call runs with 256
+// threads (its sweeps are in place per colour and its transfers per cell,
+// so the thread count does not change a result), its levels in LDS where
+// they fit PERSIST_LDS, else in a global-memory area of the block's own
+// (block barriers only).
+constexpr int PERSIST_LDS = 38 * 1024;  // dynamic LDS of a block (with the static part, 4 per CU)
+constexpr unsigned PERSIST_SPIN_LIMIT = 1u << 22;    // barrier polls (seconds in all), then err
 static_assert(sizeof(rb::RbgsLds<double, true, true>) <= PERSIST_LDS &&
                   sizeof(rb::RbgsLds<double, false, true>) <= PERSIST_LDS &&
                   sizeof(tr::ResLds<double>) <= PERSIST_LDS && 1024 * sizeof(double) <= PERSIST_LDS,
@@ -264,36 +265,46 @@ struct PArgs {
     double *const *phi;
     unsigned *bar;  // [2]: arrivals, generation
     int *err;       // set when a barrier wait exceeds its bound
+    const int *sbytes[3];  // per order and patch: bytes of its small-level call's levels
+    double *gsmall;        // per block: gsmall_elems doubles for a call above PERSIST_LDS
+    long long gsmall_elems;
 };
 
-// Grid-wide barrier of a co-resident launch.  Every thread's global writes
-// are made visible at device scope before the block arrives, and every
-// thread's view is refreshed after it leaves.  The wait is bounded: past
+// Grid-wide barrier of a co-resident launch.  One thread per block: an
+// agent-scope release fence (the block's global writes, ordered before it by
+// the block barrier, are written back from this XCD's L2), a relaxed arrival
+// on the counter, a relaxed spin on the generation word, then one
+// agent-scope acquire fence (this XCD's L2 and the CU's L1 are invalidated).
+// The spin issues plain coherent loads: an acquire load per iteration would
+// invalidate the XCD's L2 on every poll while other blocks still work.  The
+// last arrival acquires every other block's release (it read their arrivals)
+// and releases before it bumps the generation.  The wait is bounded: past
 // the bound it raises err and goes on, so every wave reaches the kernel's
 // end (the host then reports the error).
 __device__ void persist_sync(unsigned *bar, int *err) {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned arrived =
-            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
         if (arrived == gridDim.x) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             unsigned spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
                 if (++spins > PERSIST_SPIN_LIMIT) {
                     __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __threadfence();
 }
 
 // Work item of virtual block vb of a phase with `grid` virtual blocks, as
@@ -339,6 +350,11 @@ __device__ __attribute__((noinline)) void p_residual(unsigned char *smem, const 
 __device__ __attribute__((noinline)) void p_small(unsigned char *smem, const small::SmallLevels<double> &S,
                                                   const double *f0, double *x0, bool load_x) {
     small::small_tail<double, rb::NT>(reinterpret_cast<double *>(smem), S, f0, x0, load_x);
+}
+
+__device__ __attribute__((noinline)) void p_small_global(double *area, const small::SmallLevels<double> &S,
+                                                         const double *f0, double *x0, bool load_x) {
+    small::small_tail<double, rb::NT, false>(area, S, f0, x0, load_x);
 }
 
 __device__ __attribute__((noinline)) void p_cell(int kind, const BLev &L, int idx, int sel, const double *rho,
@@ -404,7 +420,11 @@ __global__ __launch_bounds__(rb::NT, 4) void kb_persist(PArgs A) {
                     if (S.state[p] != order) continue;
                     const BLev &L = lev[r.lev];
                     const int sel = r.w >> WBITS;
-                    p_small(smem, A.sl[order][p], L.f, L.x[sel & 1], (sel & 2) == 0);
+                    if (A.sbytes[order][p] <= PERSIST_LDS)
+                        p_small(smem, A.sl[order][p], L.f, L.x[sel & 1], (sel & 2) == 0);
+                    else
+                        p_small_global(A.gsmall + (size_t)blockIdx.x * A.gsmall_elems, A.sl[order][p], L.f,
+                                       L.x[sel & 1], (sel & 2) == 0);
                     __syncthreads();
                 }
                 continue;
@@ -487,6 +507,9 @@ struct mg_batch {
     bool use_persist = false;
     mg::Launch *dk[5] = {};
     int plds = 0;  // dynamic LDS of a persistent block
+    const int *psbytes[3] = {nullptr, nullptr, nullptr};  // per order, per patch: small-level call bytes
+    double *gsmall = nullptr;     // per persistent block: a global area for the larger small-level calls
+    long long gsmall_elems = 0;
     unsigned *pbar = nullptr;
     int *perr = nullptr;
     int *perr_host = nullptr;  // pinned
@@ -935,24 +958,25 @@ bool build_persistent(mg_batch *B) {
         (void)hipGetLastError();
         return false;
     }
-    // LDS: the largest small-level call of either order (every other phase
-    // needs at most PERSIST_LDS)
-    size_t lds = PERSIST_LDS;
-    for (int o = 1; o <= 2; o++)
-        for (const mg::Launch &k : B->cycle[o].k)
-            if (k.kind == K_SMALL) lds = std::max(lds, k.lds);
-    lds = (lds + 1023) / 1024 * 1024;
-    if (lds > (size_t)B->small_lim) return false;
-    B->plds = (int)lds;
-    if (lds > 64 * 1024 &&
-        hipFuncSetAttribute((const void *)kb_persist, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-            hipSuccess) {
-        (void)hipGetLastError();
-        return false;
+    // per order and patch, the bytes of its small-level call's levels; the
+    // largest sizes the global area of a block (calls above PERSIST_LDS)
+    size_t gmax = 0;
+    for (int o = 1; o <= 2; o++) {
+        std::vector<int> sb(B->n, 0);
+        for (int p = 0; p < B->n; p++) {
+            const mg_hierarchy *H = B->patches[p];
+            if (H->ls[o] >= 0) sb[p] = (int)small_lds_bytes(H, o, H->ls[o], false);
+            if (sb[p] > PERSIST_LDS) gmax = std::max(gmax, (size_t)sb[p]);
+        }
+        B->psbytes[o] = upload(B, sb);
     }
-    BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kb_persist, rb::NT, lds));
+    B->psbytes[0] = B->psbytes[2];
+    B->plds = PERSIST_LDS;
+    BHIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kb_persist, rb::NT, PERSIST_LDS));
     B->pgrid = (per * ncu) / 8 * 8;
     if (B->pgrid < 8) return false;
+    B->gsmall_elems = (long long)((gmax / sizeof(double) + 31) / 32 * 32);
+    if (B->gsmall_elems > 0) B->gsmall = balloc<double>(B, (size_t)B->pgrid * (size_t)B->gsmall_elems);
     const mg_batch::Prog *progs[5] = {&B->begin, &B->end, &B->pre, &B->cycle[1], &B->cycle[2]};
     for (int i = 0; i < 5; i++) B->dk[i] = upload(B, progs[i]->k);
     B->pbar = balloc<unsigned>(B, 2);
@@ -1091,6 +1115,9 @@ void run_persist(mg_batch *B, std::initializer_list<PRun> runs) {
     A.phi = B->in_phi;
     A.bar = B->pbar;
     A.err = B->perr;
+    for (int o = 0; o < 3; o++) A.sbytes[o] = B->psbytes[o];
+    A.gsmall = B->gsmall;
+    A.gsmall_elems = B->gsmall_elems;
     kb_zero_bar<<<1, 64, 0, B->stream>>>(B->pbar, B->perr);
     void *args[] = {&A};
     BHIP(hipLaunchCooperativeKernel((const void *)kb_persist, dim3(B->pgrid), dim3(rb::NT), args, (size_t)B->plds,

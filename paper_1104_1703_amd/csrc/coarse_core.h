@@ -198,10 +198,13 @@ __device__ void smooth_regs(const Lv<T> &L, int passes) {
 }
 
 // Red-black passes; each half-sweep visits only the cells of its colour.
-template <typename T, int NTH>
+// WAVE: a level of at most WAVE_SLOTS slots per colour runs on one wave with
+// no block barrier (levels in LDS only; with levels in global memory every
+// half-sweep ends at a block barrier).
+template <typename T, int NTH, bool WAVE = true>
 __device__ void smooth(const Lv<T> &L, int passes) {
     const int slots = L.hx * L.ny * L.nz;
-    if (slots <= WAVE_SLOTS) {
+    if (WAVE && slots <= WAVE_SLOTS) {
         if (threadIdx.x < 64) smooth_wave(L, passes);
         __syncthreads();
         return;
@@ -268,11 +271,12 @@ __device__ void prolong_from(const Lv<T> &L, const Lv<T> &C) {
     __syncthreads();
 }
 
-// One call MG(ls) for the levels held in S, all resident in LDS at `sm`
-// (the one-wave path relies on a wave's in-order LDS accesses); f0 is level ls's
-// right-hand side and x0 its iterate (in/out), started from zero unless
-// load_x.  Called by all NTH threads of a block.
-template <typename T, int NTH>
+// One call MG(ls) for the levels held in S, all resident at `sm`: in LDS
+// (WAVE: the one-wave path relies on a wave's in-order LDS accesses), or in
+// a global-memory area of the block's own (!WAVE: block barriers only); f0 is
+// level ls's right-hand side and x0 its iterate (in/out), started from zero
+// unless load_x.  Called by all NTH threads of a block.
+template <typename T, int NTH, bool WAVE = true>
 __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, bool load_x) {
     // level descriptors live in LDS (dynamic indexing without private memory)
     __shared__ int s_nx[MAXS], s_ny[MAXS], s_nz[MAXS], s_off[MAXS];
@@ -356,11 +360,11 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
     while (true) {
         if (down) {
             if (l == last) {
-                smooth<T, NTH>(level(l), S.n_coarse);
+                smooth<T, NTH, WAVE>(level(l), S.n_coarse);
                 down = false;
                 continue;
             }
-            smooth<T, NTH>(level(l), S.n_pre);
+            smooth<T, NTH, WAVE>(level(l), S.n_pre);
             restrict_to<T, NTH>(level(l), level(l + 1));
             visits &= ~(7u << (3 * (l + 1)));
             l++;
@@ -374,7 +378,7 @@ __device__ void small_tail(T *sm, const SmallLevels<T> &S, const T *f0, T *x0, b
             continue;
         }
         prolong_from<T, NTH>(level(l - 1), level(l));
-        smooth<T, NTH>(level(l - 1), S.n_post);
+        smooth<T, NTH, WAVE>(level(l - 1), S.n_post);
         l--;
     }
     const Lv<T> top = level(0);
