@@ -558,9 +558,20 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
         return;
     }
     Level &C = H->lev[l + 1];
-    smooth(H, l, order, o.n_pre, zero_start, cur, f32, in);
-    if (f32) launch_restrict32(L, C, l, order, L.x32[cur.c[l]], L.f32, C.f32, H->stream);
-    else launch_restrict(L, C, l, order, L.x[cur.c[l]], L.f, C.f, H->stream);
+    const OrderData &odl = odata(H, l, order);
+    if (l > 0 && odl.cube && o.n_pre >= 1) {
+        // cube levels: the last pre-smoothing pass also restricts the residual
+        if (o.n_pre > 1) smooth(H, l, order, o.n_pre - 1, zero_start, cur, f32, in);
+        const bool zin = zero_start && o.n_pre == 1;
+        const int a = cur.c[l], b = a ^ 1;
+        if (f32) launch_rbgs_restrict32(L, C, order, odl, zin ? nullptr : L.x32[a], L.x32[b], L.f32, C.f32, H->stream);
+        else launch_rbgs_restrict(L, C, order, odl, zin ? nullptr : L.x[a], L.x[b], L.f, C.f, H->stream);
+        cur.c[l] = b;
+    } else {
+        smooth(H, l, order, o.n_pre, zero_start, cur, f32, in);
+        if (f32) launch_restrict32(L, C, l, order, L.x32[cur.c[l]], L.f32, C.f32, H->stream);
+        else launch_restrict(L, C, l, order, L.x[cur.c[l]], L.f, C.f, H->stream);
+    }
     for (int c = 0; c < o.n_cycles; c++) mg_level(H, l + 1, order, c == 0, cur, f32);
     if (o.n_post == 0) {
         if (f32) launch_prolong32(L, C, l, order, C.x32[cur.c[l + 1]], L.x32[cur.c[l]], H->stream);

@@ -106,5 +106,142 @@ __device__ __forceinline__ void rbgs_cube(Lds<T> &L, const T *__restrict__ xin, 
     }
 }
 
+// The same pass followed by the residual r = L x - f of the cube's cells and
+// its R1 restriction onto the 4 x 4 x 4 coarse cells the cube covers (Sec. 2
+// steps 2-4; coarse right-hand side -(1/8) of the sum of the active
+// children's residuals, 0 off the coarse domain): the residual needs the
+// pass's black values on a 1-cell ring too, so red runs on the cube plus a
+// 2-cell ring, black on the cube plus a 1-cell ring, from a 14^3 x region
+// (3-cell halo).  Every value is formed with the expression and order of the
+// stand-alone pass and restriction, so x and the coarse right-hand side are
+// bit for bit theirs.  fc / cd / (cnx, cny, cnz): right-hand side, diagonal
+// and dims of the next coarser level.
+constexpr int RR = C + 6;                                  // x region with a 3-cell halo
+constexpr int RRN = RR * RR * RR;                          // 2744
+constexpr int NRED3 = (C + 4) * (C + 4) * (C + 4) / 2;     // red cells on the cube plus a 2-cell ring: 864
+constexpr int NBLK3 = (C + 2) * (C + 2) * (C + 2) / 2;     // black cells on the cube plus a 1-cell ring: 500
+constexpr int RED_SLOTS = (NRED3 + NT - 1) / NT;           // 4
+constexpr int BLK_SLOTS = (NBLK3 + NT - 1) / NT;           // 2
+
+template <typename T>
+struct LdsRes {
+    T x[RRN];
+    T r[C * C * C];
+};
+
+template <typename T>
+__device__ __forceinline__ void rbgs_cube_restrict(LdsRes<T> &L, const T *__restrict__ xin, T *__restrict__ xout,
+                                                   const T *__restrict__ f, const T *__restrict__ d, int nx, int ny,
+                                                   int nz, T h2, T ih2, int x0, int y0, int z0,
+                                                   const T *__restrict__ cd, T *__restrict__ fc, int cnx, int cny,
+                                                   int cnz) {
+    const int tid = threadIdx.x;
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    auto gidx = [&](int gx, int gy, int gz) { return (size_t)gz * sz + (size_t)gy * sy + (size_t)gx; };
+    auto inbox = [&](int gx, int gy, int gz) {
+        return gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+    };
+    constexpr int E = C + 4, EH = E / 2, F = C + 2, FH = F / 2;
+    // red cells: region coords in [0, 12), origin two cells before the cube
+    // (global i + j + k even: a + b + c even); black: region [0, 10), origin
+    // one cell before (global odd: a + b + c even as well, the origin sum is odd)
+    int ra[RED_SLOTS], rb[RED_SLOTS], rc[RED_SLOTS], ba[BLK_SLOTS], bb[BLK_SLOTS], bc[BLK_SLOTS];
+    T rf[RED_SLOTS], rd[RED_SLOTS], bf[BLK_SLOTS], bd[BLK_SLOTS];
+#pragma unroll
+    for (int s = 0; s < RED_SLOTS; s++) {
+        const int r = tid + s * NT;
+        const bool v = r < NRED3;
+        const int row = v ? r / EH : 0, m = r % EH;
+        rb[s] = row % E;
+        rc[s] = row / E;
+        ra[s] = ((rb[s] + rc[s]) & 1) + 2 * m;
+        const int gx = x0 - 2 + ra[s], gy = y0 - 2 + rb[s], gz = z0 - 2 + rc[s];
+        const bool ok = v && inbox(gx, gy, gz);
+        rd[s] = ok ? d[gidx(gx, gy, gz)] : T(0);
+        rf[s] = ok ? f[gidx(gx, gy, gz)] : T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < BLK_SLOTS; s++) {
+        const int r = tid + s * NT;
+        const bool v = r < NBLK3;
+        const int row = v ? r / FH : 0, m = r % FH;
+        bb[s] = row % F;
+        bc[s] = row / F;
+        ba[s] = ((bb[s] + bc[s]) & 1) + 2 * m;
+        const int gx = x0 - 1 + ba[s], gy = y0 - 1 + bb[s], gz = z0 - 1 + bc[s];
+        const bool ok = v && inbox(gx, gy, gz);
+        bd[s] = ok ? d[gidx(gx, gy, gz)] : T(0);
+        bf[s] = ok ? f[gidx(gx, gy, gz)] : T(0);
+    }
+    // the residual's cells: this thread's two cube cells
+    T qf[2], qd[2];
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        const int e = tid + s * NT;
+        const int a = e % C, b = (e / C) % C, c = e / (C * C);
+        const int gx = x0 + a, gy = y0 + b, gz = z0 + c;
+        const bool ok = inbox(gx, gy, gz);
+        qd[s] = ok ? d[gidx(gx, gy, gz)] : T(0);
+        qf[s] = ok ? f[gidx(gx, gy, gz)] : T(0);
+    }
+    constexpr int XL = (RRN + NT - 1) / NT;  // 11
+    T xv[XL];
+#pragma unroll
+    for (int q = 0; q < XL; q++) {
+        const int e = tid + q * NT;
+        const int u = e % RR, v = (e / RR) % RR, w = e / (RR * RR);
+        const int gx = x0 - 3 + u, gy = y0 - 3 + v, gz = z0 - 3 + w;
+        xv[q] = (e < RRN && xin && inbox(gx, gy, gz)) ? xin[gidx(gx, gy, gz)] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < XL; q++) {
+        const int e = tid + q * NT;
+        if (e < RRN) L.x[e] = xv[q];
+    }
+    __syncthreads();
+    auto nbs = [&](int q) {
+        const T *c = L.x;
+        return (c[q - 1] + c[q + 1]) + (c[q - RR] + c[q + RR]) + (c[q - RR * RR] + c[q + RR * RR]);
+    };
+    auto relax = [&](int q, T fv, T dv) {
+        const T s = nbs(q);
+        L.x[q] = (s - h2 * fv) / dv;
+    };
+#pragma unroll
+    for (int s = 0; s < RED_SLOTS; s++)
+        if (rd[s] != T(0)) relax(((rc[s] + 1) * RR + (rb[s] + 1)) * RR + (ra[s] + 1), rf[s], rd[s]);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < BLK_SLOTS; s++)
+        if (bd[s] != T(0)) relax(((bc[s] + 2) * RR + (bb[s] + 2)) * RR + (ba[s] + 2), bf[s], bd[s]);
+    __syncthreads();
+    // store the cube and form its residual
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        const int e = tid + s * NT;
+        const int a = e % C, b = (e / C) % C, c = e / (C * C);
+        const int q = ((c + 3) * RR + (b + 3)) * RR + (a + 3);
+        const int gx = x0 + a, gy = y0 + b, gz = z0 + c;
+        const T xq = L.x[q];
+        if (inbox(gx, gy, gz)) xout[gidx(gx, gy, gz)] = xq;
+        const T sn = nbs(q);
+        L.r[e] = qd[s] != T(0) ? (sn - qd[s] * xq) * ih2 - qf[s] : T(0);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int I = tid % 4, J = (tid / 4) % 4, K = tid / 16;
+        const int gI = x0 / 2 + I, gJ = y0 / 2 + J, gK = z0 / 2 + K;
+        if (gI < cnx && gJ < cny && gK < cnz) {
+            const size_t P = (size_t)gK * cnx * cny + (size_t)gJ * cnx + gI;
+            const T cdv = cd[P];
+            T s = T(0);
+#pragma unroll
+            for (int c = 0; c < 8; c++)  // children in x, y, z order
+                s += L.r[((2 * K + (c >> 2)) * C + (2 * J + ((c >> 1) & 1))) * C + (2 * I + (c & 1))];
+            fc[P] = cdv != T(0) ? -s / T(8) : T(0);
+        }
+    }
+}
+
 }  // namespace cube
 }  // namespace mg

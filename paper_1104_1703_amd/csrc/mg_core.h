@@ -189,6 +189,13 @@ hipError_t launch_rbgs(const Level &L, int level, const OrderData &od, const dou
                        const double *f, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_rbgs32(const Level &L, int level, const OrderData &od, const float *xin, float *xout,
                          const float *f, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// A pass over the 8^3 cubes of a coarse level (od.cube) that also forms the
+// residual and its R1 restriction fc onto the next coarser level C (in
+// order `order`): bit for bit launch_rbgs followed by launch_restrict.
+void launch_rbgs_restrict(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
+                          double *xout, const double *f, double *fc, hipStream_t s);
+void launch_rbgs_restrict32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
+                            float *xout, const float *f, float *fc, hipStream_t s);
 // A finest-level FP64 pass (xin != nullptr) that also writes the residual
 // norm partials of its input xin, one per work item, to part[0 .. od.nsegs):
 // the same values, bit for bit, as launch_resnorm's partials of xin.

@@ -102,9 +102,47 @@ __global__ __launch_bounds__(cube::NT) void k_rbgs_cube(const T *__restrict__ xi
     cube::rbgs_cube<T>(lds, xin, xout, f, d, nx, ny, nz, h2, x0, ty * TY, tz * TZ);
 }
 
+// The cube pass that also forms the residual and its R1 restriction onto
+// the next coarser level (the last pre-smoothing pass of a cube level).
+template <typename T>
+__global__ __launch_bounds__(cube::NT) void k_rbgs_cube_restrict(
+    const T *__restrict__ xin, T *__restrict__ xout, const T *__restrict__ f, const T *__restrict__ d, int nx, int ny,
+    int nz, int ntx, int nty, T h2, T ih2, const int *__restrict__ tiles, int ntiles, const int *__restrict__ halt,
+    const T *__restrict__ cd, T *__restrict__ fc, int cnx, int cny, int cnz) {
+    __shared__ cube::LdsRes<T> lds;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= 4 * ntiles || (halt && *halt)) return;
+    const int tile = tiles[item >> 2];
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int x0 = tx * TX + (item & 3) * cube::C;
+    if (x0 >= nx) return;  // a tile wider than the level
+    cube::rbgs_cube_restrict<T>(lds, xin, xout, f, d, nx, ny, nz, h2, ih2, x0, ty * TY, tz * TZ, cd, fc, cnx, cny,
+                                cnz);
+}
+
 inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
 
 }  // namespace
+
+template <typename T>
+void launch_cube_restrict(const T *xin, T *xout, const T *f, const T *d, const Level &L, const OrderData &od, T h2,
+                          T ih2, const Level &C, const T *cd, T *fc, hipStream_t s) {
+    if (od.ntiles == 0) return;
+    k_rbgs_cube_restrict<T><<<grid8(4 * od.ntiles), cube::NT, 0, s>>>(xin, xout, f, d, L.nx, L.ny, L.nz, L.ntx,
+                                                                     L.nty, h2, ih2, od.tiles, od.ntiles, L.halt, cd,
+                                                                     fc, C.nx, C.ny, C.nz);
+}
+
+void launch_rbgs_restrict(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
+                          double *xout, const double *f, double *fc, hipStream_t s) {
+    launch_cube_restrict<double>(xin, xout, f, od.d, L, od, L.h * L.h, 1.0 / (L.h * L.h), C, C.od[order].d, fc, s);
+}
+
+void launch_rbgs_restrict32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
+                            float *xout, const float *f, float *fc, hipStream_t s) {
+    launch_cube_restrict<float>(xin, xout, f, od.d32, L, od, (float)(L.h * L.h), (float)(1.0 / (L.h * L.h)), C,
+                                C.od[order].d32, fc, s);
+}
 
 template <typename T>
 void launch_cube(const T *xin, T *xout, const T *f, const T *d, const Level &L, const OrderData &od, T h2,
