@@ -254,10 +254,28 @@ void tune_cache_put(const std::string &key, int depth) {
 // with the outer residual (mixed).  At creation every iterate and
 // right-hand side buffer holds zeros, which this work keeps; it costs the
 // same on any values.
-float time_pass(mg_hierarchy *H, int l, const OrderData &od, bool f32) {
+float time_pass(mg_hierarchy *H, int l, int order, const OrderData &od, bool f32) {
     Level &L = H->lev[l];
     const bool coarse = H->nlev[2] > 1;
+    // a coarse level with a coarser one restricts after every other pass
+    // (on cubes inside the pass itself)
+    const bool restricts = l > 0 && l + 1 < H->nlev[order];
     auto pass = [&](int p) {
+        if (restricts && (p & 1)) {
+            Level &C = H->lev[l + 1];
+            if (od.cube) {
+                if (f32) launch_rbgs_restrict32(L, C, order, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, C.f32,
+                                                H->stream);
+                else launch_rbgs_restrict(L, C, order, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, C.f, H->stream);
+            } else if (f32) {
+                launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream);
+                launch_restrict32(L, C, l, order, L.x32[(p & 1) ^ 1], L.f32, C.f32, H->stream);
+            } else {
+                launch_rbgs(L, l, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, H->stream);
+                launch_restrict(L, C, l, order, L.x[(p & 1) ^ 1], L.f, C.f, H->stream);
+            }
+            return;
+        }
         if (f32) launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream);
         else launch_rbgs(L, l, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, H->stream);
         if (l != 0 || (p & 1) == 0) return;
@@ -308,13 +326,13 @@ void tune_depths(mg_hierarchy *H) {
             if (!depth_supported(l, best) && !(l > 0 && best == DEPTH_CUBE && !H->opt.fuse_passes)) {
                 const int cand0[3] = {8, 16, 32}, cand1[3] = {2, 4, 8};
                 const int *cand = l == 0 ? cand0 : cand1;
-                float tbest = time_pass(H, l, od, f32);
+                float tbest = time_pass(H, l, o, od, f32);
                 best = od.depth;
                 for (int c = 0; c < 3; c++) {
                     if (cand[c] == od.depth) continue;
                     OrderData t = od;
                     build_lists(H, l, o, cand[c], t);
-                    const float tc = time_pass(H, l, t, f32);
+                    const float tc = time_pass(H, l, o, t, f32);
                     HIPCHK(hipStreamSynchronize(H->stream));
                     if (tc < tbest) {
                         tbest = tc;
@@ -325,7 +343,7 @@ void tune_depths(mg_hierarchy *H) {
                 if (l > 0 && !H->opt.fuse_passes) {  // whole 8^3 cubes instead of a march
                     OrderData t = od;
                     t.cube = true;
-                    if (time_pass(H, l, t, f32) < tbest) best = DEPTH_CUBE;
+                    if (time_pass(H, l, o, t, f32) < tbest) best = DEPTH_CUBE;
                 }
                 tune_cache_put(key, best);
             }
