@@ -91,68 +91,114 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
 #pragma unroll
         for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Staging: thread t copies the 16-byte piece `sub` of voxels t / SUB,
+    // t / SUB + VPT, ... of the halo tile, its (hx, hy, hz) stepped by VPT
+    // voxels in mixed radix (no divisions in the loop).
+    constexpr int SUB = CK / 8, VPT = NTH / SUB;
+    constexpr int SDX = VPT % HX, SDY = (VPT / HX) % HY, SDZ = VPT / (HX * HY);
+    const int sub = threadIdx.x % SUB, hv0 = threadIdx.x / SUB;
+    // A fragments: LDS element offset of tap (dz, dy, dx) is toff * CKP with
+    // toff = ((dz - 1) HY + dy - 1) HX + dx - 1 >= -TMIN; bases shifted by
+    // TMIN keep every offset a non-negative constant
+    constexpr int TMIN = HY * HX + HX + 1;
+    const bf16 *tb[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) tb[mt] = tile + (hb[mt] - TMIN) * CKP;
+    // weights [tap][co][ci]: a uniform per-tap base and this lane's offset
+    const size_t wtap = (size_t)cout * cin;
     for (int c0 = 0; c0 < cin; c0 += CK) {
         __syncthreads();
-        for (int e = threadIdx.x; e < HV * (CK / 8); e += NTH) {
-            const int hv = e / (CK / 8), c8 = (e - hv * (CK / 8)) * 8;
-            const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-            const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-            const int c = c0 + c8;
-            bf16x8 v = zero8();
-            if (c < cin && gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D) {
-                if (c < ca) {
-                    const size_t vox = upa ? (((size_t)n * Dc + (gz >> 1)) * Hc + (gy >> 1)) * Wc + (gx >> 1)
-                                           : (((size_t)n * D + gz) * H + gy) * W + gx;
-                    v = *(const bf16x8 *)(ina + vox * ca + c);
-                } else {
-                    const size_t vox = (((size_t)n * D + gz) * H + gy) * W + gx;
-                    v = *(const bf16x8 *)(inb + vox * cb + (c - ca));
+        {
+            const int c = c0 + sub * 8;  // this thread's 8 channels: all of a or all of b (8 | ca)
+            const bool cok = c < cin, isa = c < ca;
+            const bf16 *src = isa ? ina + c : inb + (c - ca);
+            const int cs = isa ? ca : cb;
+            int hv = hv0, hx = hv0 % HX, hy = (hv0 / HX) % HY, hz = hv0 / (HX * HY);
+#pragma unroll
+            for (int k = 0; k < (HV + VPT - 1) / VPT; k++) {
+                if (hv < HV) {
+                    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+                    bf16x8 v = zero8();
+                    if (cok && (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H && (unsigned)gz < (unsigned)D) {
+                        const size_t vox = (isa && upa) ? (((size_t)n * Dc + (gz >> 1)) * Hc + (gy >> 1)) * Wc + (gx >> 1)
+                                                        : (((size_t)n * D + gz) * H + gy) * W + gx;
+                        v = *(const bf16x8 *)(src + vox * cs);
+                    }
+                    *(bf16x8 *)(tile + hv * CKP + sub * 8) = v;
                 }
+                hv += VPT;
+                hx += SDX;
+                if (hx >= HX) {
+                    hx -= HX;
+                    hy++;
+                }
+                hy += SDY;
+                if (hy >= HY) {
+                    hy -= HY;
+                    hz++;
+                }
+                hz += SDZ;
             }
-            *(bf16x8 *)(tile + hv * CKP + c8) = v;
         }
         __syncthreads();
         if (CK == 32 && (!HALF || cin - c0 >= 32)) {
             const int cw = c0 + grp * 8;  // this lane's 8 K entries: channels cw .. cw + 7 of one tap
+            unsigned wl[NTC];  // byte offsets within a tap's weights
+#pragma unroll
+            for (int nt = 0; nt < NTC; nt++) wl[nt] = (unsigned)(((co_base + nt * 16 + row) * cin + cw) * 2);
 #pragma unroll 1
             for (int tzy = 0; tzy < 9; ++tzy) {  // (dz, dy) rows of taps; the 3 dx taps unrolled
-                const int rowoff = ((tzy / 3 - 1) * HY + tzy % 3 - 1) * HX;
+                const int rowoff = ((tzy / 3 - 1) * HY + tzy % 3 - 1) * HX;  // uniform
+                // the row's 3 x MT A fragments and 3 x NTC B fragments are all
+                // read before its matrix products
+                bf16x8 afr[3][MT], bfr[3][NTC];
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
-                    const int tap = tzy * 3 + dx;
-                    const int toff = rowoff + dx - 1;
-                    bf16x8 bfr[NTC];
+                    const char *wb = (const char *)(wt + (tzy * 3 + dx) * wtap);  // uniform
 #pragma unroll
-                    for (int nt = 0; nt < NTC; nt++) {
-                        const int co = co_base + nt * 16 + row;
-                        bfr[nt] = *(const bf16x8 *)(wt + ((size_t)tap * cout + co) * cin + cw);
-                    }
-#pragma unroll
-                    for (int mt = 0; mt < MT; mt++) {
-                        const bf16x8 afr = *(const bf16x8 *)(tile + (hb[mt] + toff) * CKP + grp * 8);
-#pragma unroll
-                        for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = mfma(afr, bfr[nt], acc[mt][nt]);
-                    }
+                    for (int nt = 0; nt < NTC; nt++) bfr[dx][nt] = *(const bf16x8 *)(wb + wl[nt]);
                 }
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int mt = 0; mt < MT; mt++)
+                        afr[dx][mt] = *(const bf16x8 *)(tb[mt] + (rowoff + TMIN - 1 + dx) * CKP + grp * 8);
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+                        for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = mfma(afr[dx][mt], bfr[dx][nt], acc[mt][nt]);
+                // schedule: the row's weight loads, its LDS reads, then its matrix products
+                __builtin_amdgcn_sched_group_barrier(0x020, 3 * NTC, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 3 * MT, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 3 * MT * NTC, 0);
             }
         } else if constexpr (CK == 16 || HALF) {
             // 16 channels per tap: one K step of 32 covers taps 2p (lane groups 0, 1) and 2p + 1 (2, 3)
             const int half = grp >> 1, cl = (grp & 1) * 8, cw = c0 + cl;
             const bool cok = cw < cin;
+            unsigned wl[NTC];  // byte offsets within tap 2p's weights (this lane's tap is 2p + half)
+#pragma unroll
+            for (int nt = 0; nt < NTC; nt++)
+                wl[nt] = (unsigned)((half * (int)wtap + (co_base + nt * 16 + row) * cin + cw) * 2);
+            const bf16 *tc[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; mt++) tc[mt] = tb[mt] + TMIN * CKP + cl;
 #pragma unroll 2
             for (int p = 0; p < 14; ++p) {
-                const int tap = 2 * p + half;
-                const bool tok = cok && tap < 27;
-                const int toff = tap < 27 ? ((tap / 9 - 1) * HY + (tap / 3) % 3 - 1) * HX + tap % 3 - 1 : 0;
+                const int t0 = 2 * p, t1 = 2 * p + 1;  // uniform; this lane's tap is t0 + half
+                const int o0 = ((t0 / 9 - 1) * HY + (t0 / 3) % 3 - 1) * HX + t0 % 3 - 1;
+                const int o1 = t1 < 27 ? ((t1 / 9 - 1) * HY + (t1 / 3) % 3 - 1) * HX + t1 % 3 - 1 : 0;
+                const bool tok = cok && (t1 < 27 || !half);
+                const int toff = (half ? o1 : o0) * CKP;
+                const char *wb = (const char *)(wt + t0 * wtap);  // uniform
                 bf16x8 bfr[NTC];
 #pragma unroll
-                for (int nt = 0; nt < NTC; nt++) {
-                    const int co = co_base + nt * 16 + row;
-                    bfr[nt] = tok ? *(const bf16x8 *)(wt + ((size_t)tap * cout + co) * cin + cw) : zero8();
-                }
+                for (int nt = 0; nt < NTC; nt++) bfr[nt] = tok ? *(const bf16x8 *)(wb + wl[nt]) : zero8();
 #pragma unroll
                 for (int mt = 0; mt < MT; mt++) {
-                    const bf16x8 afr = tok ? *(const bf16x8 *)(tile + (hb[mt] + toff) * CKP + cl) : zero8();
+                    const bf16x8 afr = tok ? *(const bf16x8 *)(tc[mt] + toff) : zero8();
 #pragma unroll
                     for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = mfma(afr, bfr[nt], acc[mt][nt]);
                 }
