@@ -92,11 +92,27 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
         for (int nt = 0; nt < NTC; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // Staging: thread t copies the 16-byte piece `sub` of voxels t / SUB,
-    // t / SUB + VPT, ... of the halo tile, its (hx, hy, hz) stepped by VPT
-    // voxels in mixed radix (no divisions in the loop).
+    // t / SUB + VPT, ... of the halo tile, its (row, x) stepped by VPT voxels
+    // in mixed radix (no divisions in the loop).
     constexpr int SUB = CK / 8, VPT = NTH / SUB;
-    constexpr int SDX = VPT % HX, SDY = (VPT / HX) % HY, SDZ = VPT / (HX * HY);
     const int sub = threadIdx.x % SUB, hv0 = threadIdx.x / SUB;
+    // base pointers of the halo's 36 (z, y) source rows at x = 0, per input
+    // (null outside the box), built once per block: an element's address is
+    // then its row base plus x times the voxel stride
+    __shared__ const bf16 *rowb[2][HZ * HY];
+    if (threadIdx.x < 2 * HZ * HY) {
+        const int src = threadIdx.x / (HZ * HY), r = threadIdx.x % (HZ * HY);
+        const int gz = z0 - 1 + r / HY, gy = y0 - 1 + r % HY;
+        const bf16 *bp = nullptr;
+        if ((unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)H) {
+            if (src == 0)
+                bp = upa ? ina + ((((size_t)n * Dc + (gz >> 1)) * Hc + (gy >> 1)) * Wc) * ca
+                         : ina + ((((size_t)n * D + gz) * H + gy) * W) * ca;
+            else if (inb)
+                bp = inb + ((((size_t)n * D + gz) * H + gy) * W) * cb;
+        }
+        rowb[src][r] = bp;
+    }
     // A fragments: LDS element offset of tap (dz, dy, dx) is toff * CKP with
     // toff = ((dz - 1) HY + dy - 1) HX + dx - 1 >= -TMIN; bases shifted by
     // TMIN keep every offset a non-negative constant
@@ -111,33 +127,28 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
         {
             const int c = c0 + sub * 8;  // this thread's 8 channels: all of a or all of b (8 | ca)
             const bool cok = c < cin, isa = c < ca;
-            const bf16 *src = isa ? ina + c : inb + (c - ca);
-            const int cs = isa ? ca : cb;
-            int hv = hv0, hx = hv0 % HX, hy = (hv0 / HX) % HY, hz = hv0 / (HX * HY);
+            const int coff = isa ? c : c - ca, cs = isa ? ca : cb, sh = (isa && upa) ? 1 : 0;
+            const bf16 *const *rb = rowb[isa ? 0 : 1];
+            // voxel hv = row hr (z-major over (z, y)) x HX + hx, stepped by VPT
+            constexpr int SDR = VPT / HX, SDX2 = VPT % HX;
+            int hv = hv0, hx = hv0 % HX, hr = hv0 / HX;
 #pragma unroll
             for (int k = 0; k < (HV + VPT - 1) / VPT; k++) {
                 if (hv < HV) {
-                    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+                    const int gx = x0 - 1 + hx;
+                    const bf16 *bp = rb[hr];
                     bf16x8 v = zero8();
-                    if (cok && (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H && (unsigned)gz < (unsigned)D) {
-                        const size_t vox = (isa && upa) ? (((size_t)n * Dc + (gz >> 1)) * Hc + (gy >> 1)) * Wc + (gx >> 1)
-                                                        : (((size_t)n * D + gz) * H + gy) * W + gx;
-                        v = *(const bf16x8 *)(src + vox * cs);
-                    }
+                    if (cok && bp && (unsigned)gx < (unsigned)W)  // x < 2^24, channels < 2^24
+                        v = *(const bf16x8 *)(bp + (__umul24((unsigned)(gx >> sh), (unsigned)cs) + coff));
                     *(bf16x8 *)(tile + hv * CKP + sub * 8) = v;
                 }
                 hv += VPT;
-                hx += SDX;
+                hx += SDX2;
+                hr += SDR;
                 if (hx >= HX) {
                     hx -= HX;
-                    hy++;
+                    hr++;
                 }
-                hy += SDY;
-                if (hy >= HY) {
-                    hy -= HY;
-                    hz++;
-                }
-                hz += SDZ;
             }
         }
         __syncthreads();
@@ -207,6 +218,8 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
     }
     // lane l holds D[4 (l div 16) + r][l mod 16]: voxel x = 4 grp + r of row y = mt, channel row
     const int z = z0 + wave;
+    // this lane's first output (x0 + 4 grp, y0, z, channel co_base + row)
+    bf16 *ob = out + ((((size_t)n * D + z) * H + y0) * W + x0 + grp * 4) * cout + co_base + row;
 #pragma unroll
     for (int mt = 0; mt < MT; mt++)
 #pragma unroll
@@ -219,7 +232,7 @@ __global__ __launch_bounds__(NTH) void k_conv_tile(const bf16 *__restrict__ ina,
                 if (x < W && y < H && z < D) {
                     float val = acc[mt][nt][r] + bv;
                     if (relu) val = fmaxf(val, 0.f);
-                    out[((((size_t)n * D + z) * H + y) * W + x) * cout + co] = (bf16)val;
+                    ob[(size_t)(mt * W + r) * cout + nt * 16] = (bf16)val;
                 }
             }
         }
