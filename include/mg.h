@@ -85,6 +85,10 @@ typedef struct {
                                  over 8 x 8 x 8 cubes loaded whole (no z march; not with
                                  fuse_passes), the prolongation pass keeping the default */
     int32_t item_depth_coarse;/* levels >= 2: as item_depth_l1 (default 2) */
+    int32_t fuse_restrict;    /* 1 (default) = the last finest-level pre-smoothing pass also forms
+                                 the residual and its R1 restriction (3-cell halo; no separate
+                                 residual pass); 0 = a residual pass after it.  Same results bit
+                                 for bit; not with fuse_passes, which keeps the residual pass. */
     mg_allocator allocator;
 } mg_options;
 

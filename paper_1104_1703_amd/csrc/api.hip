@@ -131,6 +131,12 @@ void build_lists(mg_hierarchy *H, int l, int order, int depth, OrderData &od) {
     const int npl = depth + 4;
     od.pmask = alloc_n<unsigned long long>(H, std::max<size_t>(1, segs.size() * npl));
     launch_item_masks(L, l, order, od, npl, od.pmask, H->stream);
+    od.pmask3 = nullptr;
+    if (l == 0 && H->opt.fuse_restrict && !H->opt.fuse_passes) {  // the last finest pre-smoothing pass
+        const int npl3 = depth + 6;
+        od.pmask3 = alloc_n<unsigned long long>(H, std::max<size_t>(1, segs.size() * npl3));
+        launch_item_masks(L, l, order, od, npl3, od.pmask3, H->stream, 3);
+    }
     od.pmask2 = nullptr;
     if (H->opt.fuse_passes) {
         const int npl2 = depth + 8;
@@ -167,8 +173,8 @@ void build_lists(mg_hierarchy *H, int l, int order, int depth, OrderData &od) {
 
 // Frees the lists build_lists made (the stream must be idle).
 void free_lists(mg_hierarchy *H, OrderData &od) {
-    for (void *p : {(void *)od.tiles, (void *)od.segs, (void *)od.pmask, (void *)od.pmask2, (void *)od.segs8,
-                    (void *)od.pmask8})
+    for (void *p : {(void *)od.tiles, (void *)od.segs, (void *)od.pmask, (void *)od.pmask2, (void *)od.pmask3,
+                    (void *)od.segs8, (void *)od.pmask8})
         dev_free(H, p);
     od.tiles = nullptr;
     od.segs = nullptr;
@@ -179,7 +185,8 @@ void free_lists(mg_hierarchy *H, OrderData &od) {
 mg_status validate_options(const mg_options &o) {
     if (o.n_pre < 0 || o.n_post < 0 || o.n_cycles < 1 || o.n_coarse_sweeps < 0 || o.min_coarse_dim < 1 ||
         o.max_cycles < 0 || (o.precision != MG_FP64 && o.precision != MG_MIXED) || o.bc_order < 0 ||
-        o.bc_order > 2 || !(o.eta > 0) || o.first_order_hold < 0 || o.fuse_passes < 0 || o.fuse_passes > 1) {
+        o.bc_order > 2 || !(o.eta > 0) || o.first_order_hold < 0 || o.fuse_passes < 0 || o.fuse_passes > 1 ||
+        o.fuse_restrict < 0 || o.fuse_restrict > 1) {
         set_error("invalid mg_options");
         return MG_ERR_ARG;
     }
@@ -219,8 +226,9 @@ int start_depth(const mg_options &o, int l) {
 std::string tune_key(const mg_hierarchy *H, int l, int order, bool f32) {
     const Level &L = H->lev[l];
     char b[160];
-    snprintf(b, sizeof b, "gfx950:%dx%dx%d:l%d:o%d:%s:a%lld", H->lev[0].nx, H->lev[0].ny, H->lev[0].nz, l, order,
-             f32 ? "fp32" : "fp64", (long long)L.od[l == 0 ? 2 : order].nact);
+    snprintf(b, sizeof b, "gfx950:%dx%dx%d:l%d:o%d:%s:a%lld%s", H->lev[0].nx, H->lev[0].ny, H->lev[0].nz, l, order,
+             f32 ? "fp32" : "fp64", (long long)L.od[l == 0 ? 2 : order].nact,
+             l == 0 && H->opt.fuse_restrict && !H->opt.fuse_passes ? ":res" : "");
     return b;
 }
 
@@ -249,9 +257,10 @@ void tune_cache_put(const std::string &key, int depth) {
 // Average time of the work a cycle runs over the work items of od on
 // level l, with HIP events on the hierarchy's stream (best of three runs):
 // on coarse levels one smoother pass; on the finest level, which runs
-// several kernels over the same items, two passes, the residual with its
-// restriction and the pass forming its input's norm (FP64) or the update
-// with the outer residual (mixed).  At creation every iterate and
+// several kernels over the same items, a plain pass, the pass with the
+// residual and its restriction (or a plain pass and the residual march with
+// the restriction) and the pass forming its input's norm (FP64) or the
+// update with the outer residual (mixed).  At creation every iterate and
 // right-hand side buffer holds zeros, which this work keeps; it costs the
 // same on any values.
 float time_pass(mg_hierarchy *H, int l, int order, const OrderData &od, bool f32) {
@@ -276,15 +285,19 @@ float time_pass(mg_hierarchy *H, int l, int order, const OrderData &od, bool f32
             }
             return;
         }
-        if (f32) launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream);
+        if (l == 0 && coarse && od.pmask3 && (p & 1)) {  // the pass that also restricts
+            Level &C = H->lev[1];
+            if (f32) launch_rbgs_res_fine32(L, C, 2, od, L.x32[1], L.x32[0], L.f32, C.f32, H->stream);
+            else launch_rbgs_res_fine(L, C, 2, od, L.x[1], L.x[0], L.f, C.f, H->stream);
+        } else if (f32) launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream);
         else launch_rbgs(L, l, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, H->stream);
         if (l != 0 || (p & 1) == 0) return;
         if (f32) {
-            if (coarse) launch_restrict32(L, H->lev[1], 0, 2, L.x32[0], L.f32, H->lev[1].f32, H->stream);
+            if (coarse && !od.pmask3) launch_restrict32(L, H->lev[1], 0, 2, L.x32[0], L.f32, H->lev[1].f32, H->stream);
             launch_axpy_resnorm32(L, od, L.x[0], L.x32[0], L.x[1], L.f, L.f32, H->part, H->norm_dev, 0, H->stream,
                                   nullptr);
         } else {
-            if (coarse) launch_restrict(L, H->lev[1], 0, 2, L.x[0], L.f, H->lev[1].f, H->stream);
+            if (coarse && !od.pmask3) launch_restrict(L, H->lev[1], 0, 2, L.x[0], L.f, H->lev[1].f, H->stream);
             launch_rbgs_norm(L, od, L.x[0], L.x[1], L.f, H->part, H->stream);
         }
     };
@@ -577,7 +590,16 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
     }
     Level &C = H->lev[l + 1];
     const OrderData &odl = odata(H, l, order);
-    if (l > 0 && odl.cube && o.n_pre >= 1) {
+    if (l == 0 && odl.pmask3 && !o.fuse_passes && o.n_pre >= 1 && (o.n_pre >= 2 || !in)) {
+        // the last pre-smoothing pass also forms the residual and restricts it
+        // (the first pass may have to form the norm of its input instead)
+        if (o.n_pre > 1) smooth(H, l, order, o.n_pre - 1, zero_start, cur, f32, in);
+        const bool zin = zero_start && o.n_pre == 1;
+        const int a = cur.c[l], b = a ^ 1;
+        if (f32) launch_rbgs_res_fine32(L, C, order, odl, zin ? nullptr : L.x32[a], L.x32[b], L.f32, C.f32, H->stream);
+        else launch_rbgs_res_fine(L, C, order, odl, zin ? nullptr : L.x[a], L.x[b], L.f, C.f, H->stream);
+        cur.c[l] = b;
+    } else if (l > 0 && odl.cube && o.n_pre >= 1) {
         // cube levels: the last pre-smoothing pass also restricts the residual
         if (o.n_pre > 1) smooth(H, l, order, o.n_pre - 1, zero_start, cur, f32, in);
         const bool zin = zero_start && o.n_pre == 1;
@@ -1048,6 +1070,7 @@ void mg_default_options(mg_options *o) {
     o->eta = 0.5;
     o->first_order_hold = 10;
     o->use_graph = 0;
+    o->fuse_restrict = 1;
 }
 
 const char *mg_status_string(mg_status s) {

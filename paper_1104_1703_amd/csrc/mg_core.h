@@ -60,6 +60,7 @@ struct OrderData {
     Seg *segs = nullptr;   // smoother work items (device)
     unsigned long long *pmask = nullptr;  // per item and plane activity masks (device)
     unsigned long long *pmask2 = nullptr; // the same for fused pairs of passes (4-cell halo; fuse_passes)
+    unsigned long long *pmask3 = nullptr; // finest level: masks with a 3-cell halo for the pass with the residual
     // level 1, FP64 pass with the prolongation on load: whole 8-plane tiles as
     // work items and their masks (that pass fits 4 blocks per CU, not 5, and
     // one round of tiles beats two rounds of 4-plane items)
@@ -177,7 +178,8 @@ void launch_diag(const Level &L, int level, int order, double *d, unsigned long 
 void launch_tile_flags(const Level &L, int level, int order, uint8_t *flags, hipStream_t s);
 void launch_to_float(const double *a, float *b, size_t n, hipStream_t s);
 // Activity masks of the smoother work items of `od` (npl planes per item)
-// for an xy halo of 2 (single passes) or 4 (fused pairs of passes) cells.
+// for an xy halo of 2 (single passes), 3 (the finest pass that also forms the
+// residual) or 4 (fused pairs of passes) cells.
 void launch_item_masks(const Level &L, int level, int order, const OrderData &od, int npl, unsigned long long *pm,
                        hipStream_t s, int halo = 2);
 
@@ -195,6 +197,13 @@ hipError_t launch_rbgs32(const Level &L, int level, const OrderData &od, const f
 void launch_rbgs_restrict(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
                           double *xout, const double *f, double *fc, hipStream_t s);
 void launch_rbgs_restrict32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
+                            float *xout, const float *f, float *fc, hipStream_t s);
+// A finest-level pass (od.pmask3 must exist; xin may be null) that also forms
+// the residual of its result and its R1 restriction fc onto level 1 in order
+// `order`: bit for bit launch_rbgs followed by launch_restrict.
+void launch_rbgs_res_fine(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
+                          double *xout, const double *f, double *fc, hipStream_t s);
+void launch_rbgs_res_fine32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
                             float *xout, const float *f, float *fc, hipStream_t s);
 // A finest-level FP64 pass (xin != nullptr) that also writes the residual
 // norm partials of its input xin, one per work item, to part[0 .. od.nsegs):

@@ -145,7 +145,8 @@ __global__ void k_tile_flags(const int32_t *__restrict__ cnt, int nx, int ny, in
 // One block per smoother work item: its activity masks (one word per plane
 // z0-2 .. z0+npl-3; bit layout of item_mask_bit).
 // Activity masks of smoother work items with an xy halo of HH cells (2: one
-// pass per launch, smooth_core.h; 4: two fused passes, smooth2_core.h): per
+// pass per launch, smooth_core.h; 3: the finest pass that also forms the
+// residual, smooth_res_core.h; 4: two fused passes, smooth2_core.h): per
 // item and plane z0-HH .. z0-HH+npl-1, bit 4 v + g for row y0-HH+v and the
 // 16-cell granule g of the row (granule boundaries at x0-16, x0, x0+16,
 // x0+32); planes outside the box or past z1+HH-1 get no bits.
@@ -223,6 +224,8 @@ void launch_item_masks(const Level &L, int level, int order, const OrderData &od
     if (od.nsegs == 0) return;
     if (halo == 4)
         k_item_masks<4><<<od.nsegs, 256, 0, s>>>(L.cnt, L.nx, L.ny, L.nz, level, order, od.segs, npl, pm);
+    else if (halo == 3)
+        k_item_masks<3><<<od.nsegs, 256, 0, s>>>(L.cnt, L.nx, L.ny, L.nz, level, order, od.segs, npl, pm);
     else
         k_item_masks<2><<<od.nsegs, 256, 0, s>>>(L.cnt, L.nx, L.ny, L.nz, level, order, od.segs, npl, pm);
 }

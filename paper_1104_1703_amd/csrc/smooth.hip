@@ -27,6 +27,7 @@
 #include "cube_core.h"
 #include "mg_core.h"
 #include "smooth2_core.h"
+#include "smooth_res_core.h"
 #include "transfer_core.h"
 
 namespace mg {
@@ -67,6 +68,20 @@ __global__ __launch_bounds__(NT, 5) void k_rbgs_norm(const double *__restrict__ 
                                                                0, 0, ih2);
     const double t = tr::block_sum(sq);
     if (threadIdx.x == 0) part[item] = t;
+}
+
+// The finest pass that also forms the residual of its result and restricts
+// it onto level 1 (smooth_res_core.h): four FP64 blocks per CU (LDS).
+template <typename T, int SEGZ>
+__global__ __launch_bounds__(NT, sizeof(T) == 8 ? 4 : 5) void k_rbgs_res(
+    const T *__restrict__ xin, T *__restrict__ xout, const T *__restrict__ f, const uint8_t *__restrict__ code, int nx,
+    int ny, int nz, T h2, T ih2, const Seg *__restrict__ segs, const unsigned long long *__restrict__ pm, int nsegs,
+    const int *__restrict__ halt, const T *__restrict__ cd, int cnx, int cny, T *__restrict__ fc) {
+    __shared__ rbr::Lds<T> lds;
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item >= nsegs || (halt && *halt)) return;
+    rbr::rbgs_res_item<T, SEGZ>(lds, xin, xout, f, code, nx, ny, nz, h2, ih2, segs[item],
+                                          pm + (size_t)item * (SEGZ + 2 * rbr::H), cd, cnx, cny, fc);
 }
 
 // Two passes per launch (smooth2_core.h): LDS allows two FP64 blocks per CU.
@@ -142,6 +157,28 @@ void launch_rbgs_restrict32(const Level &L, const Level &C, int order, const Ord
                             float *xout, const float *f, float *fc, hipStream_t s) {
     launch_cube_restrict<float>(xin, xout, f, od.d32, L, od, (float)(L.h * L.h), (float)(1.0 / (L.h * L.h)), C,
                                 C.od[order].d32, fc, s);
+}
+
+template <typename T>
+void launch_fine_res(const Level &L, const OrderData &od, const T *xin, T *xout, const T *f, const Level &C,
+                     const T *cd, T *fc, hipStream_t s) {
+    if (od.nsegs == 0) return;
+    const T h2 = (T)(L.h * L.h), ih2 = (T)(1.0 / (L.h * L.h));
+    with_fine_depth(od.depth, [&](auto Z) {
+        k_rbgs_res<T, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, L.nx, L.ny, L.nz, h2,
+                                                                         ih2, od.segs, od.pmask3, od.nsegs, L.halt,
+                                                                         cd, C.nx, C.ny, fc);
+    });
+}
+
+void launch_rbgs_res_fine(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
+                          double *xout, const double *f, double *fc, hipStream_t s) {
+    launch_fine_res<double>(L, od, xin, xout, f, C, C.od[order].d, fc, s);
+}
+
+void launch_rbgs_res_fine32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
+                            float *xout, const float *f, float *fc, hipStream_t s) {
+    launch_fine_res<float>(L, od, xin, xout, f, C, C.od[order].d32, fc, s);
 }
 
 template <typename T>

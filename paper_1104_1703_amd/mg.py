@@ -34,7 +34,7 @@ class Options(C.Structure):
                 ("bc_order", C.c_int32), ("eta", C.c_double), ("first_order_hold", C.c_int32),
                 ("use_graph", C.c_int32), ("fuse_passes", C.c_int32), ("tune", C.c_int32),
                 ("item_depth_fine", C.c_int32), ("item_depth_l1", C.c_int32), ("item_depth_coarse", C.c_int32),
-                ("allocator", Allocator)]
+                ("fuse_restrict", C.c_int32), ("allocator", Allocator)]
 
 
 class SolveInfo(C.Structure):
