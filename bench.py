@@ -41,6 +41,32 @@ SMOOTH_BYTES_FP64 = 25.0    # per active cell per pass: x read + x write + f rea
 SMOOTH_BYTES_FP32 = 13.0
 
 
+# algorithmic bytes per active finest cell of each kind of finest-level FP64
+# pass in a cycle: the plain pass; the pass that also forms the residual and
+# writes the restricted right-hand side (1/8 x 8 B); the pass that reads the
+# coarse iterate for the prolongation (1/8 x 8 B); the pass that also forms
+# the input's residual norm (no extra bytes)
+FINEST_BYTES = {"plain": 25.0, "residual": 26.0, "prolong": 26.0, "norm": 25.0}
+FINEST_KERNELS = {"plain": "k_rbgs<double, true, D, false>", "residual": "k_rbgs_res<double, D>",
+                  "prolong": "k_rbgs<double, true, D, true>", "norm": "k_rbgs_norm<D>"}
+
+
+def finest_kernels(timed, n_act):
+    """Event-timed average launch and algorithmic rate of each kind of
+    finest-level pass of a cycle ((summed ms, launches) per kind)."""
+    out = {}
+    for kind, (ms, n) in timed.items():
+        if n == 0:
+            out[kind] = {"kernel": FINEST_KERNELS[kind], "launches_timed": 0}
+            continue
+        us = ms / n * 1e3
+        b = FINEST_BYTES[kind] * n_act
+        out[kind] = {"kernel": FINEST_KERNELS[kind], "avg_launch_us": round(us, 3), "launches_timed": n,
+                     "algorithmic_bytes_per_launch": b, "achieved": round(b / (us * 1e-6) / 1e9, 1),
+                     "frac": round(b / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)}
+    return out
+
+
 def measured_traffic():
     """HBM bytes per launch of the finest smoother from the committed counter
     runs (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or
@@ -582,6 +608,16 @@ def main():
     depths64 = H.item_depths()
     ms_wall, infos64, walls64 = time_solves(H, kernel_timing=True)
     k_ms, k_launches = H.kernel_timing_read()
+    # the other finest-level passes of a cycle, timed the same way in two
+    # more solves each after the timed region (one kind per solve set)
+    finest = {"plain": (k_ms, k_launches)}
+    for kind in ("residual", "prolong", "norm"):
+        H.kernel_timing(True, kind)
+        for _ in range(2):
+            phi.zero_()
+            H.solve(rho, phi, None, tol=args.tol)
+        finest[kind] = H.kernel_timing_read()
+        H.kernel_timing(False)
     last = infos64[-1]
     reg64 = regimes(infos64, walls64)
     ms_events = float(np.median([i["ms"] for i in infos64]))
@@ -739,6 +775,7 @@ def main():
             "algorithmic_bytes_per_launch": bytes_per,
             "back_to_back_us": round(b2b_ms * 1e3, 3),
             "back_to_back_frac": round(bytes_per / (b2b_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "finest_kernels": finest_kernels(finest, n_act),
         },
         "vcycle": vcycle_rate(n_act, ms_wall, cycles_mean),
     }

@@ -237,15 +237,19 @@ mg_status mg_vcycle(mg_hierarchy *H, int32_t order, double *x_dev, const double 
 mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches);
 
 /*
- * Duration of the finest level's plain red-black passes inside later solves
- * (the passes that neither form the input norm nor apply the prolongation;
- * FP64, or FP32 in a mixed solve): enable = 1 clears the record and launches
- * each such pass with a pair of HIP events that take the kernel's own start
- * and end times (hipExtLaunchKernel), up to 1024 launches; a launch of a
- * cycle that the device stop test halted is dropped from the record; enable
- * = 0 stops recording.  Both synchronise the stream first.  MG_ERR_ARG for
- * another enable value or with use_graph set (a captured cycle records no
- * events).
+ * Duration of one kind of finest-level red-black launch inside later solves
+ * (FP64, or FP32 in a mixed solve).  enable selects the kind, clears the
+ * record and launches each such pass with a pair of HIP events that take the
+ * kernel's own start and end times (hipExtLaunchKernel), up to 1024
+ * launches: 1 = the plain passes (those that neither form the input norm,
+ * nor the residual, nor apply the prolongation), 2 = the last pre-smoothing
+ * pass that also forms the residual and its restriction (fuse_restrict), 3 =
+ * the first post-smoothing pass that applies the prolongation, 4 = the first
+ * pre-smoothing pass that also forms the residual norm of its input (FP64).
+ * A launch of a cycle that the device stop test halted is dropped from the
+ * record; enable = 0 stops recording.  Both synchronise the stream first.
+ * MG_ERR_ARG for another enable value or with use_graph set (a captured
+ * cycle records no events).
  */
 mg_status mg_kernel_timing(mg_hierarchy *H, int32_t enable);
 

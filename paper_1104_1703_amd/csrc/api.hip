@@ -520,6 +520,19 @@ struct InputNorm {
     hipEvent_t ev;
 };
 
+// Kinds of finest-level launch that mg_kernel_timing can record.
+enum { KT_PLAIN = 1, KT_RESIDUAL = 2, KT_PROLONG = 3, KT_NORM = 4 };
+
+// Events for the next launch of timing kind `kind`, if the hierarchy records
+// that kind and has a pair left (else both null and false).
+bool kt_events(mg_hierarchy *H, int kind, hipEvent_t &e0, hipEvent_t &e1) {
+    e0 = e1 = nullptr;
+    if (H->kt_on != kind || H->kt_used * 2 >= (int)H->kt_ev.size()) return false;
+    e0 = H->kt_ev[2 * H->kt_used];
+    e1 = H->kt_ev[2 * H->kt_used + 1];
+    return true;
+}
+
 // `passes` red-black passes on level l; zero_start: the iterate starts at 0.
 // in (finest level, FP64, single passes): the first pass also forms the
 // residual norm of its input.
@@ -539,7 +552,10 @@ void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur 
         const int a = cur.c[l], b = a ^ 1;
         const bool zin = (p == 0 && zero_start);
         if (in && p == 0 && l == 0 && !f32 && !zin) {
-            launch_rbgs_norm(L, od, L.x[a], L.x[b], L.f, H->part, H->stream);
+            hipEvent_t e0, e1;
+            const bool timed = od.nsegs > 0 && kt_events(H, KT_NORM, e0, e1);
+            HIPCHK(launch_rbgs_norm(L, od, L.x[a], L.x[b], L.f, H->part, H->stream, e0, e1));
+            if (timed) H->kt_used++;
             launch_finalize(L, H->part, od.nsegs, H->norm_dev, 0, in->stop, H->stream);
             if (in->host) {
                 HIPCHK(hipMemcpyAsync(in->host, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
@@ -552,9 +568,8 @@ void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur 
             p += 2;
         } else {
             // optional timing: the kernel's own start and end on a pair of events
-            const bool timed = l == 0 && H->kt_on && od.nsegs > 0 && H->kt_used * 2 < (int)H->kt_ev.size();
-            hipEvent_t e0 = timed ? H->kt_ev[2 * H->kt_used] : nullptr;
-            hipEvent_t e1 = timed ? H->kt_ev[2 * H->kt_used + 1] : nullptr;
+            hipEvent_t e0, e1;
+            const bool timed = l == 0 && od.nsegs > 0 && kt_events(H, KT_PLAIN, e0, e1);
             if (f32) HIPCHK(launch_rbgs32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream, e0, e1));
             else HIPCHK(launch_rbgs(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream, e0, e1));
             if (timed) H->kt_used++;
@@ -596,8 +611,15 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
         if (o.n_pre > 1) smooth(H, l, order, o.n_pre - 1, zero_start, cur, f32, in);
         const bool zin = zero_start && o.n_pre == 1;
         const int a = cur.c[l], b = a ^ 1;
-        if (f32) launch_rbgs_res_fine32(L, C, order, odl, zin ? nullptr : L.x32[a], L.x32[b], L.f32, C.f32, H->stream);
-        else launch_rbgs_res_fine(L, C, order, odl, zin ? nullptr : L.x[a], L.x[b], L.f, C.f, H->stream);
+        hipEvent_t e0, e1;
+        const bool timed = odl.nsegs > 0 && kt_events(H, KT_RESIDUAL, e0, e1);
+        if (f32)
+            HIPCHK(launch_rbgs_res_fine32(L, C, order, odl, zin ? nullptr : L.x32[a], L.x32[b], L.f32, C.f32,
+                                          H->stream, e0, e1));
+        else
+            HIPCHK(launch_rbgs_res_fine(L, C, order, odl, zin ? nullptr : L.x[a], L.x[b], L.f, C.f, H->stream, e0,
+                                        e1));
+        if (timed) H->kt_used++;
         cur.c[l] = b;
     } else if (l > 0 && odl.cube && o.n_pre >= 1) {
         // cube levels: the last pre-smoothing pass also restricts the residual
@@ -627,8 +649,14 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
         if (f32) launch_rbgs2_prolong32(L, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream);
         else launch_rbgs2_prolong(L, od, C, C.x[cur.c[l + 1]], L.x[a], L.x[b], L.f, H->stream);
     } else {
-        if (f32) launch_rbgs_prolong32(L, l, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream);
-        else launch_rbgs_prolong(L, l, od, C, C.x[cur.c[l + 1]], L.x[a], L.x[b], L.f, H->stream);
+        hipEvent_t e0, e1;
+        const bool timed = l == 0 && od.nsegs > 0 && kt_events(H, KT_PROLONG, e0, e1);
+        if (f32)
+            HIPCHK(launch_rbgs_prolong32(L, l, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream, e0,
+                                         e1));
+        else
+            HIPCHK(launch_rbgs_prolong(L, l, od, C, C.x[cur.c[l + 1]], L.x[a], L.x[b], L.f, H->stream, e0, e1));
+        if (timed) H->kt_used++;
     }
     cur.c[l] = b;
     smooth(H, l, order, o.n_post - (fused ? 2 : 1), false, cur, f32);
@@ -1465,7 +1493,7 @@ mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches) {
 }
 
 mg_status mg_kernel_timing(mg_hierarchy *H, int32_t enable) {
-    if (!H || (enable != 0 && enable != 1)) {
+    if (!H || enable < 0 || enable > 4) {
         set_error("invalid argument");
         return MG_ERR_ARG;
     }
@@ -1480,7 +1508,7 @@ mg_status mg_kernel_timing(mg_hierarchy *H, int32_t enable) {
             H->kt_ev.assign(2 * KT_MAX_LAUNCHES, nullptr);
             for (hipEvent_t &e : H->kt_ev) HIPCHK(hipEventCreate(&e));
         }
-        H->kt_on = enable != 0;
+        H->kt_on = enable;
         if (enable) H->kt_used = 0;
         return MG_OK;
     });

@@ -123,10 +123,12 @@ struct mg_hierarchy {
     std::vector<mg::Graph> graphs;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evq[2] = {nullptr, nullptr};  // ends of the (at most two) cycles in flight
-    // optional timing of the finest level's plain red-black launches inside
-    // solves: an event pair per launch (the kernel's own start and end), up
-    // to kt_ev.size() / 2 launches
-    bool kt_on = false;
+    // optional timing of one kind of finest-level red-black launch inside
+    // solves (kt_on: 0 off, 1 plain passes, 2 the pass with the residual, 3
+    // the pass with the prolongation, 4 the pass forming the input norm): an
+    // event pair per launch (the kernel's own start and end), up to
+    // kt_ev.size() / 2 launches
+    int kt_on = 0;
     std::vector<hipEvent_t> kt_ev;
     int kt_used = 0;
 };
@@ -201,22 +203,26 @@ void launch_rbgs_restrict32(const Level &L, const Level &C, int order, const Ord
 // A finest-level pass (od.pmask3 must exist; xin may be null) that also forms
 // the residual of its result and its R1 restriction fc onto level 1 in order
 // `order`: bit for bit launch_rbgs followed by launch_restrict.
-void launch_rbgs_res_fine(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
-                          double *xout, const double *f, double *fc, hipStream_t s);
-void launch_rbgs_res_fine32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
-                            float *xout, const float *f, float *fc, hipStream_t s);
+hipError_t launch_rbgs_res_fine(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
+                                double *xout, const double *f, double *fc, hipStream_t s, hipEvent_t e0 = nullptr,
+                                hipEvent_t e1 = nullptr);
+hipError_t launch_rbgs_res_fine32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
+                                  float *xout, const float *f, float *fc, hipStream_t s, hipEvent_t e0 = nullptr,
+                                  hipEvent_t e1 = nullptr);
 // A finest-level FP64 pass (xin != nullptr) that also writes the residual
 // norm partials of its input xin, one per work item, to part[0 .. od.nsegs):
 // the same values, bit for bit, as launch_resnorm's partials of xin.
-void launch_rbgs_norm(const Level &L, const OrderData &od, const double *xin, double *xout, const double *f,
-                      double *part, hipStream_t s);
+hipError_t launch_rbgs_norm(const Level &L, const OrderData &od, const double *xin, double *xout, const double *f,
+                            double *part, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // A pass that first adds the P2 prolongation of the coarse iterate xc (level
 // level + 1, dims of C) to xin on active cells, as launch_prolong would, then
 // relaxes; xin is left unchanged.
-void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const Level &C, const double *xc,
-                         const double *xin, double *xout, const double *f, hipStream_t s);
-void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const Level &C, const float *xc,
-                           const float *xin, float *xout, const float *f, hipStream_t s);
+hipError_t launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const Level &C, const double *xc,
+                               const double *xin, double *xout, const double *f, hipStream_t s,
+                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const Level &C, const float *xc,
+                                 const float *xin, float *xout, const float *f, hipStream_t s,
+                                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Two passes in one launch (fused; od.pmask2 must exist): the same result as
 // two launch_rbgs calls xin -> tmp -> xout, bit for bit.
 void launch_rbgs2(const Level &L, int level, const OrderData &od, const double *xin, double *xout, const double *f,

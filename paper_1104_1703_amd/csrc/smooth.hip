@@ -137,6 +137,23 @@ __global__ __launch_bounds__(cube::NT) void k_rbgs_cube_restrict(
 
 inline unsigned grid8(int items) { return (unsigned)(((items + 7) / 8) * 8); }
 
+template <typename T>
+struct same_t {
+    using type = T;
+};
+// Launches kernel k over `grid` blocks of NT threads; with events, through
+// hipExtLaunchKernel so that e0 and e1 take the kernel's own start and end.
+template <typename... P>
+hipError_t launch_k(void (*k)(P...), unsigned grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                    typename same_t<P>::type... a) {
+    if (!e0 && !e1) {
+        k<<<grid, NT, 0, s>>>(a...);
+        return hipSuccess;
+    }
+    void *args[] = {(void *)&a...};
+    return hipExtLaunchKernel((const void *)k, dim3(grid), dim3(NT), args, 0, s, e0, e1, 0);
+}
+
 }  // namespace
 
 template <typename T>
@@ -160,25 +177,28 @@ void launch_rbgs_restrict32(const Level &L, const Level &C, int order, const Ord
 }
 
 template <typename T>
-void launch_fine_res(const Level &L, const OrderData &od, const T *xin, T *xout, const T *f, const Level &C,
-                     const T *cd, T *fc, hipStream_t s) {
-    if (od.nsegs == 0) return;
+hipError_t launch_fine_res(const Level &L, const OrderData &od, const T *xin, T *xout, const T *f, const Level &C,
+                           const T *cd, T *fc, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (od.nsegs == 0) return hipSuccess;
     const T h2 = (T)(L.h * L.h), ih2 = (T)(1.0 / (L.h * L.h));
+    hipError_t err = hipSuccess;
     with_fine_depth(od.depth, [&](auto Z) {
-        k_rbgs_res<T, decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, L.nx, L.ny, L.nz, h2,
-                                                                         ih2, od.segs, od.pmask3, od.nsegs, L.halt,
-                                                                         cd, C.nx, C.ny, fc);
+        err = launch_k(k_rbgs_res<T, decltype(Z)::value>, grid8(od.nsegs), s, e0, e1, xin, xout, f, L.code, L.nx,
+                       L.ny, L.nz, h2, ih2, od.segs, od.pmask3, od.nsegs, L.halt, cd, C.nx, C.ny, fc);
     });
+    return err;
 }
 
-void launch_rbgs_res_fine(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
-                          double *xout, const double *f, double *fc, hipStream_t s) {
-    launch_fine_res<double>(L, od, xin, xout, f, C, C.od[order].d, fc, s);
+hipError_t launch_rbgs_res_fine(const Level &L, const Level &C, int order, const OrderData &od, const double *xin,
+                                double *xout, const double *f, double *fc, hipStream_t s, hipEvent_t e0,
+                                hipEvent_t e1) {
+    return launch_fine_res<double>(L, od, xin, xout, f, C, C.od[order].d, fc, s, e0, e1);
 }
 
-void launch_rbgs_res_fine32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
-                            float *xout, const float *f, float *fc, hipStream_t s) {
-    launch_fine_res<float>(L, od, xin, xout, f, C, C.od[order].d32, fc, s);
+hipError_t launch_rbgs_res_fine32(const Level &L, const Level &C, int order, const OrderData &od, const float *xin,
+                                  float *xout, const float *f, float *fc, hipStream_t s, hipEvent_t e0,
+                                  hipEvent_t e1) {
+    return launch_fine_res<float>(L, od, xin, xout, f, C, C.od[order].d32, fc, s, e0, e1);
 }
 
 template <typename T>
@@ -216,21 +236,9 @@ hipError_t launch_fine(const Level &L, const OrderData &od, const T *xin, T *xou
                        hipEvent_t e0, hipEvent_t e1) {
     hipError_t err = hipSuccess;
     with_fine_depth(od.depth, [&](auto Z) {
-        auto kern = k_rbgs<T, true, decltype(Z)::value>;
-        const dim3 grid(grid8(od.nsegs)), block(NT);
-        if (!e0 && !e1) {
-            k_rbgs<T, true, decltype(Z)::value><<<grid, block, 0, s>>>(xin, xout, f, L.code, nullptr, L.nx, L.ny,
-                                                                       L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt);
-            return;
-        }
-        const uint8_t *code = L.code;
-        const T *dco = nullptr, *xc = nullptr;
-        int nx = L.nx, ny = L.ny, nz = L.nz, nsegs = od.nsegs, c0 = 0;
-        const Seg *segs = od.segs;
-        const unsigned long long *pm = od.pmask;
-        const int *halt = L.halt;
-        void *args[] = {&xin, &xout, &f, &code, &dco, &nx, &ny, &nz, &h2, &segs, &pm, &nsegs, &halt, &xc, &c0, &c0, &c0};
-        err = hipExtLaunchKernel((const void *)kern, grid, block, args, 0, s, e0, e1, 0);
+        err = launch_k(k_rbgs<T, true, decltype(Z)::value>, grid8(od.nsegs), s, e0, e1, xin, xout, f, L.code,
+                       (const T *)nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt,
+                       (const T *)nullptr, 0, 0, 0);
     });
     return err;
 }
@@ -248,25 +256,28 @@ hipError_t launch_rbgs(const Level &L, int level, const OrderData &od, const dou
     return hipSuccess;
 }
 
-void launch_rbgs_norm(const Level &L, const OrderData &od, const double *xin, double *xout, const double *f,
-                      double *part, hipStream_t s) {
-    if (od.nsegs == 0) return;
+hipError_t launch_rbgs_norm(const Level &L, const OrderData &od, const double *xin, double *xout, const double *f,
+                            double *part, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (od.nsegs == 0) return hipSuccess;
+    hipError_t err = hipSuccess;
     with_fine_depth(od.depth, [&](auto Z) {
-        k_rbgs_norm<decltype(Z)::value><<<grid8(od.nsegs), NT, 0, s>>>(xin, xout, f, L.code, L.nx, L.ny, L.nz, L.h * L.h,
-                                                                       1.0 / (L.h * L.h), od.segs, od.pmask, od.nsegs,
-                                                                       L.halt, part);
+        err = launch_k(k_rbgs_norm<decltype(Z)::value>, grid8(od.nsegs), s, e0, e1, xin, xout, f, L.code, L.nx, L.ny,
+                       L.nz, L.h * L.h, 1.0 / (L.h * L.h), od.segs, od.pmask, od.nsegs, L.halt, part);
     });
+    return err;
 }
 
-void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const Level &C, const double *xc,
-                         const double *xin, double *xout, const double *f, hipStream_t s) {
-    if (od.nsegs == 0) return;
+hipError_t launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const Level &C, const double *xc,
+                               const double *xin, double *xout, const double *f, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
+    if (od.nsegs == 0) return hipSuccess;
     const double h2 = L.h * L.h;
+    hipError_t err = hipSuccess;
     if (level == 0)
         with_fine_depth(od.depth, [&](auto Z) {
-            k_rbgs<double, true, decltype(Z)::value, true><<<grid8(od.nsegs), NT, 0, s>>>(
-                xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx,
-                C.ny, C.nz);
+            err = launch_k(k_rbgs<double, true, decltype(Z)::value, true>, grid8(od.nsegs), s, e0, e1, xin, xout, f,
+                           L.code, (const double *)nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt,
+                           xc, C.nx, C.ny, C.nz);
         });
     else if (level == 1 && od.nsegs8 > 0)  // whole tiles: one round at 4 blocks per CU
         k_rbgs<double, false, TZ, true><<<grid8(od.nsegs8), NT, 0, s>>>(xin, xout, f, nullptr, od.d, L.nx, L.ny, L.nz,
@@ -274,20 +285,24 @@ void launch_rbgs_prolong(const Level &L, int level, const OrderData &od, const L
                                                                       C.nx, C.ny, C.nz);
     else
         launch_coarse<double, true>(od.depth, xin, xout, f, od.d, L, od, h2, s, xc, &C);
+    return err;
 }
 
-void launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const Level &C, const float *xc,
-                           const float *xin, float *xout, const float *f, hipStream_t s) {
-    if (od.nsegs == 0) return;
+hipError_t launch_rbgs_prolong32(const Level &L, int level, const OrderData &od, const Level &C, const float *xc,
+                                 const float *xin, float *xout, const float *f, hipStream_t s, hipEvent_t e0,
+                                 hipEvent_t e1) {
+    if (od.nsegs == 0) return hipSuccess;
     const float h2 = (float)(L.h * L.h);
+    hipError_t err = hipSuccess;
     if (level == 0)
         with_fine_depth(od.depth, [&](auto Z) {
-            k_rbgs<float, true, decltype(Z)::value, true><<<grid8(od.nsegs), NT, 0, s>>>(
-                xin, xout, f, L.code, nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt, xc, C.nx,
-                C.ny, C.nz);
+            err = launch_k(k_rbgs<float, true, decltype(Z)::value, true>, grid8(od.nsegs), s, e0, e1, xin, xout, f,
+                           L.code, (const float *)nullptr, L.nx, L.ny, L.nz, h2, od.segs, od.pmask, od.nsegs, L.halt,
+                           xc, C.nx, C.ny, C.nz);
         });
     else
         launch_coarse<float, true>(od.depth, xin, xout, f, od.d32, L, od, h2, s, xc, &C);
+    return err;
 }
 
 template <typename T>

@@ -359,10 +359,15 @@ class Hierarchy:
     def time_smoother(self, launches: int, order: int = 2):
         _check(self._call(load_library().mg_time_smoother, self._h, order, launches), "mg_time_smoother")
 
-    def kernel_timing(self, enable: bool):
-        """Start (clearing the record) or stop HIP-event timing of the finest
-        level's plain red-black launches inside later solves."""
-        _check(self._call(load_library().mg_kernel_timing, self._h, int(bool(enable))), "mg_kernel_timing")
+    TIMING_KINDS = {"plain": 1, "residual": 2, "prolong": 3, "norm": 4}
+
+    def kernel_timing(self, enable, kind: str = "plain"):
+        """Start (clearing the record) or stop HIP-event timing of one kind of
+        finest-level red-black launch inside later solves: "plain", "residual"
+        (the pass that also restricts the residual), "prolong" (the pass that
+        applies the prolongation) or "norm" (the pass forming the input norm)."""
+        code = self.TIMING_KINDS[kind] if enable else 0
+        _check(self._call(load_library().mg_kernel_timing, self._h, code), "mg_kernel_timing")
 
     def kernel_timing_read(self):
         """(summed milliseconds, launches) of the recorded launches."""

@@ -341,27 +341,33 @@ def test_max_cycles_status(mg):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_kernel_timing_leaves_the_solve_unchanged(mg, precision):
-    """Event pairs around the finest plain passes of a solve (the benchmark's
-    in-solve kernel timing): the same solution bit for bit.  With n_pre =
-    n_post = 2 a cycle has two plain passes (the one that also forms the
-    residual and the one that applies the prolongation are not plain); in
-    FP64 the first pass of every cycle after the first also forms the input
-    norm, except right after an order switch, and a halted speculative cycle
-    leaves no record."""
+    """Event pairs around one kind of finest-level launch inside a solve (the
+    benchmark's in-solve kernel timing) leave every solve bit for bit as it
+    was.  With n_pre = n_post = 2 a cycle has one pass that also forms the
+    residual and its restriction, one that applies the prolongation and two
+    others: in FP64 the first pass of every cycle after the first forms the
+    input norm, except right after an order switch, so the plain ones are
+    one per cycle plus those; in the mixed inner cycle both are plain.  A
+    halted speculative cycle leaves no record."""
     p = gen.holes_problem(n=64, seed=2)
+    kinds = ["plain", "residual", "prolong", "norm"]
     ref_H = mg.Hierarchy(dev(p.mask), p.h, precision=precision)
-    ref, rinfo = ref_H.solve(dev(p.rho), tol=1e-10)
+    refs = [ref_H.solve(dev(p.rho), tol=1e-10) for _ in kinds]
     H = mg.Hierarchy(dev(p.mask), p.h, precision=precision)
-    H.kernel_timing(True)
-    got, info = H.solve(dev(p.rho), tol=1e-10)
-    ms, n = H.kernel_timing_read()
-    print(f"[case] holes64 {precision}: {n} launches, {ms / max(n, 1) * 1e3:.2f} us each", flush=True)
-    assert info["cycles"] == rinfo["cycles"] and np.array_equal(host(got), host(ref))
-    if precision == "fp64":
-        assert n == info["cycles"] + 1 + (info["switched_at"] >= 0)
-    else:
-        assert n == 2 * info["cycles"]
-    assert ms > 0
+    for kind, (ref, rinfo) in zip(kinds, refs):
+        H.kernel_timing(True, kind)
+        got, info = H.solve(dev(p.rho), tol=1e-10)
+        ms, n = H.kernel_timing_read()
+        print(f"[case] holes64 {precision} {kind}: {n} launches, {ms / max(n, 1) * 1e3:.2f} us each", flush=True)
+        assert info["cycles"] == rinfo["cycles"] and info["switched_at"] == rinfo["switched_at"]
+        assert np.array_equal(host(got), host(ref)), kind
+        cyc, sw = info["cycles"], int(info["switched_at"] >= 0)
+        if precision == "fp64":
+            expect = {"plain": cyc + 1 + sw, "residual": cyc, "prolong": cyc, "norm": cyc - 1 - sw}[kind]
+        else:
+            expect = {"plain": 2 * cyc, "residual": cyc, "prolong": cyc, "norm": 0}[kind]
+        assert n == expect, (kind, n, expect)
+        assert (ms > 0) == (n > 0)
     H.kernel_timing(False)
     H.solve(dev(p.rho), tol=1e-10)
     assert H.kernel_timing_read()[1] == n          # stopped: the record is kept
