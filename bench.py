@@ -551,16 +551,15 @@ def main():
     rho = torch.from_numpy(p.rho).to(dev)
     phi = torch.zeros(p.shape, dtype=torch.float64, device=dev)
 
-    def time_solves(H, make_guess=None, prho=None, pphi=None, kernel_timing=False):
+    def time_solves(H, make_guess=None, prho=None, pphi=None):
         """W warm-up then K timed solves on one fresh hierarchy, each solve
         timed alone (wall clock, synchronised) and recorded with its regime:
         a solve that starts in second order and switches, or one that starts
         held in first order by an earlier switch (Sec. 4), take different
         cycle counts, so both the mean over the K solves (`value`) and the
         per-regime figures are reported.  Every variant runs the same
-        schedule on its own fresh hierarchy.  kernel_timing: HIP events on
-        the solver's stream also bracket every plain finest-level red-black
-        launch of the timed solves."""
+        schedule on its own fresh hierarchy.  No kernel timing is on: its
+        event pairs would add a few microseconds around each launch timed."""
         prho = rho if prho is None else prho
         pphi = phi if pphi is None else pphi
 
@@ -573,8 +572,6 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        if kernel_timing:
-            H.kernel_timing(True)
         infos, walls = [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -583,8 +580,6 @@ def main():
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t1)
         wall = time.perf_counter() - t0
-        if kernel_timing:
-            H.kernel_timing(False)
         return wall / max(1, args.steps) * 1e3, infos, walls
 
     def regimes(infos, walls):
@@ -606,18 +601,19 @@ def main():
     H = mg.Hierarchy(mask, p.h, precision="fp64", tune=1)
     n_act = H.n_active(0)
     depths64 = H.item_depths()
-    ms_wall, infos64, walls64 = time_solves(H, kernel_timing=True)
-    k_ms, k_launches = H.kernel_timing_read()
-    # the other finest-level passes of a cycle, timed the same way in two
-    # more solves each after the timed region (one kind per solve set)
-    finest = {"plain": (k_ms, k_launches)}
-    for kind in ("residual", "prolong", "norm"):
+    ms_wall, infos64, walls64 = time_solves(H)
+    # after the timed region, each kind of finest-level pass of a cycle timed
+    # inside more solves of the same schedule by the HIP event pairs the
+    # library records around its launches (one kind per set of solves)
+    finest = {}
+    for kind, solves in (("plain", 4), ("residual", 2), ("prolong", 2), ("norm", 2)):
         H.kernel_timing(True, kind)
-        for _ in range(2):
+        for _ in range(solves):
             phi.zero_()
             H.solve(rho, phi, None, tol=args.tol)
         finest[kind] = H.kernel_timing_read()
         H.kernel_timing(False)
+    k_ms, k_launches = finest["plain"]
     last = infos64[-1]
     reg64 = regimes(infos64, walls64)
     ms_events = float(np.median([i["ms"] for i in infos64]))
@@ -625,8 +621,8 @@ def main():
 
     # dominant kernel: the finest-level plain red-black pass, its average
     # launch duration from the HIP event pairs that the library's launches of
-    # it in the timed solves record (the kernel's own start and end, on the
-    # solver's stream)
+    # it record inside solves of the benchmark's schedule run after the timed
+    # ones (the kernel's own start and end, on the solver's stream)
     if k_launches == 0:
         raise RuntimeError("no finest-level smoother launch was timed")
     smooth_ms = k_ms / k_launches
@@ -771,7 +767,7 @@ def main():
             "avg_launch_us": round(smooth_ms * 1e3, 3),
             "launches_timed": k_launches,
             "timing": "HIP event pair (the kernel's start and end, hipExtLaunchKernel) on each plain "
-                      "finest-level pass of the timed solves",
+                      "finest-level pass of 4 solves of the same schedule after the timed ones",
             "algorithmic_bytes_per_launch": bytes_per,
             "back_to_back_us": round(b2b_ms * 1e3, 3),
             "back_to_back_frac": round(bytes_per / (b2b_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),

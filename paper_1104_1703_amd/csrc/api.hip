@@ -495,10 +495,13 @@ void create(mg_hierarchy *H, const int8_t *mask, int nx, int ny, int nz, double 
     HIPCHK(hipMemsetAsync(H->stop_dev, 0, sizeof(StopTest), s));
     for (int l = 0; l < MAXL; l++) lev[l].halt = H->halt_dev;
     HIPCHK(hipMemsetAsync(H->norm_dev, 0, 8 * sizeof(double), s));
-    HIPCHK(hipHostMalloc((void **)&H->norm_host, 8 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&H->norm_host, 8 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHK(hipHostGetDevicePointer((void **)&H->norm_map, H->norm_host, 0));
     HIPCHK(hipEventCreate(&H->ev0));
     HIPCHK(hipEventCreate(&H->ev1));
     for (int q = 0; q < 2; q++) HIPCHK(hipEventCreateWithFlags(&H->evq[q], hipEventDisableTiming));
+    for (int q = 0; q < 2; q++)
+        HIPCHK(hipEventCreateWithFlags(&H->evn[q], hipEventDisableTiming | hipEventDisableSystemFence));
     HIPCHK(hipStreamSynchronize(s));
     if (H->opt.tune) tune_depths(H);
     HIPCHK(hipStreamSynchronize(s));
@@ -513,7 +516,8 @@ struct Cur {
 
 // The residual norm of a cycle's input formed by its first finest pass
 // (launch_rbgs_norm), its final sum right after that pass (with `stop`, the
-// device stop test), and a copy of the sum to `host` followed by `ev`.
+// device stop test), which also stores the sum to `host` (device address of
+// coherent host memory), followed by `ev`.
 struct InputNorm {
     const StopTest *stop;
     double *host;
@@ -556,11 +560,8 @@ void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur 
             const bool timed = od.nsegs > 0 && kt_events(H, KT_NORM, e0, e1);
             HIPCHK(launch_rbgs_norm(L, od, L.x[a], L.x[b], L.f, H->part, H->stream, e0, e1));
             if (timed) H->kt_used++;
-            launch_finalize(L, H->part, od.nsegs, H->norm_dev, 0, in->stop, H->stream);
-            if (in->host) {
-                HIPCHK(hipMemcpyAsync(in->host, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
-                HIPCHK(hipEventRecord(in->ev, H->stream));
-            }
+            launch_finalize(L, H->part, od.nsegs, H->norm_dev, 0, in->stop, H->stream, in->host);
+            if (in->host) HIPCHK(hipEventRecord(in->ev, H->stream));
             p += 1;
         } else if (H->opt.fuse_passes && passes - p >= 2) {
             if (f32) launch_rbgs2_32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream);
@@ -919,7 +920,7 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
             int par_after = par_next;
             kt_mark = H->kt_used;
             if (k + 1 <= o.max_cycles) {
-                const InputNorm in{H->stop_dev, H->norm_host + slot, H->evq[k & 1]};
+                const InputNorm in{H->stop_dev, H->norm_map + slot, H->evn[k & 1]};
                 enqueue_cycle(H, S.order, par_next, false, &par_after, true, NORM_INPUT, &in);
             } else {
                 Level &L0 = H->lev[0];
@@ -928,7 +929,7 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
                 HIPCHK(hipMemcpyAsync(H->norm_host + slot, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipEventRecord(H->evq[k & 1], s));
             }
-            HIPCHK(hipEventSynchronize(H->evq[k & 1]));
+            HIPCHK(hipEventSynchronize(k + 1 <= o.max_cycles ? H->evn[k & 1] : H->evq[k & 1]));
             const int order_before = S.order;
             S.host_slot = slot;
             solve_cycle_finish(H, S);
@@ -1130,8 +1131,10 @@ void mg_destroy_hierarchy(mg_hierarchy *H) {
     for (hipEvent_t e : H->kt_ev) (void)hipEventDestroy(e);
     if (H->ev0) (void)hipEventDestroy(H->ev0);
     if (H->ev1) (void)hipEventDestroy(H->ev1);
-    for (int q = 0; q < 2; q++)
+    for (int q = 0; q < 2; q++) {
         if (H->evq[q]) (void)hipEventDestroy(H->evq[q]);
+        if (H->evn[q]) (void)hipEventDestroy(H->evn[q]);
+    }
     delete H;
 }
 

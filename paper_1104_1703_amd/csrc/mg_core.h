@@ -114,7 +114,8 @@ struct mg_hierarchy {
     double *part = nullptr;         // per-block partial sums (device)
     int part_cap = 0;
     double *norm_dev = nullptr;     // finalised sums (device, 4 doubles)
-    double *norm_host = nullptr;    // pinned mirror
+    double *norm_host = nullptr;    // pinned mirror (coherent host memory, mapped)
+    double *norm_map = nullptr;     // device address of norm_host
     int *halt_dev = nullptr;        // set by the device stop test; read by every cycle kernel
     mg::StopTest *stop_dev = nullptr;
     double *scratch = nullptr;      // finest-level float64 scratch (fold/residual of the fine level)
@@ -123,6 +124,10 @@ struct mg_hierarchy {
     std::vector<mg::Graph> graphs;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evq[2] = {nullptr, nullptr};  // ends of the (at most two) cycles in flight
+    // input norms written by the device straight to norm_host: events
+    // without a system-scope fence (the value does not pass through the
+    // device caches)
+    hipEvent_t evn[2] = {nullptr, nullptr};
     // optional timing of one kind of finest-level red-black launch inside
     // solves (kt_on: 0 off, 1 plain passes, 2 the pass with the residual, 3
     // the pass with the prolongation, 4 the pass forming the input norm): an
@@ -256,9 +261,11 @@ void launch_copy_masked(const Level &L, int level, const OrderData &od, const do
 void launch_resnorm(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *part,
                     double *out, int slot, hipStream_t s, const StopTest *stop = nullptr);
 // The fixed-order total of n partials into out[slot], with `stop` also the
-// stop test on it (halt flag of L) -- the final step of launch_resnorm.
+// stop test on it (halt flag of L) -- the final step of launch_resnorm;
+// host_out (device address of coherent host memory): the total is also
+// stored there at system scope.
 void launch_finalize(const Level &L, const double *part, int n, double *out, int slot, const StopTest *stop,
-                     hipStream_t s);
+                     hipStream_t s, double *host_out = nullptr);
 // Device flags of the solve loop (small kernels, safe inside captured graphs).
 void launch_set_halt(int *halt, int v, hipStream_t s);
 void launch_set_stop(StopTest *st, double thresh, double rprev, double eta, int check_switch, hipStream_t s);

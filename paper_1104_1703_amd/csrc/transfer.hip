@@ -72,7 +72,8 @@ __global__ __launch_bounds__(NT) void k_resnorm(const int *__restrict__ tiles, i
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ part, int n, double *__restrict__ out,
-                                                   int slot, StopTest *__restrict__ stop, int *__restrict__ halt) {
+                                                   int slot, StopTest *__restrict__ stop, int *__restrict__ halt,
+                                                   double *__restrict__ host_out = nullptr) {
     __shared__ double sm[1024];
     if (halt && *halt) return;
     double v = 0.0;
@@ -85,6 +86,9 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ pa
     }
     if (threadIdx.x == 0) {
         out[slot] = sm[0];
+        if (host_out)  // coherent host memory: a system-scope store reaches it directly
+            __hip_atomic_store(reinterpret_cast<unsigned long long *>(host_out), __double_as_longlong(sm[0]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         if (stop) {
             const double r = sqrt(sm[0]);
             const bool h = !(r > stop->thresh) || !isfinite(r) || (stop->check_switch && r / stop->rprev > stop->eta);
@@ -293,8 +297,8 @@ void launch_resnorm(const Level &L, int level, const OrderData &od, const double
 }
 
 void launch_finalize(const Level &L, const double *part, int n, double *out, int slot, const StopTest *stop,
-                     hipStream_t s) {
-    k_finalize<<<1, 1024, 0, s>>>(part, n, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
+                     hipStream_t s, double *host_out) {
+    k_finalize<<<1, 1024, 0, s>>>(part, n, out, slot, const_cast<StopTest *>(stop), halt_rw(L), host_out);
 }
 
 void launch_set_halt(int *halt, int v, hipStream_t s) { k_set_halt<<<1, 1, 0, s>>>(halt, v); }
