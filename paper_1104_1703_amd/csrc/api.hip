@@ -696,7 +696,7 @@ void zero_level_x(mg_hierarchy *H, int l) {
 enum { NORM_AFTER = 0, NORM_INPUT = 1, NORM_NONE = 2 };
 
 void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out, bool decide,
-                   int mode = NORM_AFTER, const InputNorm *in = nullptr) {
+                   int mode = NORM_AFTER, const InputNorm *in = nullptr, double *host_out = nullptr) {
     const StopTest *stop = decide ? H->stop_dev : nullptr;
     Cur cur;
     for (int l = 0; l < MAXL; l++) cur.c[l] = 0;
@@ -706,12 +706,12 @@ void enqueue_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *pari
         cur.c[0] = parity;
         mg_level(H, 0, order, false, cur, false, mode == NORM_INPUT ? in : nullptr);
         if (mode == NORM_AFTER)
-            launch_resnorm(L0, 0, od0, L0.x[cur.c[0]], L0.f, H->part, H->norm_dev, 0, H->stream, stop);
+            launch_resnorm(L0, 0, od0, L0.x[cur.c[0]], L0.f, H->part, H->norm_dev, 0, H->stream, stop, host_out);
     } else {
         mg_level(H, 0, order, true, cur, true);
         // x + e goes to the other FP64 buffer (unused by the FP32 inner cycle)
         launch_axpy_resnorm32(L0, od0, L0.x[parity], L0.x32[cur.c[0]], L0.x[parity ^ 1], L0.f, L0.f32, H->part,
-                              H->norm_dev, 0, H->stream, stop);
+                              H->norm_dev, 0, H->stream, stop, host_out);
     }
     *parity_out = mixed ? parity ^ 1 : cur.c[0];
 }
@@ -759,9 +759,15 @@ void run_cycle_kernels(mg_hierarchy *H, int order, int parity, bool mixed, int *
     HIPCHK(hipGraphLaunch(g.exec, H->stream));
 }
 
-// One cycle (replayed from its captured graph when use_graph), then an
-// 8-byte copy of its norm to norm_host[host_slot].
+// One cycle whose norm lands in norm_host[host_slot]: launched directly, its
+// final sum stores the norm there itself (wait on an evn event); replayed
+// from its captured graph (use_graph), followed by an 8-byte copy (wait on
+// an evq event).
 void run_cycle(mg_hierarchy *H, int order, int parity, bool mixed, int *parity_out, bool decide, int host_slot) {
+    if (!H->opt.use_graph) {
+        enqueue_cycle(H, order, parity, mixed, parity_out, decide, NORM_AFTER, nullptr, H->norm_map + host_slot);
+        return;
+    }
     run_cycle_kernels(H, order, parity, mixed, parity_out, decide);
     HIPCHK(hipMemcpyAsync(H->norm_host + host_slot, H->norm_dev, sizeof(double), hipMemcpyDeviceToHost, H->stream));
 }
@@ -959,12 +965,14 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
         int parity_out, slot, ev, kt_mark;
     } fl[2];
     int nf = 0, enq = 0, par = S.parity;
+    // a directly launched cycle stores its norm to host memory itself
+    hipEvent_t *const evc = o.use_graph ? H->evq : H->evn;
     auto launch = [&]() {
         const int k = enq & 1;
         int np = par;
         const int kt_mark = H->kt_used;
         run_cycle(H, S.order, par, S.mixed, &np, true, 4 + k);
-        HIPCHK(hipEventRecord(H->evq[k], s));
+        HIPCHK(hipEventRecord(evc[k], s));
         fl[nf++] = Flight{np, 4 + k, k, kt_mark};
         par = np;
         enq++;
@@ -972,7 +980,7 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
     while (S.active) {
         if (nf == 0) launch();
         if (nf == 1 && S.n + 2 <= H->opt.max_cycles) launch();  // speculative
-        HIPCHK(hipEventSynchronize(H->evq[fl[0].ev]));
+        HIPCHK(hipEventSynchronize(evc[fl[0].ev]));
         const int order_before = S.order;
         S.host_slot = fl[0].slot;
         solve_cycle_finish(H, S);
@@ -982,7 +990,7 @@ mg_status solve(mg_hierarchy *H, const double *rho, double *phi, const double *B
         if (!S.active || S.order != order_before) {
             // the cycle in flight found the halt flag set and did nothing
             if (nf) {
-                HIPCHK(hipEventSynchronize(H->evq[fl[0].ev]));
+                HIPCHK(hipEventSynchronize(evc[fl[0].ev]));
                 H->kt_used = fl[0].kt_mark;
             }
             nf = 0;

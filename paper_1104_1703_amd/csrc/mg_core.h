@@ -259,7 +259,8 @@ void launch_copy_masked(const Level &L, int level, const OrderData &od, const do
 // then a fixed-order total into out[slot]; with `stop` the total also runs
 // the stop test and sets the level's halt flag.
 void launch_resnorm(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *part,
-                    double *out, int slot, hipStream_t s, const StopTest *stop = nullptr);
+                    double *out, int slot, hipStream_t s, const StopTest *stop = nullptr,
+                    double *host_out = nullptr);
 // The fixed-order total of n partials into out[slot], with `stop` also the
 // stop test on it (halt flag of L) -- the final step of launch_resnorm;
 // host_out (device address of coherent host memory): the total is also
@@ -290,6 +291,6 @@ void launch_resnorm32(const Level &L, const OrderData &od, const double *x, cons
 // in float.
 void launch_axpy_resnorm32(const Level &L, const OrderData &od, const double *x, const float *e, double *xo,
                            const double *f, float *r32, double *part, double *out, int slot, hipStream_t s,
-                           const StopTest *stop = nullptr);
+                           const StopTest *stop = nullptr, double *host_out = nullptr);
 
 }  // namespace mg

@@ -278,7 +278,7 @@ void launch_copy_masked(const Level &L, int level, const OrderData &od, const do
 inline int *halt_rw(const Level &L) { return const_cast<int *>(L.halt); }
 
 void launch_resnorm(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *part,
-                    double *out, int slot, hipStream_t s, const StopTest *stop) {
+                    double *out, int slot, hipStream_t s, const StopTest *stop, double *host_out) {
     const double ih2 = 1.0 / (L.h * L.h);
     if (level == 0) {
         if (od.nsegs)
@@ -287,13 +287,14 @@ void launch_resnorm(const Level &L, int level, const OrderData &od, const double
                     x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part,
                     nullptr, nullptr, nullptr, L.halt);
             });
-        k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
+        k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, const_cast<StopTest *>(stop), halt_rw(L), host_out);
         return;
     }
     if (od.ntiles)
         k_resnorm<false, true, false><<<gridc(od.ntiles), NT, 0, s>>>(od.tiles, od.ntiles, L.ntx, L.nty, L.nx, L.ny,
                                                                       L.nz, ih2, nullptr, od.d, x, f, part, nullptr);
-    k_finalize<<<1, 1024, 0, s>>>(part, od.ntiles * NQ, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
+    k_finalize<<<1, 1024, 0, s>>>(part, od.ntiles * NQ, out, slot, const_cast<StopTest *>(stop), halt_rw(L),
+                                  host_out);
 }
 
 void launch_finalize(const Level &L, const double *part, int n, double *out, int slot, const StopTest *stop,
@@ -321,7 +322,7 @@ void launch_resnorm32(const Level &L, const OrderData &od, const double *x, cons
 
 void launch_axpy_resnorm32(const Level &L, const OrderData &od, const double *x, const float *e, double *xo,
                            const double *f, float *r32, double *part, double *out, int slot, hipStream_t s,
-                           const StopTest *stop) {
+                           const StopTest *stop, double *host_out) {
     const double ih2 = 1.0 / (L.h * L.h);
     if (od.nsegs)
         with_fine_depth(od.depth, [&](auto Z) {
@@ -329,7 +330,7 @@ void launch_axpy_resnorm32(const Level &L, const OrderData &od, const double *x,
                 x, f, L.code, L.nx, L.ny, L.nz, ih2, od.segs, od.pmask, od.nsegs, nullptr, 0, 0, nullptr, part, r32, e,
                 xo, L.halt);
         });
-    k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, const_cast<StopTest *>(stop), halt_rw(L));
+    k_finalize<<<1, 1024, 0, s>>>(part, od.nsegs, out, slot, const_cast<StopTest *>(stop), halt_rw(L), host_out);
 }
 
 void launch_residual(const Level &L, int level, const OrderData &od, const double *x, const double *f, double *r,
