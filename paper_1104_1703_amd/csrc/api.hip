@@ -1517,7 +1517,9 @@ mg_status mg_kernel_timing(mg_hierarchy *H, int32_t enable) {
         HIPCHK(hipStreamSynchronize(H->stream));  // no recorded pair is still pending
         if (enable && H->kt_ev.empty()) {
             H->kt_ev.assign(2 * KT_MAX_LAUNCHES, nullptr);
-            for (hipEvent_t &e : H->kt_ev) HIPCHK(hipEventCreate(&e));
+            // no system-scope fence: a timed launch then ends with the same
+            // device-scope release as an untimed one
+            for (hipEvent_t &e : H->kt_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         }
         H->kt_on = enable;
         if (enable) H->kt_used = 0;
