@@ -3,6 +3,7 @@
 #pragma once
 
 #include "mg_core.h"
+#include "smooth_core.h"
 
 namespace mg {
 namespace small {
@@ -66,8 +67,11 @@ __device__ __forceinline__ T nb_sum(const T *x, int i, int j, int k, int nx, int
 // The three relaxation paths below (one wave, cells in registers, slots in
 // turn) are chosen by level size and thread count; each evaluates
 // ((x-neighbour pair) + (y pair) + (z pair) - h^2 f) / d with h^2 f rounded
-// on its own (no fused multiply-add), so every path, for any thread count,
-// gives the same value bit for bit.
+// on its own (no fused multiply-add) and the quotient correctly rounded (by
+// a division, or, where a cell's diagonal stays in registers over the passes,
+// from its correctly rounded reciprocal with one correction step: rb::
+// div_small), so every path, for any thread count, gives the same value bit
+// for bit.
 
 // Red-black half-sweep of colour `col` over slots first, first + step, ...
 // (slot m of row (j, k) is cell i = 2m + ((col + j + k) mod 2)).
@@ -102,7 +106,7 @@ __device__ __forceinline__ void smooth_wave(const Lv<T> &L, int passes) {
     const int nxy = L.nx * L.ny;
     int e[2] = {-1, -1};
     unsigned nb[2] = {0u, 0u};  // valid neighbours: -x, +x, -y, +y, -z, +z
-    T dg[2] = {T(1), T(1)}, rhs[2] = {T(0), T(0)};
+    T dg[2] = {T(1), T(1)}, yr[2] = {T(1), T(1)}, rhs[2] = {T(0), T(0)};
 #pragma unroll
     for (int col = 0; col < 2; col++) {
         if (lane >= L.hx * L.ny * L.nz) continue;
@@ -115,6 +119,7 @@ __device__ __forceinline__ void smooth_wave(const Lv<T> &L, int passes) {
         if (L.d[c] == T(0)) continue;
         e[col] = c;
         dg[col] = L.d[c];
+        yr[col] = T(1) / dg[col];
         rhs[col] = L.h2 * L.f[c];
         nb[col] = (unsigned)(i > 0) | (unsigned)(i < L.nx - 1) << 1 | (unsigned)(j > 0) << 2 |
                   (unsigned)(j < L.ny - 1) << 3 | (unsigned)(k > 0) << 4 | (unsigned)(k < L.nz - 1) << 5;
@@ -132,7 +137,7 @@ __device__ __forceinline__ void smooth_wave(const Lv<T> &L, int passes) {
                 const T yp = (m & 8u) ? x[c + L.nx] : T(0);
                 const T zm = (m & 16u) ? x[c - nxy] : T(0);
                 const T zp = (m & 32u) ? x[c + nxy] : T(0);
-                L.x[c] = (((xm + xp) + (ym + yp) + (zm + zp)) - rhs[col]) / dg[col];
+                L.x[c] = rb::div_small<T>(((xm + xp) + (ym + yp) + (zm + zp)) - rhs[col], dg[col], yr[col]);
             }
             // keep the next half-sweep's LDS reads behind this one's writes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -151,7 +156,7 @@ __device__ void smooth_regs(const Lv<T> &L, int passes) {
     const int nxy = L.nx * L.ny;
     int e[2][2];
     unsigned nb[2][2];
-    T dg[2][2], fv[2][2];
+    T dg[2][2], yr[2][2], fv[2][2];
 #pragma unroll
     for (int col = 0; col < 2; col++)
 #pragma unroll
@@ -159,6 +164,7 @@ __device__ void smooth_regs(const Lv<T> &L, int passes) {
             e[col][u] = -1;
             nb[col][u] = 0u;
             dg[col][u] = T(1);
+            yr[col][u] = T(1);
             fv[col][u] = T(0);
             const int s = threadIdx.x + u * NTH;
             if (s >= slots) continue;
@@ -172,6 +178,7 @@ __device__ void smooth_regs(const Lv<T> &L, int passes) {
             if (d == T(0)) continue;
             e[col][u] = c;
             dg[col][u] = d;
+            yr[col][u] = T(1) / d;
             fv[col][u] = L.f[c];
             nb[col][u] = (unsigned)(i > 0) | (unsigned)(i < L.nx - 1) << 1 | (unsigned)(j > 0) << 2 |
                          (unsigned)(j < L.ny - 1) << 3 | (unsigned)(k > 0) << 4 | (unsigned)(k < L.nz - 1) << 5;
@@ -191,7 +198,8 @@ __device__ void smooth_regs(const Lv<T> &L, int passes) {
                 const T yp = (m & 8u) ? x[c + L.nx] : T(0);
                 const T zm = (m & 16u) ? x[c - nxy] : T(0);
                 const T zp = (m & 32u) ? x[c + nxy] : T(0);
-                L.x[c] = (((xm + xp) + (ym + yp) + (zm + zp)) - L.h2 * fv[col][u]) / dg[col][u];
+                L.x[c] = rb::div_small<T>(((xm + xp) + (ym + yp) + (zm + zp)) - L.h2 * fv[col][u], dg[col][u],
+                                          yr[col][u]);
             }
             __syncthreads();
         }

@@ -83,13 +83,14 @@ constexpr double RCP64[13] = {0.0,       1.0,       1.0 / 2,  1.0 / 3,  1.0 / 4,
 constexpr float RCP32[13] = {0.0f,      1.0f,      1.0f / 2, 1.0f / 3, 1.0f / 4,  1.0f / 5,  1.0f / 6,
                              1.0f / 7,  1.0f / 8,  1.0f / 9, 1.0f / 10, 1.0f / 11, 1.0f / 12};
 
-// a / d for a diagonal d = 1..12 with y = RN(1/d): q0 = RN(a y) is within
-// one unit in the last place of a/d, the remainder a - q0 d is exact under
-// a fused multiply-add, and one correction step q0 + (a - q0 d) y rounds to
-// the correctly rounded quotient (Markstein's theorem), so the result is bit
-// for bit that of the division, except that a quotient in the subnormal
-// range may differ from it by one unit of that range.  The remainder is
-// formed as -(q0 d - a) so that a zero keeps its sign.
+// a / d with y = RN(1/d) (the finest level's diagonals 1..12 from a table,
+// coarse diagonals from one division per cell and call): q0 = RN(a y) is
+// within one unit in the last place of a/d, the remainder a - q0 d is exact
+// under a fused multiply-add, and one correction step q0 + (a - q0 d) y
+// rounds to the correctly rounded quotient (Markstein's theorem), so the
+// result is bit for bit that of the division, except that a quotient in the
+// subnormal range may differ from it by one unit of that range.  The
+// remainder is formed as -(q0 d - a) so that a zero keeps its sign.
 template <typename T>
 __device__ __forceinline__ T div_small(T a, T d, T y) {
     const T q0 = a * y;

@@ -130,7 +130,8 @@ def test_tuned_hierarchy_solves_as_the_default_and_caches_its_choice(mg, precisi
 def test_invalid_depths_are_rejected(mg):
     p = gen.sphere_problem(16)
     for opts in (dict(item_depth_fine=12), dict(item_depth_l1=16), dict(tune=2), dict(item_depth_fine=1),
-                 dict(fuse_passes=1, item_depth_fine=8), dict(fuse_passes=1, item_depth_coarse=1)):
+                 dict(fuse_passes=1, item_depth_fine=8), dict(fuse_passes=1, item_depth_coarse=1),
+                 dict(fuse_restrict=2), dict(fuse_restrict=-1)):
         with pytest.raises(mg.MGError) as e:
             mg.Hierarchy(dev(p.mask), p.h, **opts)
         assert e.value.status == mg.MG_ERR_ARG
