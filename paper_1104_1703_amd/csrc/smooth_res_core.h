@@ -8,12 +8,12 @@
 // halo, f and the neighbour code with a 2-cell halo.  Red cells are relaxed on
 // the tile plus a 2-cell ring and black cells on the tile plus a 1-cell ring,
 // so that every in-plane neighbour of a tile cell holds its final value of the
-// pass.  A plane is final once its black half-sweep is done; at the next step
-// each thread reads its own tile cell and the four in-plane neighbours of that
-// plane, and with the two final planes before it in registers forms the
-// residual of the plane below, in the expression and neighbour order of the
-// residual march, then sums the 2 x 2 x 2 children by lane exchanges and
-// planes in the march's order.  The iterate, the residual and the restricted
+// pass.  A plane is final once its black half-sweep is done; in the black
+// phase of the next step each thread reads its own tile cell and the four
+// in-plane neighbours of that plane, and with the two final planes before it
+// in registers forms the residual of the plane below, in the expression and
+// neighbour order of the residual march, then sums the 2 x 2 x 2 children by
+// lane exchanges and planes in the march's order.  The iterate, the residual and the restricted
 // right-hand side are therefore those of the plain pass followed by the march,
 // bit for bit.
 #pragma once
