@@ -206,8 +206,9 @@ class Hierarchy:
     and an inactive outermost layer.  Options are ``mg_options`` fields
     (n_pre, n_post, n_cycles, n_coarse_sweeps, min_coarse_dim, max_cycles,
     precision 'fp64'|'mixed', bc_order 'auto'|'first'|'second', eta,
-    first_order_hold, use_graph); ``torch_allocator`` routes buffers through
-    torch's caching allocator.
+    first_order_hold, use_graph, fuse_passes, fuse_restrict, tune,
+    item_depth_fine, item_depth_l1, item_depth_coarse); ``torch_allocator``
+    routes buffers through torch's caching allocator.
     """
 
     def __init__(self, mask: torch.Tensor, h: float, stream=None, torch_allocator: bool = True, **options):
