@@ -36,14 +36,14 @@ namespace {
 
 using namespace rb;
 
+// Five blocks per CU (LDS); the finest plain float pass (16 KB of LDS, 62
+// registers) eight, so that the 2048 items of a 256^3 pass run in one round.
 template <typename T, bool FINE, int SEGZ, bool PRO = false>
-__global__ __launch_bounds__(NT, 5) void k_rbgs(const T *__restrict__ xin, T *__restrict__ xout,
-                                              const T *__restrict__ f, const uint8_t *__restrict__ code,
-                                              const T *__restrict__ dco, int nx, int ny, int nz, T h2,
-                                              const Seg *__restrict__ segs, const unsigned long long *__restrict__ pm,
-                                              int nsegs, const int *__restrict__ halt,
-                                              const T *__restrict__ xc = nullptr, int cnx = 0, int cny = 0,
-                                              int cnz = 0) {
+__global__ __launch_bounds__(NT, FINE && !PRO && sizeof(T) == 4 ? 8 : 5) void k_rbgs(
+    const T *__restrict__ xin, T *__restrict__ xout, const T *__restrict__ f, const uint8_t *__restrict__ code,
+    const T *__restrict__ dco, int nx, int ny, int nz, T h2, const Seg *__restrict__ segs,
+    const unsigned long long *__restrict__ pm, int nsegs, const int *__restrict__ halt, const T *__restrict__ xc = nullptr,
+    int cnx = 0, int cny = 0, int cnz = 0) {
     __shared__ RbgsLds<T, FINE, PRO> lds;
     const int item = xcd_item(blockIdx.x, gridDim.x);
     if (item >= nsegs || (halt && *halt)) return;
@@ -71,9 +71,10 @@ __global__ __launch_bounds__(NT, 5) void k_rbgs_norm(const double *__restrict__ 
 }
 
 // The finest pass that also forms the residual of its result and restricts
-// it onto level 1 (smooth_res_core.h): four FP64 blocks per CU (LDS).
+// it onto level 1 (smooth_res_core.h): four FP64 blocks per CU (LDS), six
+// FP32 blocks.
 template <typename T, int SEGZ>
-__global__ __launch_bounds__(NT, sizeof(T) == 8 ? 4 : 5) void k_rbgs_res(
+__global__ __launch_bounds__(NT, sizeof(T) == 8 ? 4 : 6) void k_rbgs_res(
     const T *__restrict__ xin, T *__restrict__ xout, const T *__restrict__ f, const uint8_t *__restrict__ code, int nx,
     int ny, int nz, T h2, T ih2, const Seg *__restrict__ segs, const unsigned long long *__restrict__ pm, int nsegs,
     const int *__restrict__ halt, const T *__restrict__ cd, int cnx, int cny, T *__restrict__ fc) {

@@ -33,9 +33,9 @@ constexpr int QR = (QN + NT - 1) / NT;
 constexpr int MAXPL = SEGZ_FINE_MAX + 2 * H;  // mask words of the longest work item
 constexpr int CXN = BX / 2 * (BY / 2);  // coarse cells above one tile plane pair
 // Planes of global loads in flight (doubles: two were measured as fast as
-// three and take 14 fewer registers; floats: three keep five blocks per CU
-// free of spills)
-constexpr int PF64 = 2, PF32 = 3;
+// three and take 14 fewer registers; floats: two keep six blocks per CU free
+// of spills, 52.3 against 54.7 us with three at five blocks)
+constexpr int PF64 = 2, PF32 = 2;
 static_assert(BX == 32 && BY * BX == NT, "one tile cell per thread, two tile rows per wave");
 
 // Mask bit of x-plane cell (u, v) (cell (x0-3+u, y0-3+v)) in the item's mask
