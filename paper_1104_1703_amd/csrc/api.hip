@@ -277,20 +277,20 @@ float time_pass(mg_hierarchy *H, int l, int order, const OrderData &od, bool f32
                                                 H->stream);
                 else launch_rbgs_restrict(L, C, order, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, C.f, H->stream);
             } else if (f32) {
-                launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream);
+                HIPCHK(launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream));
                 launch_restrict32(L, C, l, order, L.x32[(p & 1) ^ 1], L.f32, C.f32, H->stream);
             } else {
-                launch_rbgs(L, l, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, H->stream);
+                HIPCHK(launch_rbgs(L, l, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, H->stream));
                 launch_restrict(L, C, l, order, L.x[(p & 1) ^ 1], L.f, C.f, H->stream);
             }
             return;
         }
         if (l == 0 && coarse && od.pmask3 && (p & 1)) {  // the pass that also restricts
             Level &C = H->lev[1];
-            if (f32) launch_rbgs_res_fine32(L, C, 2, od, L.x32[1], L.x32[0], L.f32, C.f32, H->stream);
-            else launch_rbgs_res_fine(L, C, 2, od, L.x[1], L.x[0], L.f, C.f, H->stream);
-        } else if (f32) launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream);
-        else launch_rbgs(L, l, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, H->stream);
+            if (f32) HIPCHK(launch_rbgs_res_fine32(L, C, 2, od, L.x32[1], L.x32[0], L.f32, C.f32, H->stream));
+            else HIPCHK(launch_rbgs_res_fine(L, C, 2, od, L.x[1], L.x[0], L.f, C.f, H->stream));
+        } else if (f32) HIPCHK(launch_rbgs32(L, l, od, L.x32[p & 1], L.x32[(p & 1) ^ 1], L.f32, H->stream));
+        else HIPCHK(launch_rbgs(L, l, od, L.x[p & 1], L.x[(p & 1) ^ 1], L.f, H->stream));
         if (l != 0 || (p & 1) == 0) return;
         if (f32) {
             if (coarse && !od.pmask3) launch_restrict32(L, H->lev[1], 0, 2, L.x32[0], L.f32, H->lev[1].f32, H->stream);
@@ -298,7 +298,7 @@ float time_pass(mg_hierarchy *H, int l, int order, const OrderData &od, bool f32
                                   nullptr);
         } else {
             if (coarse && !od.pmask3) launch_restrict(L, H->lev[1], 0, 2, L.x[0], L.f, H->lev[1].f, H->stream);
-            launch_rbgs_norm(L, od, L.x[0], L.x[1], L.f, H->part, H->stream);
+            HIPCHK(launch_rbgs_norm(L, od, L.x[0], L.x[1], L.f, H->part, H->stream));
         }
     };
     // the restriction march reads the finest lists from the level itself
@@ -556,7 +556,7 @@ void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur 
         const int a = cur.c[l], b = a ^ 1;
         const bool zin = (p == 0 && zero_start);
         if (in && p == 0 && l == 0 && !f32 && !zin) {
-            hipEvent_t e0, e1;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
             const bool timed = od.nsegs > 0 && kt_events(H, KT_NORM, e0, e1);
             HIPCHK(launch_rbgs_norm(L, od, L.x[a], L.x[b], L.f, H->part, H->stream, e0, e1));
             if (timed) H->kt_used++;
@@ -569,7 +569,7 @@ void smooth(mg_hierarchy *H, int l, int order, int passes, bool zero_start, Cur 
             p += 2;
         } else {
             // optional timing: the kernel's own start and end on a pair of events
-            hipEvent_t e0, e1;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
             const bool timed = l == 0 && od.nsegs > 0 && kt_events(H, KT_PLAIN, e0, e1);
             if (f32) HIPCHK(launch_rbgs32(L, l, od, zin ? nullptr : L.x32[a], L.x32[b], L.f32, H->stream, e0, e1));
             else HIPCHK(launch_rbgs(L, l, od, zin ? nullptr : L.x[a], L.x[b], L.f, H->stream, e0, e1));
@@ -612,7 +612,7 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
         if (o.n_pre > 1) smooth(H, l, order, o.n_pre - 1, zero_start, cur, f32, in);
         const bool zin = zero_start && o.n_pre == 1;
         const int a = cur.c[l], b = a ^ 1;
-        hipEvent_t e0, e1;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         const bool timed = odl.nsegs > 0 && kt_events(H, KT_RESIDUAL, e0, e1);
         if (f32)
             HIPCHK(launch_rbgs_res_fine32(L, C, order, odl, zin ? nullptr : L.x32[a], L.x32[b], L.f32, C.f32,
@@ -650,7 +650,7 @@ void mg_level(mg_hierarchy *H, int l, int order, bool zero_start, Cur &cur, bool
         if (f32) launch_rbgs2_prolong32(L, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream);
         else launch_rbgs2_prolong(L, od, C, C.x[cur.c[l + 1]], L.x[a], L.x[b], L.f, H->stream);
     } else {
-        hipEvent_t e0, e1;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         const bool timed = l == 0 && od.nsegs > 0 && kt_events(H, KT_PROLONG, e0, e1);
         if (f32)
             HIPCHK(launch_rbgs_prolong32(L, l, od, C, C.x32[cur.c[l + 1]], L.x32[a], L.x32[b], L.f32, H->stream, e0,
@@ -1385,7 +1385,7 @@ mg_status mg_smooth(mg_hierarchy *H, int32_t level, int32_t order, double *x_dev
                 launch_rbgs2(L, level, od, L.x[c], L.x[c ^ 1], f_dev, H->stream);
                 p += 2;
             } else {
-                launch_rbgs(L, level, od, L.x[c], L.x[c ^ 1], f_dev, H->stream);
+                HIPCHK(launch_rbgs(L, level, od, L.x[c], L.x[c ^ 1], f_dev, H->stream));
                 p += 1;
             }
             c ^= 1;
@@ -1495,7 +1495,7 @@ mg_status mg_time_smoother(mg_hierarchy *H, int32_t order, int32_t launches) {
         const OrderData &od0 = odata(H, 0, order);
         for (int p = 0; p < launches; p++) {
             if (H->opt.fuse_passes) launch_rbgs2(L0, 0, od0, L0.x[p & 1], L0.x[(p & 1) ^ 1], L0.f, H->stream);
-            else launch_rbgs(L0, 0, od0, L0.x[p & 1], L0.x[(p & 1) ^ 1], L0.f, H->stream);
+            else HIPCHK(launch_rbgs(L0, 0, od0, L0.x[p & 1], L0.x[(p & 1) ^ 1], L0.f, H->stream));
         }
         if (launches & 1)
             HIPCHK(hipMemcpyAsync(L0.x[0], L0.x[1], L0.n * sizeof(double), hipMemcpyDeviceToDevice, H->stream));
