@@ -36,10 +36,10 @@ namespace {
 
 using namespace rb;
 
-// Five blocks per CU (LDS); the finest plain float pass (16 KB of LDS, 62
+// Five blocks per CU (LDS); the finest float passes (16-19 KB of LDS, 62
 // registers) eight, so that the 2048 items of a 256^3 pass run in one round.
 template <typename T, bool FINE, int SEGZ, bool PRO = false>
-__global__ __launch_bounds__(NT, FINE && !PRO && sizeof(T) == 4 ? 8 : 5) void k_rbgs(
+__global__ __launch_bounds__(NT, FINE && sizeof(T) == 4 ? 8 : 5) void k_rbgs(
     const T *__restrict__ xin, T *__restrict__ xout, const T *__restrict__ f, const uint8_t *__restrict__ code,
     const T *__restrict__ dco, int nx, int ny, int nz, T h2, const Seg *__restrict__ segs,
     const unsigned long long *__restrict__ pm, int nsegs, const int *__restrict__ halt, const T *__restrict__ xc = nullptr,

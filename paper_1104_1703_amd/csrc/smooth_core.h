@@ -21,9 +21,10 @@ constexpr int XR = (PN + NT - 1) / NT;  // x elements per thread per plane
 constexpr int QR = (QN + NT - 1) / NT;  // f elements per thread per plane
 // Planes of global loads in flight per block.  Double planes carry twice the
 // bytes of float planes; measured on the 256^3 workload, three are best for
-// doubles and more would only keep lines in L2 longer; three for floats let
-// the finest float pass run eight blocks per CU without spills (four: five
-// blocks, 34.6 against 30.1 us).
+// doubles and more would only keep lines in L2 longer; three for floats (two
+// in the pass that applies the prolongation) let the finest float passes run
+// eight blocks per CU without spills (four at five blocks: plain pass 34.6
+// against 30.1 us, prolongation pass 46.0 against 41.3 us at three).
 constexpr int PF64 = 3, PF32 = 3;
 constexpr int PFC = 3;  // coarse levels
 
@@ -338,7 +339,7 @@ __device__ __forceinline__ double rbgs_item(RbgsLds<T, FINE, PRO> &L, const T *_
     // ck = st/2 .. st/2 + 2; an odd step stores coarse plane st/2 + 3 for the
     // next steps (its ring slot was last read two steps before).
     constexpr int NSTEP = SEGZ + 4;
-    constexpr int PF = !FINE ? (PFC < NSTEP ? PFC : NSTEP) : sizeof(T) == 8 ? PF64 : PF32;
+    constexpr int PF = !FINE ? (PFC < NSTEP ? PFC : NSTEP) : sizeof(T) == 8 ? PF64 : PRO ? PF32 - 1 : PF32;
     constexpr int CKMAX = ((NSTEP - 1) >> 1) + 2;  // last coarse plane read
     Regs r[PF];
 #pragma unroll
